@@ -1,0 +1,322 @@
+"""Pins of the CPU oracle against facts fixed by the definition of the median
+filter (Sugy 2025, Section 1) and by mathematics, not by the oracle itself.
+
+Each test would fail on a plausible mistake in the oracle: a wrong rank, a
+border off by one, a dropped window row, a float order that calls -0 == +0, a
+tie rule that picks the wrong copy, a gradient that scatters to the wrong pixel.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2507_19926_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+DTYPES = [np.uint8, np.uint16, np.uint32, np.float32]
+
+
+def _brute_sort_median(img, k):
+    """Full sort of every padded window (numpy): an independent algorithm."""
+    r = (k - 1) // 2
+    pad = np.pad(img, r, mode="edge")
+    win = np.lib.stride_tricks.sliding_window_view(pad, (k, k))
+    flat = win.reshape(img.shape[0], img.shape[1], k * k)
+    return np.sort(flat, axis=-1)[..., (k * k - 1) // 2]
+
+
+def _finite_nonzero_f32(H, W, seed):
+    g = wl.rng(seed)
+    v = g.uniform(-1.0, 1.0, size=(H, W)).astype(np.float32)
+    v[v == 0] = np.float32(0.5)
+    return v
+
+
+def _read_golden(name):
+    sections, cur = {}, None
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            if line.isalpha():
+                cur = sections.setdefault(line, [])
+                continue
+            cur.append(line.split())
+    return sections
+
+
+# ---------------------------------------------------------------- worked cases
+
+def test_hand_worked_3x3():
+    g = _read_golden("hand_3x3_k3.txt")
+    img = np.array(g["input"], dtype=np.uint8)
+    want = np.array(g["output"], dtype=np.uint8)
+    np.testing.assert_array_equal(oracle.median_filter(img, 3), want)
+
+
+def test_float_total_order_worked_case():
+    g = _read_golden("float_total_order_k3.txt")
+    bits = np.array([[int(v, 16) for v in row] for row in g["input"]], dtype=np.uint32)
+    out = oracle.median_filter(bits.view(np.float32), 3).view(np.uint32)
+    assert out[1, 1] == int(g["centre"][0][0], 16)
+    # Every permutation of the nine patterns has the same centre median.
+    pr = wl.rng(7)
+    for _ in range(20):
+        perm = pr.permutation(9)
+        b2 = bits.reshape(-1)[perm].reshape(3, 3)
+        assert oracle.median_filter(b2.view(np.float32), 3).view(np.uint32)[1, 1] == 0x80000000
+
+
+# ------------------------------------------------------- brute force, all k
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("shape", [(1, 1), (1, 7), (6, 1), (5, 9), (13, 11)])
+def test_brute_force_full_sort(dtype, shape):
+    H, W = shape
+    if dtype == np.float32:
+        img = _finite_nonzero_f32(H, W, seed=H * 100 + W)
+    else:
+        img = wl.uniform_plane(H, W, dtype, seed=H * 100 + W)
+    for k in range(1, 2 * max(H, W) + 4, 2):
+        np.testing.assert_array_equal(oracle.median_filter(img, k), _brute_sort_median(img, k),
+                                      err_msg="k=%d" % k)
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16, np.float32])
+def test_brute_force_ties(dtype):
+    img = wl.tie_heavy_plane(17, 23, dtype, levels=3, seed=3)
+    for k in (3, 5, 9, 15, 25):
+        np.testing.assert_array_equal(oracle.median_filter(img, k), _brute_sort_median(img, k))
+
+
+def test_rows_and_points_agree_with_full():
+    img = wl.uniform_plane(37, 29, np.uint16, seed=11)
+    full = oracle.median_filter(img, 7)
+    np.testing.assert_array_equal(oracle.median_filter(img, 7, rows=(5, 19)), full[5:19])
+    ys = np.array([0, 36, 10, 3, 36]); xs = np.array([0, 28, 14, 27, 0])
+    np.testing.assert_array_equal(oracle.median_points(img, 7, ys, xs), full[ys, xs])
+
+
+# --------------------------------------------- threshold decomposition (u8)
+
+def _threshold_decomposition_u8(img, k):
+    """median(x) = sum over tau=1..255 of [#{window >= tau} >= (N+1)/2].
+
+    An independent algorithm: counts come from summed-area tables of the
+    replicate-padded image, no sorting or selection anywhere.
+    """
+    r = (k - 1) // 2
+    H, W = img.shape
+    need = (k * k + 1) // 2
+    pad = np.pad(img, r, mode="edge").astype(np.int32)
+    out = np.zeros((H, W), dtype=np.int32)
+    for tau in range(1, 256):
+        b = (pad >= tau).astype(np.int32)
+        s = np.zeros((b.shape[0] + 1, b.shape[1] + 1), dtype=np.int32)
+        s[1:, 1:] = b.cumsum(0).cumsum(1)
+        cnt = s[k:k + H, k:k + W] - s[0:H, k:k + W] - s[k:k + H, 0:W] + s[0:H, 0:W]
+        out += (cnt >= need)
+    return out.astype(np.uint8)
+
+
+@pytest.mark.parametrize("k", [3, 5, 9, 15, 21, 31, 75])
+def test_threshold_decomposition_u8(k):
+    img = wl.uniform_plane(40, 37, np.uint8, seed=k)
+    np.testing.assert_array_equal(oracle.median_filter(img, k), _threshold_decomposition_u8(img, k))
+    noisy = wl.rgb30_planes(H=33, W=45, seed=k)[2]
+    np.testing.assert_array_equal(oracle.median_filter(noisy, k), _threshold_decomposition_u8(noisy, k))
+
+
+# ------------------------------------------------------- rank certificate
+
+def _keys(a):
+    if a.dtype == np.float32:
+        i = a.view(np.int32).astype(np.int64)
+        return np.where(i < 0, i ^ 0x7FFFFFFF, i)  # totalOrder, sign-extended
+    return a.astype(np.int64)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_rank_certificate(dtype):
+    if dtype == np.float32:
+        img = wl.float_specials_plane(21, 19, seed=5)
+    else:
+        img = wl.tie_heavy_plane(21, 19, dtype, levels=4, seed=5) if dtype != np.uint32 \
+            else wl.uniform_plane(21, 19, dtype, seed=5)
+    for k in (3, 7, 11):
+        out = oracle.median_filter(img, k)
+        r = (k - 1) // 2
+        m = (k * k - 1) // 2
+        win = np.lib.stride_tricks.sliding_window_view(np.pad(img, r, mode="edge"), (k, k))
+        win = win.reshape(img.shape[0], img.shape[1], k * k)
+        wk, ok = _keys(win), _keys(out)[..., None]
+        less = (wk < ok).sum(-1)
+        leq = (wk <= ok).sum(-1)
+        assert np.all(less <= m) and np.all(m < leq)
+        # membership, bit for bit
+        wb = win.view(np.uint32) if dtype == np.float32 else win
+        ob = out.view(np.uint32) if dtype == np.float32 else out
+        assert np.all((wb == ob[..., None]).any(-1))
+
+
+# -------------------------------------------------- special cases and maps
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_k1_is_identity(dtype):
+    img = wl.float_specials_plane(9, 14, 1) if dtype == np.float32 else wl.uniform_plane(9, 14, dtype, 1)
+    out = oracle.median_filter(img, 1)
+    assert out.tobytes() == img.tobytes()
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_constant_image(dtype):
+    for v in (0, 1, 200):
+        img = np.full((11, 16), v, dtype=dtype)
+        for k in (3, 5, 25):
+            assert oracle.median_filter(img, k).tobytes() == img.tobytes()
+    nan = np.full((6, 6), 0x7FC01234, dtype=np.uint32).view(np.float32)
+    assert oracle.median_filter(nan, 5).tobytes() == nan.tobytes()
+
+
+def test_monotone_maps_commute():
+    u8 = wl.uniform_plane(31, 27, np.uint8, seed=2)
+    lut = np.sort(wl.rng(3).integers(0, 256, size=256)).astype(np.uint8)  # non-decreasing
+    for k in (3, 5, 9, 13):
+        base = oracle.median_filter(u8, k)
+        np.testing.assert_array_equal(oracle.median_filter(u8 // 2, k), base // 2)
+        np.testing.assert_array_equal(oracle.median_filter(lut[u8], k), lut[base])
+        # decreasing maps also commute because the window size is odd
+        np.testing.assert_array_equal(oracle.median_filter(255 - u8, k), 255 - base)
+    u16 = wl.uniform_plane(25, 30, np.uint16, seed=4) // 2
+    for k in (3, 7):
+        base = oracle.median_filter(u16, k)
+        np.testing.assert_array_equal(oracle.median_filter(u16 * 2, k), base * 2)
+        np.testing.assert_array_equal(oracle.median_filter(65535 - u16, k), 65535 - base)
+    f = wl.float_specials_plane(23, 26, seed=6)
+    for k in (3, 5, 9):
+        base = oracle.median_filter(f, k)
+        # negation reverses totalOrder for every bit pattern (sign-bit flip)
+        neg = (f.view(np.uint32) ^ np.uint32(0x80000000)).view(np.float32)
+        want = (base.view(np.uint32) ^ np.uint32(0x80000000))
+        assert np.array_equal(oracle.median_filter(neg, k).view(np.uint32), want)
+    g = _finite_nonzero_f32(20, 20, seed=8)
+    for k in (3, 7):
+        np.testing.assert_array_equal(oracle.median_filter(g * np.float32(2), k),
+                                      oracle.median_filter(g, k) * np.float32(2))
+        np.testing.assert_array_equal(oracle.median_filter(g + np.float32(4), k),
+                                      oracle.median_filter(g, k) + np.float32(4))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_single_impulse_removed(dtype):
+    H, W = 12, 15
+    pr = wl.rng(9)
+    hi = np.float32(1e30) if dtype == np.float32 else np.iinfo(dtype).max
+    for k in (3, 5, 7):
+        for _ in range(8):
+            img = np.full((H, W), 7, dtype=dtype)
+            y, x = int(pr.integers(0, H)), int(pr.integers(0, W))
+            img[y, x] = hi
+            assert np.all(oracle.median_filter(img, k) == 7)
+        # a corner impulse is replicated by the border but still a minority
+        img = np.full((H, W), 7, dtype=dtype)
+        img[0, 0] = hi
+        assert np.all(oracle.median_filter(img, k) == 7)
+
+
+def test_minority_outliers_on_flat_region():
+    img = np.full((30, 30), 100, dtype=np.uint8)
+    k = 9
+    # place (N-1)/2 = 40 outliers inside the window of the centre pixel
+    ys, xs = np.unravel_index(wl.rng(1).permutation(81)[:40], (9, 9))
+    img[11 + ys, 11 + xs] = wl.rng(2).integers(0, 256, size=40).astype(np.uint8)
+    assert oracle.median_filter(img, k)[15, 15] == 100
+
+
+def test_ramps():
+    H, W = 40, 50
+    x = np.arange(W, dtype=np.uint16)[None, :].repeat(H, 0)
+    for k in (3, 9, 21, 75):
+        # a pure horizontal ramp is left unchanged, borders included
+        np.testing.assert_array_equal(oracle.median_filter(x * 3, k), x * 3)
+        np.testing.assert_array_equal(oracle.median_filter(x.T.copy() * 5, k), x.T * 5)
+    y = np.arange(H, dtype=np.uint16)[:, None]
+    ramp = (2 * y + 3 * x).astype(np.uint16)
+    for k in (3, 5, 11):
+        r = (k - 1) // 2
+        out = oracle.median_filter(ramp, k)
+        # interior windows are symmetric about the centre value
+        np.testing.assert_array_equal(out[r:H - r, r:W - r], ramp[r:H - r, r:W - r])
+
+
+# ------------------------------------------------------------ argmedian
+
+@pytest.mark.parametrize("levels", [2, 3, 1000])
+def test_argmedian(levels):
+    img = wl.tie_heavy_plane(14, 17, np.float32, levels=levels, seed=levels)
+    H, W = img.shape
+    for k in (3, 5, 9):
+        val, idx = oracle.argmedian_f32(img, k)
+        assert val.tobytes() == oracle.median_filter(img, k).tobytes()
+        flat = img.reshape(-1)
+        assert np.array_equal(flat[idx].view(np.uint32), val.view(np.uint32))
+        r = (k - 1) // 2
+        for y in range(H):
+            for x in range(W):
+                rows = np.clip(np.arange(y - r, y + r + 1), 0, H - 1)
+                cols = np.clip(np.arange(x - r, x + r + 1), 0, W - 1)
+                cand = (rows[:, None] * W + cols[None, :]).reshape(-1)
+                eq = cand[flat[cand].view(np.uint32) == val[y, x].view(np.uint32)]
+                # lowest plane-flat index among window pixels equal to the median
+                assert idx[y, x] == eq.min()
+
+
+def test_argmedian_rows():
+    img = wl.autograd_tensor(shape=(1, 1, 20, 24))[0, 0]
+    v, i = oracle.argmedian_f32(img, 5)
+    v2, i2 = oracle.argmedian_f32(img, 5, rows=(4, 11))
+    np.testing.assert_array_equal(v[4:11], v2)
+    np.testing.assert_array_equal(i[4:11], i2)
+
+
+# ------------------------------------------------------------- gradient
+
+def test_gradient_conservation_and_support():
+    img = wl.autograd_tensor(shape=(1, 1, 24, 20))[0, 0]
+    g = wl.grad_out_like(img.shape, seed=1)
+    for k in (3, 7):
+        _, idx = oracle.argmedian_f32(img, k)
+        gi = oracle.grad_f32(g, idx)
+        assert abs(float(gi.astype(np.float64).sum()) - float(g.astype(np.float64).sum())) < 1e-4
+        hit = np.zeros(img.size, bool)
+        hit[idx.reshape(-1)] = True
+        assert np.all(gi.reshape(-1)[~hit] == 0)
+
+
+def test_gradient_matches_finite_differences():
+    """Central differences of the oracle's own forward: at inputs whose
+    neighbours are all more than 2*eps away, a small move of x[q] keeps every
+    rank, so d(sum g*y)/dx[q] equals the scattered gradient."""
+    H, W, k = 12, 13, 5
+    vals = (wl.rng(4).permutation(H * W).astype(np.float32) * np.float32(0.01)).reshape(H, W)
+    g = wl.grad_out_like((H, W), seed=2).astype(np.float64)
+    _, idx = oracle.argmedian_f32(vals, k)
+    grad = oracle.grad_f32(g.astype(np.float32), idx).astype(np.float64)
+    eps = np.float32(1e-3)
+    for q in range(H * W):
+        xp = vals.copy().reshape(-1); xm = vals.copy().reshape(-1)
+        xp[q] = xp[q] + eps; xm[q] = xm[q] - eps
+        yp = oracle.median_filter(xp.reshape(H, W), k).astype(np.float64)
+        ym = oracle.median_filter(xm.reshape(H, W), k).astype(np.float64)
+        fd = float((g * (yp - ym)).sum()) / (float(xp[q]) - float(xm[q]))
+        assert abs(fd - grad.reshape(-1)[q]) < 1e-3 * (1 + abs(fd)), q
+
+
+def test_gradient_order_is_ascending():
+    # Three contributions to one pixel whose float32 sum depends on the order:
+    # (1e8 + 1) - 1e8 = 0 but 1e8 + (1 - 1e8) = 1 would need reassociation.
+    g = np.array([1e8, 1.0, -1e8], dtype=np.float32)
+    idx = np.array([0, 0, 0], dtype=np.int32)
+    assert oracle.grad_f32(g, idx)[0] == np.float32((np.float32(1e8) + np.float32(1.0)) - np.float32(1e8))
