@@ -1,0 +1,103 @@
+/*
+ * medfilt.h -- C ABI of the MI355X (gfx950) hierarchical-tiling median filter.
+ *
+ * The operation (Sugy, "A Fast Parallel Median Filtering Algorithm Using
+ * Hierarchical Tiling", SIGGRAPH 2025, Section 1): every output pixel is the
+ * median of the k x k window centred on it. The library computes it exactly,
+ * by hierarchical tiling (Section 3) in one of two GPU realisations: a
+ * data-oblivious selection network held in registers (Section 4) and a
+ * data-aware merge held in LDS (Section 5).
+ *
+ * Conventions shared by every entry point:
+ *   - Images are single planes, row-major, H rows of W elements, consecutive
+ *     rows pitch_bytes apart. src and dst are DEVICE pointers owned by the
+ *     caller, share the pitch and must not overlap (MF_ERR_ALIAS).
+ *   - pitch_bytes >= W * sizeof(element) and a multiple of sizeof(element).
+ *   - k is odd, 1 <= k <= mf_max_k(); k = 1 copies the image. k may exceed H
+ *     or W. Border: replicate (coordinates are clamped into the image); the
+ *     paper states no border rule, this is the reading the library takes.
+ *   - dtype: MF_U8, MF_U16, MF_U32 compare as unsigned integers; MF_F32
+ *     compares under IEEE 754 totalOrder on the bit pattern (-NaN < -inf <
+ *     ... < -0 < +0 < ... < +inf < +NaN), so the output is bit-exact and
+ *     defined for every input, NaNs and signed zeros included.
+ *   - Every argument is validated on the host before any GPU work; a bad
+ *     argument returns a negative mf_status and launches nothing.
+ *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
+ *     null stream). Launch failures return MF_ERR_HIP with a message in
+ *     mf_last_error(). No call allocates device memory on the plain path.
+ *   - No C++ exception or abort crosses this interface.
+ */
+#ifndef MEDFILT_H
+#define MEDFILT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum mf_dtype { MF_U8 = 0, MF_U16 = 1, MF_U32 = 2, MF_F32 = 3 };
+
+enum mf_border { MF_BORDER_REPLICATE = 0 };
+
+enum mf_variant {
+    MF_VARIANT_AUTO = 0,       /* the library's per-(k, dtype) choice          */
+    MF_VARIANT_OBLIVIOUS = 1,  /* register-resident selection network, Sec. 4 */
+    MF_VARIANT_DATA_AWARE = 2  /* LDS-resident merges, Sec. 5                   */
+};
+
+enum mf_status {
+    MF_OK = 0,
+    MF_ERR_NULL = -1,     /* a required pointer is NULL                       */
+    MF_ERR_DIMS = -2,     /* H < 1, W < 1, or a size that overflows int32 math */
+    MF_ERR_PITCH = -3,    /* pitch_bytes < W*size or not a multiple of size   */
+    MF_ERR_DTYPE = -4,    /* unknown dtype, or one the entry point refuses   */
+    MF_ERR_K = -5,        /* k even, < 1 or > mf_max_k()                      */
+    MF_ERR_BORDER = -6,   /* unknown border mode                              */
+    MF_ERR_ALIAS = -7,    /* src and dst byte ranges overlap                  */
+    MF_ERR_NOMEM = -8,    /* a plan could not allocate its device tables     */
+    MF_ERR_PLAN = -9,     /* plan misuse (NULL plan, shape mismatch)          */
+    MF_ERR_CONFIG = -10,  /* the requested variant or tile is not available  */
+    MF_ERR_HIP = -100     /* a HIP runtime call failed; see mf_last_error()  */
+};
+
+/* Options of median_filter_ex. Zero-initialise, then set what is needed. */
+typedef struct mf_options {
+    int32_t variant;  /* enum mf_variant                                     */
+    int32_t tile_w;   /* root tile width, power of two <= k; 0 = library's   */
+    int32_t tile_h;   /* root tile height, power of two <= k; 0 = library's  */
+} mf_options;
+
+/* k x k median of one plane (Section 1 definition, Section 3 method).
+ * src, dst: device pointers to H rows of W elements of `dtype`, pitch_bytes
+ * apart. Returns MF_OK once the kernels are enqueued on `stream`. */
+int32_t median_filter(const void* src, void* dst, int64_t H, int64_t W,
+                      int64_t pitch_bytes, int32_t dtype, int32_t k,
+                      int32_t border, void* stream);
+
+/* As median_filter, with the variant and root tile chosen by the caller
+ * (opt may be NULL = defaults). A variant or tile the library was not built
+ * for returns MF_ERR_CONFIG. Results are identical for every valid choice. */
+int32_t median_filter_ex(const void* src, void* dst, int64_t H, int64_t W,
+                         int64_t pitch_bytes, int32_t dtype, int32_t k,
+                         int32_t border, const mf_options* opt, void* stream);
+
+/* The configuration median_filter_ex would run for (dtype, k, opt): the
+ * variant and root tile actually used. Host-only; no GPU needed. */
+int32_t mf_query_config(int32_t dtype, int32_t k, const mf_options* opt,
+                        int32_t* variant, int32_t* tile_w, int32_t* tile_h);
+
+/* Largest supported kernel diameter. */
+int32_t mf_max_k(void);
+
+/* Static description of a status code. */
+const char* mf_status_string(int32_t status);
+
+/* Detail of the last error on the calling thread ("" if none). */
+const char* mf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MEDFILT_H */

@@ -1,0 +1,84 @@
+"""ctypes binding of libmedfilt.so (include/medfilt.h): argument marshalling only.
+
+The library must have been built (``__graft_entry__.build()`` or
+``python -m paper_2507_19926_amd.build``); loading fails loudly otherwise.
+There is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmedfilt.so")
+
+MF_U8, MF_U16, MF_U32, MF_F32 = 0, 1, 2, 3
+MF_BORDER_REPLICATE = 0
+MF_VARIANT_AUTO, MF_VARIANT_OBLIVIOUS, MF_VARIANT_DATA_AWARE = 0, 1, 2
+
+STATUS = {
+    0: "MF_OK", -1: "MF_ERR_NULL", -2: "MF_ERR_DIMS", -3: "MF_ERR_PITCH", -4: "MF_ERR_DTYPE",
+    -5: "MF_ERR_K", -6: "MF_ERR_BORDER", -7: "MF_ERR_ALIAS", -8: "MF_ERR_NOMEM",
+    -9: "MF_ERR_PLAN", -10: "MF_ERR_CONFIG", -100: "MF_ERR_HIP",
+}
+
+
+class MfError(RuntimeError):
+    def __init__(self, code: int, detail: str):
+        self.code = code
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, detail))
+
+
+class mf_options(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmedfilt.so once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libmedfilt.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    L.median_filter.argtypes = [vp, vp, i64, i64, i64, i32, i32, i32, vp]
+    L.median_filter.restype = i32
+    L.median_filter_ex.argtypes = [vp, vp, i64, i64, i64, i32, i32, i32, ctypes.POINTER(mf_options), vp]
+    L.median_filter_ex.restype = i32
+    L.mf_query_config.argtypes = [i32, i32, ctypes.POINTER(mf_options), ctypes.POINTER(i32),
+                                  ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.mf_query_config.restype = i32
+    L.mf_max_k.argtypes = []
+    L.mf_max_k.restype = i32
+    L.mf_status_string.argtypes = [i32]
+    L.mf_status_string.restype = ctypes.c_char_p
+    L.mf_last_error.argtypes = []
+    L.mf_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def check(code: int) -> None:
+    if code != 0:
+        raise MfError(code, lib().mf_last_error().decode())
+
+
+def options(variant: int = MF_VARIANT_AUTO, tile=None) -> mf_options:
+    o = mf_options()
+    o.variant = variant
+    if tile is not None:
+        o.tile_w, o.tile_h = int(tile[0]), int(tile[1])
+    return o
+
+
+def query_config(dtype_code: int, k: int, variant: int = MF_VARIANT_AUTO, tile=None):
+    """(variant, tile_w, tile_h) the library runs for this dtype, k and request."""
+    v, tw, th = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    o = options(variant, tile)
+    check(lib().mf_query_config(dtype_code, k, ctypes.byref(o), ctypes.byref(v), ctypes.byref(tw),
+                                ctypes.byref(th)))
+    return v.value, tw.value, th.value

@@ -1,0 +1,93 @@
+"""Build the HIP library ``libmedfilt.so`` for gfx950, in-tree.
+
+Steps: generate the oblivious network translation units (emit_hip), compile
+every HIP/C++ source with hipcc (in parallel), link one shared library next to
+this file. The library is what the Python binding loads; nothing is built at
+import time.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+from . import emit_hip
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+BUILD = os.path.join(PKG, "_build")
+GEN = os.path.join(BUILD, "gen")
+LIB = os.path.join(PKG, "libmedfilt.so")
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+
+# Oblivious configurations compiled into the library: (k, t_w, t_h, tile rows
+# per wave). The first entry for each k is the default; the others can be
+# requested through mf_options (and are what the tuner compares).
+OBL_CONFIGS = [
+    (3, 2, 1, 8), (3, 1, 1, 8), (3, 2, 2, 4),
+    (5, 4, 2, 2), (5, 2, 2, 2),
+    (7, 4, 2, 2), (7, 2, 2, 2),
+    (9, 4, 4, 1), (9, 8, 2, 1),
+    (11, 4, 4, 1), (11, 4, 2, 2),
+    (13, 4, 4, 1),
+    (15, 4, 4, 1),
+]
+
+HIP_FLAGS = [
+    "-O3", "-std=c++17", "--offload-arch=%s" % ARCH, "-fPIC",
+    # no packed-fp32 instructions anywhere in the library
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function",
+]
+
+
+def _compile(src: str, obj: str, extra=()) -> tuple[str, str]:
+    cmd = [HIPCC] + HIP_FLAGS + list(extra) + [
+        "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-I", GEN,
+        "-c", src, "-o", obj]
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), p.stderr[-6000:]))
+    return obj, p.stderr
+
+
+def build(jobs: int | None = None, verbose: bool = False) -> str:
+    """Generate, compile and link. Returns the path of libmedfilt.so."""
+    os.makedirs(GEN, exist_ok=True)
+    obl_srcs = emit_hip.generate(GEN, OBL_CONFIGS)
+    srcs = [os.path.join(CSRC, "mf_api.cpp"), os.path.join(CSRC, "mf_data_aware.hip")] + obl_srcs
+    objs = []
+    jobs = jobs or min(16, os.cpu_count() or 4)
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        futs = []
+        for s in srcs:
+            obj = os.path.join(BUILD, os.path.basename(s) + ".o")
+            objs.append(obj)
+            extra = ["-x", "hip"] if s.endswith(".hip") else []
+            futs.append(ex.submit(_compile, s, obj, extra))
+        for f in futs:
+            _, err = f.result()
+            if verbose and err.strip():
+                print(err, file=sys.stderr)
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=%s" % ARCH, "-o", tmp] + objs
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError("link failed:\n%s" % p.stderr[-4000:])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def clean() -> None:
+    shutil.rmtree(BUILD, ignore_errors=True)
+    if os.path.exists(LIB):
+        os.remove(LIB)
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

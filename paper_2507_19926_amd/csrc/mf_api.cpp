@@ -1,0 +1,210 @@
+// C ABI of the median filter: argument validation, configuration choice and
+// dispatch to the compiled kernels. Every check runs on the host before any
+// GPU call, so a bad argument never reaches a kernel.
+#include <hip/hip_runtime.h>
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "mf_internal.h"
+
+#define MF_OBL_ENTRY(K, TW, TH, RY) MF_OBL_DECLARE(K, TW, TH, RY)
+#include "mf_obl_table.inc"
+#undef MF_OBL_ENTRY
+
+namespace {
+
+struct OblEntry {
+    int k, tw, th, ry;
+    mf_launch_fn p16, u32;
+};
+
+const OblEntry kOblTable[] = {
+#define MF_OBL_ENTRY(K, TW, TH, RY) {K, TW, TH, RY, MF_OBL_NAME(K, TW, TH, p16), MF_OBL_NAME(K, TW, TH, u32)},
+#include "mf_obl_table.inc"
+#undef MF_OBL_ENTRY
+};
+constexpr int kOblCount = sizeof(kOblTable) / sizeof(kOblTable[0]);
+
+constexpr int kMaxK = 75;
+
+thread_local std::string g_last_error;
+
+int32_t fail(int32_t code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int32_t fail(int32_t code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int elem_size(int32_t dtype)
+{
+    switch (dtype) {
+    case MF_U8: return 1;
+    case MF_U16: return 2;
+    case MF_U32: return 4;
+    case MF_F32: return 4;
+    default: return 0;
+    }
+}
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+const OblEntry* find_obl(int k, int tw, int th)
+{
+    for (int i = 0; i < kOblCount; ++i) {
+        const OblEntry& e = kOblTable[i];
+        if (e.k == k && (tw == 0 || e.tw == tw) && (th == 0 || e.th == th))
+            return &e;  // the table lists each k's preferred tile first
+    }
+    return nullptr;
+}
+
+// Resolve (dtype, k, opt) to a variant and root tile. Host only.
+int32_t resolve(int32_t dtype, int32_t k, const mf_options* opt, int32_t* variant, int32_t* tw,
+                int32_t* th, const OblEntry** obl)
+{
+    mf_options o = {};
+    if (opt) o = *opt;
+    if (o.variant < MF_VARIANT_AUTO || o.variant > MF_VARIANT_DATA_AWARE)
+        return fail(MF_ERR_CONFIG, "unknown variant %d", o.variant);
+    if ((o.tile_w && (!pow2(o.tile_w) || o.tile_w > k)) || (o.tile_h && (!pow2(o.tile_h) || o.tile_h > k)) ||
+        o.tile_w < 0 || o.tile_h < 0)
+        return fail(MF_ERR_CONFIG, "root tile %dx%d is not a pair of powers of two <= k=%d", o.tile_w,
+                    o.tile_h, k);
+    *obl = nullptr;
+    if (o.variant != MF_VARIANT_DATA_AWARE) {
+        const OblEntry* e = find_obl(k, o.tile_w, o.tile_h);
+        if (e) {
+            *variant = MF_VARIANT_OBLIVIOUS;
+            *tw = e->tw;
+            *th = e->th;
+            *obl = e;
+            return MF_OK;
+        }
+        if (o.variant == MF_VARIANT_OBLIVIOUS)
+            return fail(MF_ERR_CONFIG, "no oblivious network compiled for k=%d tile %dx%d", k, o.tile_w,
+                        o.tile_h);
+    }
+    int dtw = o.tile_w, dth = o.tile_h;
+    if (!dtw || !dth) {
+        int a = 0, b = 0;
+        mf_da_default_tile(dtype, k, &a, &b);
+        if (!dtw) dtw = a;
+        if (!dth) dth = b;
+    }
+    if (!mf_da_supports(dtype, k, dtw, dth))
+        return fail(MF_ERR_CONFIG, "data-aware variant does not support k=%d tile %dx%d", k, dtw, dth);
+    *variant = MF_VARIANT_DATA_AWARE;
+    *tw = dtw;
+    *th = dth;
+    return MF_OK;
+}
+
+int32_t validate(const void* src, const void* dst, int64_t H, int64_t W, int64_t pitch, int32_t dtype,
+                 int32_t k, int32_t border)
+{
+    if (!src || !dst) return fail(MF_ERR_NULL, "src or dst is NULL");
+    const int s = elem_size(dtype);
+    if (!s) return fail(MF_ERR_DTYPE, "unknown dtype %d", dtype);
+    if (H < 1 || W < 1 || H > (1 << 30) || W > (1 << 30))
+        return fail(MF_ERR_DIMS, "H=%lld W=%lld outside [1, 2^30]", (long long)H, (long long)W);
+    if (pitch < W * s || pitch % s || pitch > ((int64_t)1 << 40))
+        return fail(MF_ERR_PITCH, "pitch %lld invalid for W=%lld of %d-byte elements", (long long)pitch,
+                    (long long)W, s);
+    if (k < 1 || k % 2 == 0 || k > kMaxK) return fail(MF_ERR_K, "k=%d must be odd in [1, %d]", k, kMaxK);
+    if (border != MF_BORDER_REPLICATE) return fail(MF_ERR_BORDER, "unknown border mode %d", border);
+    const uintptr_t a0 = (uintptr_t)src, b0 = (uintptr_t)dst;
+    const uintptr_t len = (uintptr_t)((H - 1) * pitch + W * s);
+    if (a0 < b0 + len && b0 < a0 + len) return fail(MF_ERR_ALIAS, "src and dst overlap");
+    return MF_OK;
+}
+
+int32_t hip_status(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return MF_OK;
+    return fail(MF_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t median_filter_ex(const void* src, void* dst, int64_t H, int64_t W, int64_t pitch_bytes,
+                         int32_t dtype, int32_t k, int32_t border, const mf_options* opt, void* stream)
+{
+    g_last_error.clear();
+    int32_t rc = validate(src, dst, H, W, pitch_bytes, dtype, k, border);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int s = elem_size(dtype);
+    if (k == 1)
+        return hip_status(hipMemcpy2DAsync(dst, pitch_bytes, src, pitch_bytes, W * s, H,
+                                           hipMemcpyDeviceToDevice, st),
+                          "hipMemcpy2DAsync");
+    int32_t variant = 0, tw = 0, th = 0;
+    const OblEntry* e = nullptr;
+    rc = resolve(dtype, k, opt, &variant, &tw, &th, &e);
+    if (rc) return rc;
+    if (variant == MF_VARIANT_OBLIVIOUS) {
+        mf_launch_fn fn = (dtype == MF_U8 || dtype == MF_U16) ? e->p16 : e->u32;
+        return hip_status(fn(src, dst, (int)H, (int)W, pitch_bytes, dtype, st), "oblivious kernel launch");
+    }
+    return hip_status(mf_da_launch(src, dst, (int)H, (int)W, pitch_bytes, dtype, k, tw, th, st),
+                      "data-aware kernel launch");
+}
+
+int32_t median_filter(const void* src, void* dst, int64_t H, int64_t W, int64_t pitch_bytes,
+                      int32_t dtype, int32_t k, int32_t border, void* stream)
+{
+    return median_filter_ex(src, dst, H, W, pitch_bytes, dtype, k, border, nullptr, stream);
+}
+
+int32_t mf_query_config(int32_t dtype, int32_t k, const mf_options* opt, int32_t* variant,
+                        int32_t* tile_w, int32_t* tile_h)
+{
+    g_last_error.clear();
+    if (!variant || !tile_w || !tile_h) return fail(MF_ERR_NULL, "output pointer is NULL");
+    if (!elem_size(dtype)) return fail(MF_ERR_DTYPE, "unknown dtype %d", dtype);
+    if (k < 1 || k % 2 == 0 || k > kMaxK) return fail(MF_ERR_K, "k=%d must be odd in [1, %d]", k, kMaxK);
+    if (k == 1) {
+        *variant = MF_VARIANT_AUTO;
+        *tile_w = *tile_h = 1;
+        return MF_OK;
+    }
+    const OblEntry* e = nullptr;
+    return resolve(dtype, k, opt, variant, tile_w, tile_h, &e);
+}
+
+int32_t mf_max_k(void) { return kMaxK; }
+
+const char* mf_status_string(int32_t status)
+{
+    switch (status) {
+    case MF_OK: return "ok";
+    case MF_ERR_NULL: return "null pointer";
+    case MF_ERR_DIMS: return "bad image dimensions";
+    case MF_ERR_PITCH: return "bad pitch";
+    case MF_ERR_DTYPE: return "bad dtype";
+    case MF_ERR_K: return "bad kernel diameter";
+    case MF_ERR_BORDER: return "bad border mode";
+    case MF_ERR_ALIAS: return "source and destination overlap";
+    case MF_ERR_NOMEM: return "out of device memory";
+    case MF_ERR_PLAN: return "bad plan";
+    case MF_ERR_CONFIG: return "configuration not available";
+    case MF_ERR_HIP: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+const char* mf_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

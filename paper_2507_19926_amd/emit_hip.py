@@ -1,0 +1,139 @@
+"""Emit HIP source for the data-oblivious kernels from the generated networks.
+
+For every configured (k, t_w, t_h) this writes one translation unit that
+
+* defines the straight-line selection network of ``netgen.build_tile_program``
+  as a device function over a value type V (``uint32_t`` for 32-bit data,
+  ``us2`` = two packed 16-bit lanes for 8/16-bit data), reading sorted
+  columns and raw values from LDS at compile-time offsets and handing each
+  median to a sink as soon as it is produced;
+* defines the odd-even merge sort of the column length as a register network;
+* instantiates ``mf_obl_kernel`` (csrc/mf_oblivious.hip) for both value types
+  and registers their launchers in a table the dispatcher reads.
+
+Only live operations are emitted (pruning = dead-code elimination), in the
+order a depth-first walk from each median needs them, which keeps register
+pressure close to the tile recursion's own state.
+"""
+from __future__ import annotations
+
+import os
+
+from . import netgen as ng
+
+
+def _net_body(P: ng.Prog, k: int, tw: int, th: int, indent: str = "    ") -> list[str]:
+    """Emit the live ops. Every load stays inside the root footprint
+    (x < k+tw-1, y < k+th-1) and the sorted column length (i < k-th+1): the
+    kernel's LDS buffers are sized for exactly that."""
+    lines = []
+    order = ng.demand_order(P)
+    out_index = {}
+    for i, o in enumerate(P.outputs):
+        out_index.setdefault(o, []).append(i)
+    for v in order:
+        op = P.ops[v]
+        if op[0] == ng.LD:
+            kind, a, b = op[1]
+            if kind == "col":
+                x, i = a, b
+                assert 0 <= x < k + tw - 1 and 0 <= i < k - th + 1, op
+                lines.append("%sconst V v%d = col[(%d) * Q + %d];" % (indent, v, i * tw + x % tw, x // tw))
+            else:
+                x, y = a, b
+                assert 0 <= x < k + tw - 1 and 0 <= y < k + th - 1, op
+                lines.append("%sconst V v%d = raw[(%d) * Q + %d];" % (indent, v, y * tw + x % tw, x // tw))
+        elif op[0] == ng.MIN:
+            lines.append("%sconst V v%d = vmin(v%d, v%d);" % (indent, v, op[1], op[2]))
+        else:
+            lines.append("%sconst V v%d = vmax(v%d, v%d);" % (indent, v, op[1], op[2]))
+        for i in out_index.get(v, ()):
+            assert 0 <= i < tw * th
+            lines.append("%ssink(%d, %d, v%d);" % (indent, i % tw, i // tw, v))
+    return lines
+
+
+def sort_network_pairs(n: int) -> list[tuple[int, int]]:
+    """Compare-exchange pairs (i, j), i < j, of the odd-even merge sort of n
+    wires, in an order valid for in-place execution."""
+    P = ng.Prog()
+    wires = [P.load(("in", i)) for i in range(n)]
+    outs = ng.sort(P, wires)
+    # Replay: each CAS creates a (min, max) pair; track which wire holds which
+    # SSA value to recover the in-place pairs.
+    holder = {v: i for i, v in enumerate(wires)}
+    pairs = []
+    for v, op in enumerate(P.ops):
+        if op[0] == ng.MIN:
+            a, b = op[1], op[2]
+            i, j = sorted((holder[a], holder[b]))
+            pairs.append((i, j))
+            mx = P._memo[(ng.MAX, a, b)]
+            # the min lands on the lower wire, the max on the upper one
+            holder[v] = i
+            holder[mx] = j
+    assert [holder[o] for o in outs] == list(range(n))
+    return pairs
+
+
+def emit_sort(n: int) -> str:
+    lines = ["template <class V> __device__ __forceinline__ void mf_sort_%d(V* a) {" % n]
+    for i, j in sort_network_pairs(n):
+        lines.append("    { const V lo = vmin(a[%d], a[%d]); a[%d] = vmax(a[%d], a[%d]); a[%d] = lo; }"
+                     % (i, j, j, i, j, i))
+    lines.append("}")
+    return "\n".join(lines)
+
+
+def emit_config_tu(k: int, tw: int, th: int, ry: int) -> str:
+    P = ng.build_tile_program(k, tw, th)
+    cnt = ng.op_counts(P)
+    name = "MfNet_k%d_%dx%d" % (k, tw, th)
+    lc = k - th + 1
+    body = _net_body(P, k, tw, th, indent="        ")
+    src = [
+        "// Generated: hierarchical selection network, k=%d, root tile %dx%d." % (k, tw, th),
+        "// live min/max ops per root tile: %d (%.2f per pixel), LDS loads: %d"
+        % (cnt["minmax"], cnt["minmax"] / (tw * th), cnt["loads"]),
+        '#include "mf_oblivious.hip"',
+        "",
+        emit_sort(lc) if lc > 1 else "template <class V> __device__ __forceinline__ void mf_sort_1(V*) {}",
+        "",
+        "struct %s {" % name,
+        "    static constexpr int K = %d, TW = %d, TH = %d, LC = %d;" % (k, tw, th, lc),
+        "    template <class V> static __device__ __forceinline__ void sort_column(V* a) { mf_sort_%d(a); }" % lc,
+        "    template <int Q, class V, class Sink>",
+        "    static __device__ __forceinline__ void run(const V* __restrict__ col,",
+        "                                               const V* __restrict__ raw, Sink& sink) {",
+    ] + body + [
+        "    }",
+        "};",
+        "",
+        "MF_OBL_INSTANTIATE(%s, %d)" % (name, ry),
+        "",
+    ]
+    return "\n".join(src)
+
+
+def generate(out_dir: str, configs) -> list[str]:
+    """Write one .hip per config plus the launcher table; return the .hip paths."""
+    os.makedirs(out_dir, exist_ok=True)
+    paths = []
+    table = []
+    for (k, tw, th, ry) in configs:
+        path = os.path.join(out_dir, "mf_obl_k%d_%dx%d.hip" % (k, tw, th))
+        text = emit_config_tu(k, tw, th, ry)
+        old = open(path).read() if os.path.exists(path) else None
+        if old != text:
+            with open(path, "w") as f:
+                f.write(text)
+        paths.append(path)
+        table.append("MF_OBL_ENTRY(%d, %d, %d, %d)" % (k, tw, th, ry))
+    tpath = os.path.join(out_dir, "mf_obl_table.inc")
+    text = "// Generated list of compiled oblivious configurations: (k, t_w, t_h, tile rows per wave)\n" \
+        + "\n".join(table) + "\n"
+    old = open(tpath).read() if os.path.exists(tpath) else None
+    if old != text:
+        with open(tpath, "w") as f:
+            f.write(text)
+    return paths

@@ -1,0 +1,79 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/*.h, and rejects bad arguments on the host before any GPU
+work (every error code of the header)."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from paper_2507_19926_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while", "sizeof")))
+
+
+def test_exports_every_declared_symbol():
+    L = _lib.lib()
+    names = _declared_functions()
+    assert "median_filter" in names and "mf_last_error" in names
+    for n in names:
+        assert hasattr(L, n), "missing export %s" % n
+
+
+FAKE_SRC = 0x10000000
+FAKE_DST = 0x20000000
+
+
+def _call(src=FAKE_SRC, dst=FAKE_DST, H=16, W=16, pitch=16, dtype=0, k=3, border=0, opt=None):
+    L = _lib.lib()
+    o = ctypes.byref(opt) if opt is not None else None
+    return L.median_filter_ex(src, dst, H, W, pitch, dtype, k, border, o, None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(src=None), -1), (dict(dst=None), -1),
+    (dict(H=0), -2), (dict(W=0), -2), (dict(H=-3), -2), (dict(W=2 ** 31), -2),
+    (dict(pitch=15), -3), (dict(dtype=1, pitch=31), -3), (dict(dtype=2, pitch=62), -3),
+    (dict(dtype=7), -4), (dict(dtype=-1), -4),
+    (dict(k=4), -5), (dict(k=0), -5), (dict(k=-3), -5), (dict(k=77), -5),
+    (dict(border=1), -6),
+    (dict(dst=FAKE_SRC + 100), -7), (dict(dst=FAKE_SRC - 255 + 16), -7), (dict(dst=FAKE_SRC), -7),
+    (dict(opt=_lib.options(variant=9)), -10),
+    (dict(opt=_lib.options(tile=(3, 1))), -10),
+    (dict(opt=_lib.options(tile=(4, 4)), k=3), -10),
+])
+def test_validation_codes(kw, code):
+    assert _call(**kw) == code
+    assert _lib.lib().mf_last_error().decode() != ""
+    assert _lib.lib().mf_status_string(code).decode() not in ("", "unknown status")
+
+
+def test_adjacent_buffers_are_not_aliases():
+    # dst starts right after the last byte of src: no overlap, so validation
+    # passes and the call reaches the launch (which fails without a GPU, or
+    # is never reached when the oblivious table lacks the config).
+    code = _call(dst=FAKE_SRC + 15 * 16 + 16, opt=_lib.options(variant=1, tile=(8, 8)), k=3)
+    assert code == -10  # rejected on the config, after the alias check passed
+
+
+def test_query_config():
+    for dtype in range(4):
+        v, tw, th = _lib.query_config(dtype, 1)
+        assert (tw, th) == (1, 1)
+    v, tw, th = _lib.query_config(0, 9)
+    assert v == _lib.MF_VARIANT_OBLIVIOUS and tw >= 1 and th >= 1
+    with pytest.raises(_lib.MfError):
+        _lib.query_config(0, 8)
+    with pytest.raises(_lib.MfError):
+        _lib.query_config(5, 9)
+    assert _lib.lib().mf_max_k() >= 75

@@ -1,0 +1,107 @@
+"""GPU parity: the HIP kernels against the CPU oracle, bit-exact (selection
+does no rounding, so every dtype must match exactly)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2507_19926_amd import _lib, build as mfbuild, workloads as wl
+from paper_2507_19926_amd.ops import median_filter
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = [np.uint8, np.uint16, np.uint32, np.float32]
+TORCH_DT = {np.dtype(np.uint8): torch.uint8, np.dtype(np.uint16): torch.uint16,
+            np.dtype(np.uint32): torch.uint32, np.dtype(np.float32): torch.float32}
+
+
+def _dev(a: np.ndarray) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _gpu(a: np.ndarray, k: int, **kw) -> np.ndarray:
+    out = median_filter(_dev(a), k, **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def _img(dtype, H, W, seed):
+    if np.dtype(dtype) == np.float32:
+        return wl.float_specials_plane(H, W, seed)
+    return wl.uniform_plane(H, W, dtype, seed)
+
+
+def _eq(a, b):
+    return a.tobytes() == b.tobytes()
+
+
+def test_gpu_present():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    name = torch.cuda.get_device_properties(0).gcnArchName
+    assert name.startswith("gfx950"), name
+
+
+OBL = [(k, tw, th) for (k, tw, th, _ry) in mfbuild.OBL_CONFIGS]
+
+
+@pytest.mark.parametrize("k,tw,th", OBL)
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_oblivious_configs_match_oracle(k, tw, th, dtype):
+    # ragged: several work-groups in each direction plus partial tiles
+    H, W = 45 + 7 * k, 1100 + k
+    img = _img(dtype, H, W, seed=k * 10 + tw)
+    got = _gpu(img, k, variant=_lib.MF_VARIANT_OBLIVIOUS, tile=(tw, th))
+    want = oracle.median_filter(img, k)
+    if not _eq(got, want):
+        bad = np.argwhere(got.view(np.uint8).reshape(H, -1) != want.view(np.uint8).reshape(H, -1))
+        pytest.fail("k=%d tile %dx%d %s: %d mismatching bytes, first at %s"
+                    % (k, tw, th, np.dtype(dtype).name, len(bad), bad[:5].tolist()))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("shape", [(1, 1), (1, 300), (300, 1), (2, 3), (5, 700), (129, 65)])
+def test_small_and_degenerate_shapes(dtype, shape):
+    for k in (3, 5, 9, 15):
+        img = _img(dtype, *shape, seed=sum(shape) + k)
+        assert _eq(_gpu(img, k), oracle.median_filter(img, k)), (shape, k)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_k1_identity(dtype):
+    img = _img(dtype, 33, 47, seed=1)
+    assert _eq(_gpu(img, 1), img)
+
+
+def test_pitched_rows():
+    img = wl.uniform_plane(70, 301, np.uint8, seed=3)
+    big = torch.zeros((70, 384), dtype=torch.uint8, device="cuda")
+    big[:, :301] = _dev(img)
+    view = big[:, :301]
+    out_big = torch.full((70, 384), 7, dtype=torch.uint8, device="cuda")
+    out = out_big[:, :301]
+    median_filter(view, 5, out=out)
+    torch.cuda.synchronize()
+    assert _eq(out.cpu().numpy(), oracle.median_filter(img, 5))
+    # padding bytes beyond W are untouched
+    assert torch.all(out_big[:, 301:] == 7)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_tie_heavy(dtype):
+    img = wl.tie_heavy_plane(101, 517, dtype, levels=3, seed=9)
+    for k in (3, 7, 11):
+        assert _eq(_gpu(img, k), oracle.median_filter(img, k))
+
+
+def test_deterministic():
+    img = wl.uniform_plane(257, 1031, np.uint16, seed=4)
+    a = _gpu(img, 9)
+    b = _gpu(img, 9)
+    assert _eq(a, b)
+
+
+def test_batch_of_planes():
+    x = wl.rgb30_planes(H=97, W=613, seed=2)
+    got = _gpu(x, 7)
+    for c in range(3):
+        assert _eq(got[c], oracle.median_filter(x[c], 7))
