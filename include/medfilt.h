@@ -87,6 +87,60 @@ int32_t median_filter_ex(const void* src, void* dst, int64_t H, int64_t W,
 int32_t mf_query_config(int32_t dtype, int32_t k, const mf_options* opt,
                         int32_t* variant, int32_t* tile_w, int32_t* tile_h);
 
+/* ---- Batched form -------------------------------------------------------
+ * Many images of uneven sizes, kernel diameters and dtypes filtered by ONE
+ * hipGraph launch. A plan groups its images by kernel (variant, k, root tile,
+ * value class) and gives each group one kernel node whose grid covers all of
+ * the group's images; the nodes run as parallel graph branches. Each image
+ * follows the conventions of median_filter (k >= 3 here); no destination may
+ * overlap another image's source or destination. */
+typedef struct mf_image {
+    const void* src;       /* device pointer */
+    void* dst;             /* device pointer */
+    int64_t H, W, pitch_bytes;
+    int32_t dtype, k, border;
+} mf_image;
+
+typedef struct mf_plan_s* mf_plan;
+
+/* Build a plan for n images: device job tables (one hipMalloc, owned by the
+ * plan) and an instantiated graph. *plan is NULL on failure. */
+int32_t mf_plan_create(const mf_image* imgs, int32_t n, mf_plan* plan);
+
+/* Same images (shapes, pitches, dtypes, k) with new pointers. Waits for the
+ * device to be idle, then rewrites the job tables; the graph is reused. */
+int32_t mf_plan_update(mf_plan plan, const mf_image* imgs, int32_t n);
+
+/* One graph launch on `stream` filtering every image of the plan. */
+int32_t mf_plan_launch(mf_plan plan, void* stream);
+
+/* Number of kernel groups and total work-groups of a plan (host only). */
+int32_t mf_plan_info(mf_plan plan, int32_t* buckets, int64_t* blocks);
+
+/* Free a plan (waits for the device to be idle). NULL is ignored. */
+void mf_plan_destroy(mf_plan plan);
+
+/* Create a plan, launch it on `stream`, wait for it, destroy it. */
+int32_t median_filter_batched(const mf_image* imgs, int32_t n, void* stream);
+
+/* Differentiable form, forward: median (as median_filter) and argmedian of
+ * `planes` contiguous float32 planes of H x W (NCHW-style, plane stride H*W).
+ * idx[p] is the plane-local flat index y*W + x of the input pixel the median
+ * of p was taken from: among the pixels of p's clamped window whose bits equal
+ * the median, the lowest flat index. The paper has no gradient; this tie rule
+ * is the library's. src, dst and idx are device pointers that must not
+ * overlap; H*W must be < 2^31. */
+int32_t median_filter_fwd_argmedian(const float* src, float* dst, int32_t* idx, int64_t planes,
+                                    int64_t H, int64_t W, int32_t k, int32_t border, void* stream);
+
+/* Differentiable form, backward: grad_in[q] = sum of grad_out[p] over the
+ * pixels p of the same plane with idx[p] == q, added in binary32 from +0 in
+ * ascending p (bit-reproducible, no atomics). idx must come from
+ * median_filter_fwd_argmedian with the same k. Device pointers, contiguous
+ * planes, grad_in must not overlap the inputs. */
+int32_t median_filter_bwd_gather(const float* grad_out, const int32_t* idx, float* grad_in, int64_t planes,
+                                 int64_t H, int64_t W, int32_t k, int32_t border, void* stream);
+
 /* Largest supported kernel diameter. */
 int32_t mf_max_k(void);
 

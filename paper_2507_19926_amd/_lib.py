@@ -33,6 +33,12 @@ class mf_options(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32)]
 
 
+class mf_image(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("H", ctypes.c_int64),
+                ("W", ctypes.c_int64), ("pitch_bytes", ctypes.c_int64), ("dtype", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("border", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -52,6 +58,23 @@ def lib():
     L.mf_query_config.argtypes = [i32, i32, ctypes.POINTER(mf_options), ctypes.POINTER(i32),
                                   ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.mf_query_config.restype = i32
+    L.median_filter_fwd_argmedian.argtypes = [vp, vp, vp, i64, i64, i64, i32, i32, vp]
+    L.median_filter_fwd_argmedian.restype = i32
+    L.median_filter_bwd_gather.argtypes = [vp, vp, vp, i64, i64, i64, i32, i32, vp]
+    L.median_filter_bwd_gather.restype = i32
+    pim = ctypes.POINTER(mf_image)
+    L.mf_plan_create.argtypes = [pim, i32, ctypes.POINTER(vp)]
+    L.mf_plan_create.restype = i32
+    L.mf_plan_update.argtypes = [vp, pim, i32]
+    L.mf_plan_update.restype = i32
+    L.mf_plan_launch.argtypes = [vp, vp]
+    L.mf_plan_launch.restype = i32
+    L.mf_plan_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+    L.mf_plan_info.restype = i32
+    L.mf_plan_destroy.argtypes = [vp]
+    L.mf_plan_destroy.restype = None
+    L.median_filter_batched.argtypes = [pim, i32, vp]
+    L.median_filter_batched.restype = i32
     L.mf_max_k.argtypes = []
     L.mf_max_k.restype = i32
     L.mf_status_string.argtypes = [i32]

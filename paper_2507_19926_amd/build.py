@@ -13,7 +13,7 @@ import shutil
 import subprocess
 import sys
 
-from . import emit_hip
+from . import emit_da, emit_hip
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -36,6 +36,7 @@ OBL_CONFIGS = [
     (11, 4, 4, 1), (11, 4, 2, 2),
     (13, 4, 4, 1),
     (15, 4, 4, 1),
+    (17, 4, 4, 1),
 ]
 
 HIP_FLAGS = [
@@ -60,7 +61,17 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     """Generate, compile and link. Returns the path of libmedfilt.so."""
     os.makedirs(GEN, exist_ok=True)
     obl_srcs = emit_hip.generate(GEN, OBL_CONFIGS)
-    srcs = [os.path.join(CSRC, "mf_api.cpp"), os.path.join(CSRC, "mf_data_aware.hip")] + obl_srcs
+    emit_da.generate(GEN)
+    blob_cpp = os.path.join(GEN, "mf_da_blob.cpp")
+    text = ("// Generated: host image of the data-aware schedules (copied to each device once).\n"
+            "__asm__(\".section .rodata\\n.balign 16\\n.global mf_da_blob_host\\n"
+            "mf_da_blob_host:\\n.incbin \\\"%s\\\"\\n.previous\\n\");\n"
+            % os.path.join(GEN, "mf_da_blob.bin"))
+    if not os.path.exists(blob_cpp) or open(blob_cpp).read() != text:
+        with open(blob_cpp, "w") as f:
+            f.write(text)
+    srcs = [os.path.join(CSRC, "mf_api.cpp"), os.path.join(CSRC, "mf_plan.cpp"), os.path.join(CSRC, "mf_data_aware.hip"),
+            os.path.join(CSRC, "mf_autograd.hip"), blob_cpp] + obl_srcs
     objs = []
     jobs = jobs or min(16, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:

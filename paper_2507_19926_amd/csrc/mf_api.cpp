@@ -20,10 +20,14 @@ namespace {
 struct OblEntry {
     int k, tw, th, ry;
     mf_launch_fn p16, u32;
+    void (*batched_p16)(MfBatchedKernel*);
+    void (*batched_u32)(MfBatchedKernel*);
 };
 
 const OblEntry kOblTable[] = {
-#define MF_OBL_ENTRY(K, TW, TH, RY) {K, TW, TH, RY, MF_OBL_NAME(K, TW, TH, p16), MF_OBL_NAME(K, TW, TH, u32)},
+#define MF_OBL_ENTRY(K, TW, TH, RY)                                                                  \
+    {K, TW, TH, RY, MF_OBL_NAME(K, TW, TH, p16), MF_OBL_NAME(K, TW, TH, u32),                       \
+     MF_OBL_BATCHED_NAME(K, TW, TH, p16), MF_OBL_BATCHED_NAME(K, TW, TH, u32)},
 #include "mf_obl_table.inc"
 #undef MF_OBL_ENTRY
 };
@@ -136,6 +140,27 @@ int32_t hip_status(hipError_t e, const char* what)
 
 }  // namespace
 
+int32_t mf_internal_validate(const void* src, const void* dst, int64_t H, int64_t W, int64_t pitch,
+                             int32_t dtype, int32_t k, int32_t border)
+{
+    return validate(src, dst, H, W, pitch, dtype, k, border);
+}
+
+int32_t mf_internal_fail(int32_t code, const char* msg) { return fail(code, "%s", msg); }
+
+int32_t mf_internal_resolve(int32_t dtype, int32_t k, int32_t* variant, int32_t* tw, int32_t* th,
+                            MfBatchedKernel* obl_p16, MfBatchedKernel* obl_u32)
+{
+    const OblEntry* e = nullptr;
+    int32_t rc = resolve(dtype, k, nullptr, variant, tw, th, &e);
+    if (rc) return rc;
+    if (e) {
+        e->batched_p16(obl_p16);
+        e->batched_u32(obl_u32);
+    }
+    return MF_OK;
+}
+
 extern "C" {
 
 int32_t median_filter_ex(const void* src, void* dst, int64_t H, int64_t W, int64_t pitch_bytes,
@@ -182,6 +207,55 @@ int32_t mf_query_config(int32_t dtype, int32_t k, const mf_options* opt, int32_t
     }
     const OblEntry* e = nullptr;
     return resolve(dtype, k, opt, variant, tile_w, tile_h, &e);
+}
+
+static bool overlap(const void* a, size_t na, const void* b, size_t nb)
+{
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+static int32_t validate_planes(int64_t planes, int64_t H, int64_t W, int32_t k, int32_t border)
+{
+    if (planes < 1 || H < 1 || W < 1 || H * W >= ((int64_t)1 << 31) || planes > ((int64_t)1 << 31) / 1)
+        return fail(MF_ERR_DIMS, "planes=%lld H=%lld W=%lld: need >= 1 and H*W < 2^31", (long long)planes,
+                    (long long)H, (long long)W);
+    if (k < 1 || k % 2 == 0 || k > kMaxK) return fail(MF_ERR_K, "k=%d must be odd in [1, %d]", k, kMaxK);
+    if (border != MF_BORDER_REPLICATE) return fail(MF_ERR_BORDER, "unknown border mode %d", border);
+    return MF_OK;
+}
+
+int32_t median_filter_fwd_argmedian(const float* src, float* dst, int32_t* idx, int64_t planes, int64_t H,
+                                    int64_t W, int32_t k, int32_t border, void* stream)
+{
+    g_last_error.clear();
+    if (!src || !dst || !idx) return fail(MF_ERR_NULL, "src, dst or idx is NULL");
+    int32_t rc = validate_planes(planes, H, W, k, border);
+    if (rc) return rc;
+    const size_t bytes = (size_t)(planes * H * W) * 4;
+    if (overlap(src, bytes, dst, bytes) || overlap(src, bytes, idx, bytes) || overlap(dst, bytes, idx, bytes))
+        return fail(MF_ERR_ALIAS, "src, dst and idx must not overlap");
+    for (int64_t p = 0; p < planes; ++p) {
+        rc = median_filter_ex(src + p * H * W, dst + p * H * W, H, W, W * 4, MF_F32, k, border, nullptr, stream);
+        if (rc) return rc;
+    }
+    g_last_error.clear();
+    return hip_status(mf_ag_argmedian_launch(src, dst, idx, planes, (int)H, (int)W, k, (hipStream_t)stream),
+                      "argmedian kernel launch");
+}
+
+int32_t median_filter_bwd_gather(const float* grad_out, const int32_t* idx, float* grad_in, int64_t planes,
+                                 int64_t H, int64_t W, int32_t k, int32_t border, void* stream)
+{
+    g_last_error.clear();
+    if (!grad_out || !idx || !grad_in) return fail(MF_ERR_NULL, "grad_out, idx or grad_in is NULL");
+    int32_t rc = validate_planes(planes, H, W, k, border);
+    if (rc) return rc;
+    const size_t bytes = (size_t)(planes * H * W) * 4;
+    if (overlap(grad_in, bytes, grad_out, bytes) || overlap(grad_in, bytes, idx, bytes))
+        return fail(MF_ERR_ALIAS, "grad_in overlaps an input");
+    return hip_status(mf_ag_grad_launch(grad_out, idx, grad_in, planes, (int)H, (int)W, k, (hipStream_t)stream),
+                      "gradient gather kernel launch");
 }
 
 int32_t mf_max_k(void) { return kMaxK; }

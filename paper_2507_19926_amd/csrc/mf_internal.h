@@ -13,16 +13,51 @@
 typedef hipError_t (*mf_launch_fn)(const void* src, void* dst, int H, int W,
                                    long long pitch, int dtype, hipStream_t stream);
 
+// One image of a batched launch. Images of one job table share the kernel
+// (k, root tile, value class); block_begin is the first grid block of the
+// image, ascending over the table.
+struct MfJob {
+    const unsigned char* src;
+    unsigned char* dst;
+    long long pitch;
+    int H, W, dtype, nbx, block_begin, pad;
+};
+
+// A batched kernel: function, launch shape, and the output block of one
+// work-group (bw x bh pixels; an image needs ceil(W/bw) x ceil(H/bh) blocks).
+struct MfBatchedKernel {
+    const void* fn;
+    int threads;
+    size_t lds;
+    int bw, bh;
+};
+
 #define MF_OBL_NAME(K, TW, TH, VC) mf_obl_launch_MfNet_k##K##_##TW##x##TH##_##VC
+#define MF_OBL_BATCHED_NAME(K, TW, TH, VC) mf_obl_batched_MfNet_k##K##_##TW##x##TH##_##VC
 
 #define MF_OBL_DECLARE(K, TW, TH, RY)                                          \
     hipError_t MF_OBL_NAME(K, TW, TH, p16)(const void*, void*, int, int,       \
                                            long long, int, hipStream_t);       \
     hipError_t MF_OBL_NAME(K, TW, TH, u32)(const void*, void*, int, int,       \
-                                           long long, int, hipStream_t);
+                                           long long, int, hipStream_t);       \
+    void MF_OBL_BATCHED_NAME(K, TW, TH, p16)(MfBatchedKernel*);                \
+    void MF_OBL_BATCHED_NAME(K, TW, TH, u32)(MfBatchedKernel*);
 
 // Data-aware launcher: one per value class, any k up to mf_max_k().
 hipError_t mf_da_launch(const void* src, void* dst, int H, int W, long long pitch,
                         int dtype, int k, int tw, int th, hipStream_t stream);
 bool mf_da_supports(int dtype, int k, int tw, int th);
 void mf_da_default_tile(int dtype, int k, int* tw, int* th);
+// Batched data-aware kernel for (dtype class, k, tile); the blob pointer and
+// schedule offsets are filled into *args (see mf_da_batched_args).
+struct MfDaArgs {
+    const uint32_t* blob;
+    int k, tw, th, c_off, r_off, nrounds, o_off;
+};
+hipError_t mf_da_batched(int dtype, int k, int tw, int th, MfBatchedKernel* kern, MfDaArgs* args);
+
+// Differentiable form (mf_autograd.hip).
+hipError_t mf_ag_argmedian_launch(const float* src, const float* med, int32_t* idx, int64_t planes, int H,
+                                  int W, int k, hipStream_t stream);
+hipError_t mf_ag_grad_launch(const float* gout, const int32_t* idx, float* gin, int64_t planes, int H, int W,
+                             int k, hipStream_t stream);

@@ -51,10 +51,11 @@ template <> struct MfVTraits<uint32_t> { static constexpr bool PACK = false; };
 
 __device__ __forceinline__ int mf_clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
+// One work-group's block (bx, by) of one image.
 template <class NET, class V, int RY>
-__global__ void __launch_bounds__(256)
-mf_obl_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
-              int H, int W, long long pitch, int dtype, int nbx)
+__device__ __forceinline__ void
+mf_obl_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
+             int H, int W, long long pitch, int dtype, int bx, int by)
 {
     constexpr bool PACK = MfVTraits<V>::PACK;
     constexpr int K = NET::K, TW = NET::TW, TH = NET::TH, LC = NET::LC;
@@ -68,7 +69,6 @@ mf_obl_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__
     __shared__ V raw[ROWS * TW * Q];
     __shared__ V colb[TY * LC * TW * Q];
 
-    const int bx = blockIdx.x % nbx, by = blockIdx.x / nbx;
     const int X0 = bx * (PACK ? 2 * BWH : BWH);
     const int Y0 = by * (TY * TH);
 
@@ -141,6 +141,43 @@ mf_obl_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__
 }
 
 template <class NET, class V, int RY>
+__global__ void __launch_bounds__(256)
+mf_obl_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
+              int H, int W, long long pitch, int dtype, int nbx)
+{
+    mf_obl_block<NET, V, RY>(src, dst, H, W, pitch, dtype, blockIdx.x % nbx, blockIdx.x / nbx);
+}
+
+// Batched form: the grid covers the blocks of every image of a job table
+// (images sharing k, root tile and value class); each work-group finds its
+// image by binary search over the jobs' first block indices.
+template <class NET, class V, int RY>
+__global__ void __launch_bounds__(256)
+mf_obl_kernel_batched(const MfJob* __restrict__ jobs, int njobs)
+{
+    const int b = blockIdx.x;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].block_begin <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const MfJob j = jobs[lo];
+    const int lb = b - j.block_begin;
+    mf_obl_block<NET, V, RY>(j.src, j.dst, j.H, j.W, j.pitch, j.dtype, lb % j.nbx, lb / j.nbx);
+}
+
+template <class NET, class V, int RY>
+static void mf_obl_batched(MfBatchedKernel* k)
+{
+    k->fn = (const void*)mf_obl_kernel_batched<NET, V, RY>;
+    k->threads = 256;
+    k->lds = 0;
+    k->bw = (MfVTraits<V>::PACK ? 2 : 1) * 64 * NET::TW;
+    k->bh = 4 * RY * NET::TH;
+}
+
+template <class NET, class V, int RY>
 static hipError_t mf_obl_launch(const void* src, void* dst, int H, int W, long long pitch,
                                 int dtype, hipStream_t stream)
 {
@@ -163,4 +200,6 @@ static hipError_t mf_obl_launch(const void* src, void* dst, int H, int W, long l
                                          long long p, int dt, hipStream_t st)            \
     {                                                                                     \
         return mf_obl_launch<NET, uint32_t, RY>(s, d, H, W, p, dt, st);                   \
-    }
+    }                                                                                     \
+    void mf_obl_batched_##NET##_p16(MfBatchedKernel* k) { mf_obl_batched<NET, us2, RY>(k); }       \
+    void mf_obl_batched_##NET##_u32(MfBatchedKernel* k) { mf_obl_batched<NET, uint32_t, RY>(k); }

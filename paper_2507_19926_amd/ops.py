@@ -56,3 +56,124 @@ def median_filter(x: torch.Tensor, k: int, out: torch.Tensor | None = None,
         _lib.check(L.median_filter_ex(planes_x[i].data_ptr(), planes_o[i].data_ptr(), H, W, pitch,
                                       code, int(k), _lib.MF_BORDER_REPLICATE, ctypes.byref(opt), stream))
     return out
+
+
+def median_filter_argmedian(x: torch.Tensor, k: int):
+    """(y, idx) for a float32 tensor (..., H, W): the median and, per output
+    pixel, the plane-local flat index of the input pixel it was taken from
+    (lowest index among window pixels equal to the median)."""
+    if not x.is_cuda or x.dtype != torch.float32 or x.dim() < 2:
+        raise ValueError("median_filter_argmedian needs a float32 GPU tensor (..., H, W)")
+    x = x.contiguous()
+    H, W = x.shape[-2], x.shape[-1]
+    planes = x.numel() // (H * W)
+    y = torch.empty_like(x)
+    idx = torch.empty(x.shape, dtype=torch.int32, device=x.device)
+    if planes:
+        _lib.check(_lib.lib().median_filter_fwd_argmedian(
+            x.data_ptr(), y.data_ptr(), idx.data_ptr(), planes, H, W, int(k),
+            _lib.MF_BORDER_REPLICATE, _stream_handle(x.device)))
+    return y, idx
+
+
+def median_filter_backward(grad_out: torch.Tensor, idx: torch.Tensor, k: int) -> torch.Tensor:
+    """Gradient of the median filter w.r.t. its input (deterministic gather)."""
+    g = grad_out.contiguous()
+    if g.dtype != torch.float32 or idx.dtype != torch.int32 or g.shape != idx.shape:
+        raise ValueError("grad_out must be float32 and match idx (int32) in shape")
+    H, W = g.shape[-2], g.shape[-1]
+    planes = g.numel() // (H * W)
+    gi = torch.empty_like(g)
+    if planes:
+        _lib.check(_lib.lib().median_filter_bwd_gather(
+            g.data_ptr(), idx.contiguous().data_ptr(), gi.data_ptr(), planes, H, W, int(k),
+            _lib.MF_BORDER_REPLICATE, _stream_handle(g.device)))
+    return gi
+
+
+class MedianFilterFn(torch.autograd.Function):
+    """y = median_filter(x, k) with the gradient routed to the argmedian.
+
+    forward saves the int32 argmedian; backward is the deterministic gather,
+    bit-identical to a scatter of grad_out in ascending output order."""
+
+    @staticmethod
+    def forward(ctx, x, k):
+        y, idx = median_filter_argmedian(x, k)
+        ctx.save_for_backward(idx)
+        ctx.k = int(k)
+        return y
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (idx,) = ctx.saved_tensors
+        return median_filter_backward(grad_out, idx, ctx.k), None
+
+
+def median_filter_ad(x: torch.Tensor, k: int) -> torch.Tensor:
+    return MedianFilterFn.apply(x, k)
+
+
+def _images(xs, outs, ks):
+    if not (len(xs) == len(outs) == len(ks)):
+        raise ValueError("xs, outs and ks differ in length")
+    arr = (_lib.mf_image * len(xs))()
+    for i, (x, o, k) in enumerate(zip(xs, outs, ks)):
+        if x.dim() != 2 or x.stride(-1) != 1 or o.shape != x.shape or o.stride() != x.stride():
+            raise ValueError("image %d: need 2-D row-major tensors with matching out" % i)
+        arr[i].src, arr[i].dst = x.data_ptr(), o.data_ptr()
+        arr[i].H, arr[i].W = x.shape
+        arr[i].pitch_bytes = x.stride(0) * x.element_size()
+        arr[i].dtype = dtype_code(x.dtype)
+        arr[i].k = int(k)
+        arr[i].border = _lib.MF_BORDER_REPLICATE
+    return arr
+
+
+class BatchedPlan:
+    """A plan filtering many (H, W) images of mixed sizes, k and dtypes with
+    one hipGraph launch (mf_plan_*). The tensors must stay alive while the
+    plan is used; update() swaps in new tensors of the same shapes."""
+
+    def __init__(self, xs, outs, ks):
+        self._arr = _images(xs, outs, ks)
+        self._keep = (list(xs), list(outs))
+        h = ctypes.c_void_p()
+        _lib.check(_lib.lib().mf_plan_create(self._arr, len(self._arr), ctypes.byref(h)))
+        self._h = h
+
+    def info(self):
+        b, n = ctypes.c_int32(), ctypes.c_int64()
+        _lib.check(_lib.lib().mf_plan_info(self._h, ctypes.byref(b), ctypes.byref(n)))
+        return b.value, n.value
+
+    def launch(self, stream=None):
+        dev = self._keep[0][0].device
+        s = stream.cuda_stream if stream is not None else _stream_handle(dev)
+        _lib.check(_lib.lib().mf_plan_launch(self._h, s))
+
+    def update(self, xs, outs, ks):
+        arr = _images(xs, outs, ks)
+        _lib.check(_lib.lib().mf_plan_update(self._h, arr, len(arr)))
+        self._arr, self._keep = arr, (list(xs), list(outs))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.lib().mf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def median_filter_batched(xs, ks, outs=None):
+    """One-shot batched filter (creates, launches and destroys a plan)."""
+    if outs is None:
+        outs = [torch.empty_like(x) for x in xs]
+    arr = _images(xs, outs, ks)
+    dev = xs[0].device
+    _lib.check(_lib.lib().median_filter_batched(arr, len(arr), _stream_handle(dev)))
+    return outs

@@ -77,3 +77,39 @@ def test_query_config():
     with pytest.raises(_lib.MfError):
         _lib.query_config(5, 9)
     assert _lib.lib().mf_max_k() >= 75
+
+
+def test_autograd_entry_validation():
+    L = _lib.lib()
+    A, B, C = 0x10000000, 0x20000000, 0x30000000
+    assert L.median_filter_fwd_argmedian(None, B, C, 1, 8, 8, 3, 0, None) == -1
+    assert L.median_filter_fwd_argmedian(A, B, C, 0, 8, 8, 3, 0, None) == -2
+    assert L.median_filter_fwd_argmedian(A, B, C, 1, 1 << 16, 1 << 16, 3, 0, None) == -2
+    assert L.median_filter_fwd_argmedian(A, B, C, 1, 8, 8, 2, 0, None) == -5
+    assert L.median_filter_fwd_argmedian(A, B, C, 1, 8, 8, 3, 4, None) == -6
+    assert L.median_filter_fwd_argmedian(A, A + 64, C, 1, 8, 8, 3, 0, None) == -7
+    assert L.median_filter_bwd_gather(A, B, A + 4, 1, 8, 8, 3, 0, None) == -7
+    assert L.median_filter_bwd_gather(A, None, C, 1, 8, 8, 3, 0, None) == -1
+
+
+def test_plan_validation():
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    assert L.mf_plan_create(None, 1, ctypes.byref(h)) == -1
+    arr = (_lib.mf_image * 2)()
+    for i in range(2):
+        arr[i].src, arr[i].dst = 0x10000000 + i * 0x100000, 0x20000000 + i * 0x100000
+        arr[i].H, arr[i].W, arr[i].pitch_bytes, arr[i].dtype, arr[i].k, arr[i].border = 16, 16, 16, 0, 3, 0
+    assert L.mf_plan_create(arr, 0, ctypes.byref(h)) == -2
+    assert L.mf_plan_create(arr, 2, None) == -1
+    arr[1].k = 1
+    assert L.mf_plan_create(arr, 2, ctypes.byref(h)) == -5
+    arr[1].k = 4
+    assert L.mf_plan_create(arr, 2, ctypes.byref(h)) == -5
+    arr[1].k = 3
+    arr[1].dst = arr[0].src + 8       # overlaps another image's source
+    assert L.mf_plan_create(arr, 2, ctypes.byref(h)) == -7
+    assert not h.value
+    assert L.mf_plan_launch(None, None) == -9
+    assert L.mf_plan_update(None, arr, 2) == -9
+    L.mf_plan_destroy(None)

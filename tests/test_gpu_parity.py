@@ -105,3 +105,50 @@ def test_batch_of_planes():
     got = _gpu(x, 7)
     for c in range(3):
         assert _eq(got[c], oracle.median_filter(x[c], 7))
+
+
+ALL_K = list(range(3, 76, 2))
+
+
+@pytest.mark.parametrize("k", ALL_K)
+def test_data_aware_every_k(k):
+    H, W = 23 + k // 3, 41 + k
+    for dtype in DTYPES:
+        img = _img(dtype, H, W, seed=1000 + k)
+        got = _gpu(img, k, variant=_lib.MF_VARIANT_DATA_AWARE)
+        want = oracle.median_filter(img, k)
+        assert _eq(got, want), (k, np.dtype(dtype).name, int((got != want).sum()))
+
+
+@pytest.mark.parametrize("k", [17, 25, 35, 51, 75])
+def test_data_aware_multi_workgroup(k):
+    img = wl.rgb30_planes(H=150, W=333, seed=k)[0]
+    assert _eq(_gpu(img, k, variant=_lib.MF_VARIANT_DATA_AWARE), oracle.median_filter(img, k))
+    u16 = wl.uniform_plane(97, 211, np.uint16, seed=k)
+    assert _eq(_gpu(u16, k), oracle.median_filter(u16, k))
+
+
+@pytest.mark.parametrize("k", [3, 9, 15, 17])
+def test_variants_agree(k):
+    img = wl.uniform_plane(131, 517, np.uint16, seed=k)
+    a = _gpu(img, k, variant=_lib.MF_VARIANT_OBLIVIOUS)
+    b = _gpu(img, k, variant=_lib.MF_VARIANT_DATA_AWARE)
+    assert _eq(a, b)
+
+
+@pytest.mark.parametrize("k", list(wl.RGB30_KS))
+def test_full_size_rgb30_sampled(k):
+    """The benchmark's workload and launch configuration (30 MP RGB uint8,
+    three planes on the current stream), checked at sampled pixels (corners,
+    edges and random interior points) against the oracle computed one by one."""
+    frame = wl.rgb30_planes()
+    H, W = frame.shape[1:]
+    got = _gpu(frame, k)
+    g = wl.rng(k)
+    ys = np.concatenate([[0, 0, H - 1, H - 1], g.integers(0, H, 400), np.zeros(50, int) + H - 1,
+                         g.integers(0, H, 50)])
+    xs = np.concatenate([[0, W - 1, 0, W - 1], g.integers(0, W, 400), g.integers(0, W, 50),
+                         np.zeros(50, int) + W - 1])
+    for c in range(3):
+        want = oracle.median_points(frame[c], k, ys, xs)
+        assert np.array_equal(got[c][ys, xs], want), (k, c)
