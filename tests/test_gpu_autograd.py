@@ -73,7 +73,9 @@ def test_central_finite_differences(k):
     rng = wl.rng(k)
     cand = [(n, qy, qx) for n in range(2) for qy in range(H) for qx in range(W)]
     rng.shuffle(cand)
-    for (n, qy, qx) in cand[:120]:
+    for (n, qy, qx) in cand:
+        if compared >= 50:
+            break
         v = xs[n, 0, qy, qx]
         y0, y1 = max(0, qy - 2 * r), min(H, qy + 2 * r + 1)
         x0, x1 = max(0, qx - 2 * r), min(W, qx + 2 * r + 1)
