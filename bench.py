@@ -42,6 +42,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle work for the CPU baseline")
     p.add_argument("--only-headline", action="store_true", help="time only the headline k (for profilers)")
+    p.add_argument("--no-extras", action="store_true",
+                   help="skip the dtype sweep, the batched comparison and the autograd timing")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a plain 256 MiB device copy (counter calibration) and exit")
     return p.parse_args()
@@ -81,6 +83,99 @@ def roofline(dtype_code: int, k: int, pixels_per_launch: int, launch_s: float):
     return {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK_BPS / 1e9, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_BPS, "traffic": None,
             "ops_per_pixel": round(ops_px, 2) if ops_px else None, "variant": variant, "tile": list(tile)}
+
+
+def _time(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / steps
+
+
+def run_extras(args, dev, stream):
+    """dtype sweep (4096^2 planes), batched plan vs per-image launches, and
+    the differentiable form's forward/backward on 32x3x512x512 float32."""
+    import numpy as np
+    import torch
+
+    from paper_2507_19926_amd import _lib, workloads as wl
+    from paper_2507_19926_amd.ops import (BatchedPlan, median_filter, median_filter_argmedian,
+                                          median_filter_backward)
+    out = {}
+    # dtype sweep: two distinct planes per dtype, alternated
+    sweep = {}
+    side = wl.SWEEP_SIDE
+    for name, dt, code in (("u16", np.uint16, _lib.MF_U16), ("u32", np.uint32, _lib.MF_U32),
+                           ("f32", np.float32, _lib.MF_F32)):
+        base = wl.sweep_plane(dt)
+        xs = [torch.from_numpy(base).to(dev), torch.from_numpy(np.roll(base, 131, axis=1)).to(dev)]
+        ys = [torch.empty_like(x) for x in xs]
+        res = {}
+        for k in wl.SWEEP_KS:
+            state = {"i": 0}
+
+            def one():
+                i = state["i"] = state["i"] + 1
+                median_filter(xs[i % 2], k, out=ys[i % 2])
+            t = _time(one, 3 if k >= 35 else 6, 1, stream)
+            r = roofline(code, k, side * side, t)
+            res[str(k)] = {"mpix_s": round(side * side / t / 1e6, 1), "kernel_ms": round(t * 1e3, 4),
+                           "bound": r["bound"], "frac": round(r["frac"], 4), "variant": r["variant"],
+                           "tile": r["tile"]}
+        sweep[name] = res
+        del xs, ys
+    out["dtype_sweep_4096"] = sweep
+
+    # batched: 256 mixed images, one plan launch vs 256 plain launches
+    batch = wl.mixed_batch()
+    xs = [torch.from_numpy(a).to(dev) for a, _ in batch]
+    ks = [k for _, k in batch]
+    outs = [torch.empty_like(x) for x in xs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = BatchedPlan(xs, outs, ks)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+
+    def per_image():
+        for x, k, o in zip(xs, ks, outs):
+            median_filter(x, k, out=o)
+    t_plain = _time(per_image, 5, 2, stream)
+    t_plan = _time(plan.launch, 5, 2, stream)
+    npx = sum(int(x.numel()) for x in xs)
+    nb, blocks = plan.info()
+    out["batched"] = {"images": len(xs), "pixels": npx, "plan_ms": round(t_plan * 1e3, 3),
+                      "per_image_ms": round(t_plain * 1e3, 3), "speedup": round(t_plain / t_plan, 3),
+                      "plan_mpix_s": round(npx / t_plan / 1e6, 1), "plan_create_ms": round(t_create * 1e3, 1),
+                      "buckets": nb}
+    plan.close()
+    del xs, outs
+
+    # differentiable form
+    x = torch.from_numpy(wl.autograd_tensor()).to(dev)
+    g = torch.from_numpy(wl.grad_out_like(tuple(x.shape))).to(dev)
+    ag = {}
+    for k in (7, 15):
+        holder = {}
+
+        def fwd():
+            holder["idx"] = median_filter_argmedian(x, k)[1]
+        t_f = _time(fwd, 3, 1, stream)
+        idx = holder["idx"]
+        t_b = _time(lambda: median_filter_backward(g, idx, k), 5, 1, stream)
+        n = x.numel()
+        ag[str(k)] = {"fwd_ms": round(t_f * 1e3, 3), "bwd_ms": round(t_b * 1e3, 3),
+                      "fwd_mpix_s": round(n / t_f / 1e6, 1), "bwd_mpix_s": round(n / t_b / 1e6, 1),
+                      "bwd_hbm_frac": round(12 * n / t_b / HBM_PEAK_BPS, 4)}
+    out["autograd_32x3x512x512"] = ag
+    return out
 
 
 def main():
@@ -160,6 +255,10 @@ def main():
             per_k[str(k)] = {"mpix_s": round(px_step * args.sweep_steps / w / 1e6, 1),
                              "kernel_ms": round(ls * 1e3, 4), "bound": r["bound"],
                              "frac": round(r["frac"], 4), "variant": r["variant"], "tile": r["tile"]}
+    extras = {}
+    if not args.no_extras and not args.only_headline:
+        extras = run_extras(args, dev, stream)
+
     cpu = None
     if not args.no_cpu:
         import oracle  # CPU baseline only
@@ -192,7 +291,7 @@ def main():
         "dtype": "u8", "data": "synthetic",
         "config": {"workload": "30MP RGB uint8, 3 planar 6720x4480 planes, k=%d, replicate border" % args.k,
                    "k": args.k, "H": H, "W": W, "planes": 3, "frames_rotated": nsets},
-        "roofline": roof, "cpu_baseline": cpu, "per_k": per_k,
+        "roofline": roof, "cpu_baseline": cpu, "per_k": per_k, **extras,
     }
     print(json.dumps(line))
 

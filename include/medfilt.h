@@ -12,7 +12,8 @@
  *   - Images are single planes, row-major, H rows of W elements, consecutive
  *     rows pitch_bytes apart. src and dst are DEVICE pointers owned by the
  *     caller, share the pitch and must not overlap (MF_ERR_ALIAS).
- *   - pitch_bytes >= W * sizeof(element) and a multiple of sizeof(element).
+ *   - pitch_bytes >= W * sizeof(element) and a multiple of sizeof(element);
+ *     src and dst are aligned to sizeof(element) (MF_ERR_PITCH otherwise).
  *   - k is odd, 1 <= k <= mf_max_k(); k = 1 copies the image. k may exceed H
  *     or W. Border: replicate (coordinates are clamped into the image); the
  *     paper states no border rule, this is the reading the library takes.
@@ -50,7 +51,8 @@ enum mf_status {
     MF_OK = 0,
     MF_ERR_NULL = -1,     /* a required pointer is NULL                       */
     MF_ERR_DIMS = -2,     /* H < 1, W < 1, or a size that overflows int32 math */
-    MF_ERR_PITCH = -3,    /* pitch_bytes < W*size or not a multiple of size   */
+    MF_ERR_PITCH = -3,    /* pitch_bytes < W*size, not a multiple of size, or
+                             a pointer not aligned to the element size       */
     MF_ERR_DTYPE = -4,    /* unknown dtype, or one the entry point refuses   */
     MF_ERR_K = -5,        /* k even, < 1 or > mf_max_k()                      */
     MF_ERR_BORDER = -6,   /* unknown border mode                              */
@@ -66,6 +68,8 @@ typedef struct mf_options {
     int32_t variant;  /* enum mf_variant                                     */
     int32_t tile_w;   /* root tile width, power of two <= k; 0 = library's   */
     int32_t tile_h;   /* root tile height, power of two <= k; 0 = library's  */
+    int32_t group;    /* data-aware: root tiles per work-group (1, 2, 4);
+                         0 = library's                                      */
 } mf_options;
 
 /* k x k median of one plane (Section 1 definition, Section 3 method).
@@ -140,6 +144,12 @@ int32_t median_filter_fwd_argmedian(const float* src, float* dst, int32_t* idx, 
  * planes, grad_in must not overlap the inputs. */
 int32_t median_filter_bwd_gather(const float* grad_out, const int32_t* idx, float* grad_in, int64_t planes,
                                  int64_t H, int64_t W, int32_t k, int32_t border, void* stream);
+
+/* Every compiled configuration for (dtype, k): writes up to `cap` entries to
+ * out (variant, tile_w, tile_h, group all set) and returns how many exist, or
+ * a negative mf_status. The first entry is the library's default. Host only;
+ * this is what an autotuner enumerates. */
+int32_t mf_list_configs(int32_t dtype, int32_t k, mf_options* out, int32_t cap);
 
 /* Largest supported kernel diameter. */
 int32_t mf_max_k(void);

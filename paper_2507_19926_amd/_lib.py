@@ -30,7 +30,8 @@ class MfError(RuntimeError):
 
 
 class mf_options(ctypes.Structure):
-    _fields_ = [("variant", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32)]
+    _fields_ = [("variant", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+                ("group", ctypes.c_int32)]
 
 
 class mf_image(ctypes.Structure):
@@ -75,6 +76,8 @@ def lib():
     L.mf_plan_destroy.restype = None
     L.median_filter_batched.argtypes = [pim, i32, vp]
     L.median_filter_batched.restype = i32
+    L.mf_list_configs.argtypes = [i32, i32, ctypes.POINTER(mf_options), i32]
+    L.mf_list_configs.restype = i32
     L.mf_max_k.argtypes = []
     L.mf_max_k.restype = i32
     L.mf_status_string.argtypes = [i32]
@@ -90,12 +93,26 @@ def check(code: int) -> None:
         raise MfError(code, lib().mf_last_error().decode())
 
 
-def options(variant: int = MF_VARIANT_AUTO, tile=None) -> mf_options:
+def options(variant: int = MF_VARIANT_AUTO, tile=None, group: int = 0) -> mf_options:
     o = mf_options()
     o.variant = variant
     if tile is not None:
         o.tile_w, o.tile_h = int(tile[0]), int(tile[1])
+    o.group = int(group)
     return o
+
+
+def list_configs(dtype_code: int, k: int):
+    """Every compiled (variant, tile_w, tile_h, group) for dtype and k, default first."""
+    L = lib()
+    n = L.mf_list_configs(dtype_code, k, None, 0)
+    if n < 0:
+        check(n)
+    arr = (mf_options * max(n, 1))()
+    m = L.mf_list_configs(dtype_code, k, arr, n)
+    if m < 0:
+        check(m)
+    return [(o.variant, o.tile_w, o.tile_h, o.group) for o in arr[:n]]
 
 
 def query_config(dtype_code: int, k: int, variant: int = MF_VARIANT_AUTO, tile=None):

@@ -74,12 +74,15 @@ const OblEntry* find_obl(int k, int tw, int th)
 
 // Resolve (dtype, k, opt) to a variant and root tile. Host only.
 int32_t resolve(int32_t dtype, int32_t k, const mf_options* opt, int32_t* variant, int32_t* tw,
-                int32_t* th, const OblEntry** obl)
+                int32_t* th, const OblEntry** obl, int32_t* group = nullptr)
 {
     mf_options o = {};
     if (opt) o = *opt;
     if (o.variant < MF_VARIANT_AUTO || o.variant > MF_VARIANT_DATA_AWARE)
         return fail(MF_ERR_CONFIG, "unknown variant %d", o.variant);
+    if (o.group != 0 && o.group != 1 && o.group != 2 && o.group != 4)
+        return fail(MF_ERR_CONFIG, "tiles per work-group %d not in {0, 1, 2, 4}", o.group);
+    if (group) *group = 0;
     if ((o.tile_w && (!pow2(o.tile_w) || o.tile_w > k)) || (o.tile_h && (!pow2(o.tile_h) || o.tile_h > k)) ||
         o.tile_w < 0 || o.tile_h < 0)
         return fail(MF_ERR_CONFIG, "root tile %dx%d is not a pair of powers of two <= k=%d", o.tile_w,
@@ -98,18 +101,17 @@ int32_t resolve(int32_t dtype, int32_t k, const mf_options* opt, int32_t* varian
             return fail(MF_ERR_CONFIG, "no oblivious network compiled for k=%d tile %dx%d", k, o.tile_w,
                         o.tile_h);
     }
-    int dtw = o.tile_w, dth = o.tile_h;
-    if (!dtw || !dth) {
-        int a = 0, b = 0;
-        mf_da_default_tile(dtype, k, &a, &b);
-        if (!dtw) dtw = a;
-        if (!dth) dth = b;
+    int dtw = o.tile_w, dth = o.tile_h, dg = o.group;
+    if (!dtw && !dth && !dg) {
+        mf_da_default_tile(dtype, k, &dtw, &dth, &dg);
     }
-    if (!mf_da_supports(dtype, k, dtw, dth))
-        return fail(MF_ERR_CONFIG, "data-aware variant does not support k=%d tile %dx%d", k, dtw, dth);
+    if (!mf_da_supports(dtype, k, dtw, dth, dg))
+        return fail(MF_ERR_CONFIG, "data-aware variant does not support k=%d tile %dx%d group %d", k, dtw, dth,
+                    dg);
     *variant = MF_VARIANT_DATA_AWARE;
     *tw = dtw;
     *th = dth;
+    if (group) *group = dg;
     return MF_OK;
 }
 
@@ -124,6 +126,8 @@ int32_t validate(const void* src, const void* dst, int64_t H, int64_t W, int64_t
     if (pitch < W * s || pitch % s || pitch > ((int64_t)1 << 40))
         return fail(MF_ERR_PITCH, "pitch %lld invalid for W=%lld of %d-byte elements", (long long)pitch,
                     (long long)W, s);
+    if (((uintptr_t)src | (uintptr_t)dst) % s)
+        return fail(MF_ERR_PITCH, "src/dst not aligned to the %d-byte element size", s);
     if (k < 1 || k % 2 == 0 || k > kMaxK) return fail(MF_ERR_K, "k=%d must be odd in [1, %d]", k, kMaxK);
     if (border != MF_BORDER_REPLICATE) return fail(MF_ERR_BORDER, "unknown border mode %d", border);
     const uintptr_t a0 = (uintptr_t)src, b0 = (uintptr_t)dst;
@@ -149,10 +153,10 @@ int32_t mf_internal_validate(const void* src, const void* dst, int64_t H, int64_
 int32_t mf_internal_fail(int32_t code, const char* msg) { return fail(code, "%s", msg); }
 
 int32_t mf_internal_resolve(int32_t dtype, int32_t k, int32_t* variant, int32_t* tw, int32_t* th,
-                            MfBatchedKernel* obl_p16, MfBatchedKernel* obl_u32)
+                            int32_t* group, MfBatchedKernel* obl_p16, MfBatchedKernel* obl_u32)
 {
     const OblEntry* e = nullptr;
-    int32_t rc = resolve(dtype, k, nullptr, variant, tw, th, &e);
+    int32_t rc = resolve(dtype, k, nullptr, variant, tw, th, &e, group);
     if (rc) return rc;
     if (e) {
         e->batched_p16(obl_p16);
@@ -175,15 +179,15 @@ int32_t median_filter_ex(const void* src, void* dst, int64_t H, int64_t W, int64
         return hip_status(hipMemcpy2DAsync(dst, pitch_bytes, src, pitch_bytes, W * s, H,
                                            hipMemcpyDeviceToDevice, st),
                           "hipMemcpy2DAsync");
-    int32_t variant = 0, tw = 0, th = 0;
+    int32_t variant = 0, tw = 0, th = 0, group = 0;
     const OblEntry* e = nullptr;
-    rc = resolve(dtype, k, opt, &variant, &tw, &th, &e);
+    rc = resolve(dtype, k, opt, &variant, &tw, &th, &e, &group);
     if (rc) return rc;
     if (variant == MF_VARIANT_OBLIVIOUS) {
         mf_launch_fn fn = (dtype == MF_U8 || dtype == MF_U16) ? e->p16 : e->u32;
         return hip_status(fn(src, dst, (int)H, (int)W, pitch_bytes, dtype, st), "oblivious kernel launch");
     }
-    return hip_status(mf_da_launch(src, dst, (int)H, (int)W, pitch_bytes, dtype, k, tw, th, st),
+    return hip_status(mf_da_launch(src, dst, (int)H, (int)W, pitch_bytes, dtype, k, tw, th, group, st),
                       "data-aware kernel launch");
 }
 
@@ -256,6 +260,39 @@ int32_t median_filter_bwd_gather(const float* grad_out, const int32_t* idx, floa
         return fail(MF_ERR_ALIAS, "grad_in overlaps an input");
     return hip_status(mf_ag_grad_launch(grad_out, idx, grad_in, planes, (int)H, (int)W, k, (hipStream_t)stream),
                       "gradient gather kernel launch");
+}
+
+int32_t mf_list_configs(int32_t dtype, int32_t k, mf_options* out, int32_t cap)
+{
+    g_last_error.clear();
+    if (!elem_size(dtype)) return fail(MF_ERR_DTYPE, "unknown dtype %d", dtype);
+    if (k < 1 || k % 2 == 0 || k > kMaxK) return fail(MF_ERR_K, "k=%d must be odd in [1, %d]", k, kMaxK);
+    if (cap > 0 && !out) return fail(MF_ERR_NULL, "output array is NULL");
+    int n = 0;
+    if (k > 1) {
+        for (int i = 0; i < kOblCount; ++i) {
+            if (kOblTable[i].k != k) continue;
+            if (n < cap) {
+                out[n].variant = MF_VARIANT_OBLIVIOUS;
+                out[n].tile_w = kOblTable[i].tw;
+                out[n].tile_h = kOblTable[i].th;
+                out[n].group = 0;
+            }
+            ++n;
+        }
+        int tw[32], th[32], gr[32];
+        const int m = mf_da_list(dtype, k, tw, th, gr, 32);
+        for (int i = 0; i < m && i < 32; ++i) {
+            if (n < cap) {
+                out[n].variant = MF_VARIANT_DATA_AWARE;
+                out[n].tile_w = tw[i];
+                out[n].tile_h = th[i];
+                out[n].group = gr[i];
+            }
+            ++n;
+        }
+    }
+    return n;
 }
 
 int32_t mf_max_k(void) { return kMaxK; }

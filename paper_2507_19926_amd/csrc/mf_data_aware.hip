@@ -24,13 +24,13 @@
 namespace {
 
 struct DaEntry {
-    int k, es, tw, th, c_off, nchunks, r_off, nrounds, o_off, arena;
+    int k, es, tw, th, tiles, c_off, nchunks, r_off, nrounds, o_off, arena;
 };
 
 const DaEntry kDaTable[] = {MF_DA_TABLE_ENTRIES};
 constexpr int kDaCount = sizeof(kDaTable) / sizeof(kDaTable[0]);
 
-constexpr int kDaThreads = 512;
+constexpr int kDaThreads = 256;
 
 }  // namespace
 
@@ -48,26 +48,36 @@ __device__ __forceinline__ uint32_t mf_da_key_to_f32(uint32_t k)
     return k ^ ((uint32_t)((int32_t)~k >> 31) | 0x80000000u);
 }
 
-// Root tile (bx, by) of one image, schedule `a`.
-template <class E>
+template <class E> struct MfDaSent;
+template <> struct MfDaSent<uint16_t> { static constexpr uint16_t v = 0xFFFF; };
+template <> struct MfDaSent<uint32_t> { static constexpr uint32_t v = 0xFFFFFFFFu; };
+
+template <class E> __device__ __forceinline__ E mf_da_min(E a, E b) { return a < b ? a : b; }
+template <class E> __device__ __forceinline__ E mf_da_max(E a, E b) { return a < b ? b : a; }
+
+// T root tiles (bx*T + t, by) of one image, schedule `a`. LDS holds T arenas of
+// `arena` elements each; a lane executes each of its chunks for all T tiles
+// side by side, so the T co-rank searches and loads are independent and their
+// latencies overlap.
+template <class E, int T>
 __device__ __forceinline__ void
 mf_da_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, int H, int W,
             long long pitch, int dtype, const MfDaArgs& a, int bx, int by)
 {
     extern __shared__ __align__(16) unsigned char mf_da_lds[];
     E* lds = reinterpret_cast<E*>(mf_da_lds);
-    const int k = a.k, tw = a.tw, th = a.th;
+    const int k = a.k, tw = a.tw, th = a.th, arena = a.arena;
     const uint32_t* __restrict__ blob = a.blob;
-    const int c_off = a.c_off, r_off = a.r_off, nrounds = a.nrounds, o_off = a.o_off;
-    const int X0 = bx * tw, Y0 = by * th;
     const int r = (k - 1) / 2;
     const int fw = k + tw - 1, fh = k + th - 1;
+    const int Y0 = by * th;
 
-    // footprint -> LDS, row-major fw x fh (replicate border by clamping)
-    for (int i = threadIdx.x; i < fw * fh; i += kDaThreads) {
-        const int y = i / fw, x = i - y * fw;
+    // footprints -> LDS, row-major fw x fh per tile (replicate border)
+    for (int i = threadIdx.x; i < T * fw * fh; i += kDaThreads) {
+        const int t = i / (fw * fh), e = i - t * fw * fh;
+        const int y = e / fw, x = e - y * fw;
         const int gy = min(max(Y0 - r + y, 0), H - 1);
-        const int gx = min(max(X0 - r + x, 0), W - 1);
+        const int gx = min(max((bx * T + t) * tw - r + x, 0), W - 1);
         const unsigned char* row = src + (long long)gy * pitch;
         uint32_t v;
         if (dtype == MF_U8) v = row[gx];
@@ -76,72 +86,108 @@ mf_da_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
             v = ((const uint32_t*)row)[gx];
             if (dtype == MF_F32) v = mf_da_f32_to_key(v);
         }
-        lds[i] = (E)v;
+        lds[t * arena + e] = (E)v;
     }
     __syncthreads();
 
-    const uint4* chunks = reinterpret_cast<const uint4*>(blob + c_off);
-    const uint32_t* rounds = blob + r_off;
+    const uint4* __restrict__ chunks = reinterpret_cast<const uint4*>(blob + a.c_off);
+    const uint32_t* __restrict__ rounds = blob + a.r_off;
     constexpr uint32_t kMask = (1u << 18) - 1;
-    for (int rd = 0; rd < nrounds; ++rd) {
+    constexpr int CH = MF_DA_CHUNK;
+    for (int rd = 0; rd < a.nrounds; ++rd) {
         const int c1 = (int)rounds[rd + 1];
-        for (int c = (int)rounds[rd] + threadIdx.x; c < c1; c += kDaThreads) {
-            const uint4 d = chunks[c];
-            const E* A = lds + (d.x & kMask);
-            const E* B = lds + (d.y & kMask);
-            E* O = lds + (d.z & kMask);
+        int c = (int)rounds[rd] + threadIdx.x;
+        uint4 d = c < c1 ? chunks[c] : make_uint4(0, 0, 0, 0);
+        while (c < c1) {
+            const int cn = c + kDaThreads;
+            const uint4 dn = cn < c1 ? chunks[cn] : make_uint4(0, 0, 0, 0);   // prefetch
+            const int ao = (int)(d.x & kMask), bo = (int)(d.y & kMask), oo = (int)(d.z & kMask);
             const int na = (int)(d.x >> 18), nb = (int)(d.y >> 18), n = (int)(d.z >> 18);
             const int r0 = (int)d.w;
-            // co-rank: number of A elements among the first r0 merged outputs
-            // (A first on ties)
-            int lo = max(0, r0 - nb), hi = min(r0, na);
-            while (lo < hi) {
-                const int i = (lo + hi) >> 1;
-                if (A[i] <= B[r0 - i - 1]) lo = i + 1;
-                else hi = i;
+            // co-rank: number of A elements among the first r0 outputs (A first
+            // on ties); the same bounds for every tile, so one trip count
+            int lo[T], hi[T];
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                lo[t] = max(0, r0 - nb);
+                hi[t] = min(r0, na);
             }
-            int i = lo, j = r0 - lo;
-            E a = 0, b = 0;
-            if (i < na) a = A[i];
-            if (j < nb) b = B[j];
-            for (int t = 0; t < n; ++t) {
-                const bool takeA = (i < na) && (j >= nb || a <= b);
-                O[t] = takeA ? a : b;
-                if (takeA) {
-                    ++i;
-                    if (i < na) a = A[i];
-                } else {
-                    ++j;
-                    if (j < nb) b = B[j];
+            for (bool any = true; any;) {
+                any = false;
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    if (lo[t] < hi[t]) {
+                        const E* A = lds + t * arena + ao;
+                        const E* B = lds + t * arena + bo;
+                        const int i = (lo[t] + hi[t]) >> 1;
+                        if (A[i] <= B[r0 - i - 1]) lo[t] = i + 1;
+                        else hi[t] = i;
+                    }
+                    any |= lo[t] < hi[t];
                 }
             }
+            // the next n outputs are the n smallest of A[i..i+CH) and B[j..j+CH):
+            // bitonic selection of the lowest CH, then a bitonic sort
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                const E* A = lds + t * arena + ao;
+                const E* B = lds + t * arena + bo;
+                const int i = lo[t], j = r0 - lo[t];
+                E va[CH], vb[CH];
+#pragma unroll
+                for (int q = 0; q < CH; ++q) {
+                    va[q] = (i + q < na) ? A[i + q] : MfDaSent<E>::v;
+                    vb[q] = (j + q < nb) ? B[j + q] : MfDaSent<E>::v;
+                }
+#pragma unroll
+                for (int q = 0; q < CH; ++q) va[q] = mf_da_min(va[q], vb[CH - 1 - q]);
+#pragma unroll
+                for (int step = CH / 2; step >= 1; step >>= 1) {
+#pragma unroll
+                    for (int q = 0; q < CH; ++q) {
+                        if ((q & step) == 0) {
+                            const E x = va[q], y = va[q + step];
+                            va[q] = mf_da_min(x, y);
+                            va[q + step] = mf_da_max(x, y);
+                        }
+                    }
+                }
+                E* O = lds + t * arena + oo;
+#pragma unroll
+                for (int q = 0; q < CH; ++q)
+                    if (q < n) O[q] = va[q];
+            }
+            d = dn;
+            c = cn;
         }
         __syncthreads();
     }
 
-    const uint32_t* outs = blob + o_off;
-    for (int p = threadIdx.x; p < tw * th; p += kDaThreads) {
-        const int y = Y0 + p / tw, x = X0 + p % tw;
+    const uint32_t* outs = blob + a.o_off;
+    for (int p = threadIdx.x; p < T * tw * th; p += kDaThreads) {
+        const int t = p / (tw * th), e = p - t * tw * th;
+        const int y = Y0 + e / tw, x = (bx * T + t) * tw + e % tw;
         if (y >= H || x >= W) continue;
         unsigned char* row = dst + (long long)y * pitch;
-        const uint32_t v = (uint32_t)lds[outs[p]];
+        const uint32_t v = (uint32_t)lds[t * arena + outs[e]];
         if (dtype == MF_U8) row[x] = (unsigned char)v;
         else if (dtype == MF_U16) ((uint16_t*)row)[x] = (uint16_t)v;
         else ((uint32_t*)row)[x] = (dtype == MF_F32) ? mf_da_key_to_f32(v) : v;
     }
 }
 
-template <class E>
+template <class E, int T>
 __global__ void __launch_bounds__(kDaThreads)
 mf_da_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, int H, int W,
              long long pitch, int dtype, MfDaArgs a, int ntx)
 {
-    mf_da_block<E>(src, dst, H, W, pitch, dtype, a, blockIdx.x % ntx, blockIdx.x / ntx);
+    mf_da_block<E, T>(src, dst, H, W, pitch, dtype, a, blockIdx.x % ntx, blockIdx.x / ntx);
 }
 
-// Batched form: blocks of every image of a job table (same k, tile and
-// element size), image found by binary search over first block indices.
-template <class E>
+// Batched form: blocks of every image of a job table (same k, tile, tiles per
+// work-group and element size), image found by binary search over first
+// block indices.
+template <class E, int T>
 __global__ void __launch_bounds__(kDaThreads)
 mf_da_kernel_batched(const MfJob* __restrict__ jobs, int njobs, MfDaArgs a)
 {
@@ -154,17 +200,39 @@ mf_da_kernel_batched(const MfJob* __restrict__ jobs, int njobs, MfDaArgs a)
     }
     const MfJob j = jobs[lo];
     const int lb = b - j.block_begin;
-    mf_da_block<E>(j.src, j.dst, j.H, j.W, j.pitch, j.dtype, a, lb % j.nbx, lb / j.nbx);
+    mf_da_block<E, T>(j.src, j.dst, j.H, j.W, j.pitch, j.dtype, a, lb % j.nbx, lb / j.nbx);
 }
 
 namespace {
 
-const DaEntry* da_find(int dtype, int k, int tw, int th)
+// kernel pointers by (element size, tiles per work-group)
+template <class E>
+const void* da_kernel(int T, bool batched)
+{
+    switch (T) {
+    case 1: return batched ? (const void*)mf_da_kernel_batched<E, 1> : (const void*)mf_da_kernel<E, 1>;
+    case 2: return batched ? (const void*)mf_da_kernel_batched<E, 2> : (const void*)mf_da_kernel<E, 2>;
+    default: return batched ? (const void*)mf_da_kernel_batched<E, 4> : (const void*)mf_da_kernel<E, 4>;
+    }
+}
+
+const void* da_kernel_for(const DaEntry* e, bool batched)
+{
+    return e->es == 2 ? da_kernel<uint16_t>(e->tiles, batched) : da_kernel<uint32_t>(e->tiles, batched);
+}
+
+}  // namespace
+
+namespace {
+
+const DaEntry* da_find(int dtype, int k, int tw, int th, int group)
 {
     const int es = (dtype == MF_U8 || dtype == MF_U16) ? 2 : 4;
     for (int i = 0; i < kDaCount; ++i) {
         const DaEntry& e = kDaTable[i];
-        if (e.k == k && e.es == es && (tw == 0 || e.tw == tw) && (th == 0 || e.th == th)) return &e;
+        if (e.k == k && e.es == es && (tw == 0 || e.tw == tw) && (th == 0 || e.th == th) &&
+            (group == 0 || e.tiles == group))
+            return &e;
     }
     return nullptr;
 }
@@ -187,18 +255,13 @@ hipError_t da_blob(const uint32_t** out)
         void* p = nullptr;
         e = hipGetSymbolAddress(&p, HIP_SYMBOL(mf_da_blob));
         if (e != hipSuccess) return e;
-        e = hipFuncSetAttribute((const void*)mf_da_kernel<uint16_t>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        e = hipFuncSetAttribute((const void*)mf_da_kernel<uint32_t>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        e = hipFuncSetAttribute((const void*)mf_da_kernel_batched<uint16_t>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        e = hipFuncSetAttribute((const void*)mf_da_kernel_batched<uint32_t>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
+        for (int es = 2; es <= 4; es += 2)
+            for (int T = 1; T <= 4; T *= 2)
+                for (int bt = 0; bt < 2; ++bt) {
+                    const void* fn = es == 2 ? da_kernel<uint16_t>(T, bt) : da_kernel<uint32_t>(T, bt);
+                    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                    if (e != hipSuccess) return e;
+                }
         g_da_blob_dev[dev] = (const uint32_t*)p;
     }
     *out = g_da_blob_dev[dev];
@@ -207,13 +270,34 @@ hipError_t da_blob(const uint32_t** out)
 
 }  // namespace
 
-bool mf_da_supports(int dtype, int k, int tw, int th) { return da_find(dtype, k, tw, th) != nullptr; }
-
-void mf_da_default_tile(int dtype, int k, int* tw, int* th)
+bool mf_da_supports(int dtype, int k, int tw, int th, int group)
 {
-    const DaEntry* e = da_find(dtype, k, 0, 0);
+    return da_find(dtype, k, tw, th, group) != nullptr;
+}
+
+void mf_da_default_tile(int dtype, int k, int* tw, int* th, int* group)
+{
+    const DaEntry* e = da_find(dtype, k, 0, 0, 0);
     *tw = e ? e->tw : 0;
     *th = e ? e->th : 0;
+    *group = e ? e->tiles : 0;
+}
+
+int mf_da_list(int dtype, int k, int* tw, int* th, int* group, int cap)
+{
+    const int es = (dtype == MF_U8 || dtype == MF_U16) ? 2 : 4;
+    int n = 0;
+    for (int i = 0; i < kDaCount; ++i) {
+        const DaEntry& e = kDaTable[i];
+        if (e.k != k || e.es != es) continue;
+        if (n < cap) {
+            tw[n] = e.tw;
+            th[n] = e.th;
+            group[n] = e.tiles;
+        }
+        ++n;
+    }
+    return n;
 }
 
 static MfDaArgs da_args(const DaEntry* e, const uint32_t* blob)
@@ -227,41 +311,39 @@ static MfDaArgs da_args(const DaEntry* e, const uint32_t* blob)
     a.r_off = e->r_off;
     a.nrounds = e->nrounds;
     a.o_off = e->o_off;
+    a.arena = e->arena;
     return a;
 }
 
 hipError_t mf_da_launch(const void* src, void* dst, int H, int W, long long pitch, int dtype, int k,
-                        int tw, int th, hipStream_t stream)
+                        int tw, int th, int group, hipStream_t stream)
 {
-    const DaEntry* e = da_find(dtype, k, tw, th);
+    const DaEntry* e = da_find(dtype, k, tw, th, group);
     if (!e) return hipErrorInvalidValue;
     const uint32_t* blob = nullptr;
     hipError_t err = da_blob(&blob);
     if (err != hipSuccess) return err;
-    const MfDaArgs a = da_args(e, blob);
-    const int ntx = (W + e->tw - 1) / e->tw, nty = (H + e->th - 1) / e->th;
-    const size_t lds = (size_t)e->arena * e->es;
-    if (e->es == 2)
-        hipLaunchKernelGGL(mf_da_kernel<uint16_t>, dim3(ntx * nty), dim3(kDaThreads), lds, stream,
-                           (const unsigned char*)src, (unsigned char*)dst, H, W, pitch, dtype, a, ntx);
-    else
-        hipLaunchKernelGGL(mf_da_kernel<uint32_t>, dim3(ntx * nty), dim3(kDaThreads), lds, stream,
-                           (const unsigned char*)src, (unsigned char*)dst, H, W, pitch, dtype, a, ntx);
-    return hipGetLastError();
+    MfDaArgs a = da_args(e, blob);
+    const int ntx = (W + e->tw * e->tiles - 1) / (e->tw * e->tiles), nty = (H + e->th - 1) / e->th;
+    const size_t lds = (size_t)e->arena * e->es * e->tiles;
+    const unsigned char* s8 = (const unsigned char*)src;
+    unsigned char* d8 = (unsigned char*)dst;
+    void* args[] = {&s8, &d8, &H, &W, &pitch, &dtype, &a, (void*)&ntx};
+    return hipLaunchKernel(da_kernel_for(e, false), dim3(ntx * nty), dim3(kDaThreads), args, lds, stream);
 }
 
-hipError_t mf_da_batched(int dtype, int k, int tw, int th, MfBatchedKernel* kern, MfDaArgs* args)
+hipError_t mf_da_batched(int dtype, int k, int tw, int th, int group, MfBatchedKernel* kern, MfDaArgs* args)
 {
-    const DaEntry* e = da_find(dtype, k, tw, th);
+    const DaEntry* e = da_find(dtype, k, tw, th, group);
     if (!e) return hipErrorInvalidValue;
     const uint32_t* blob = nullptr;
     hipError_t err = da_blob(&blob);
     if (err != hipSuccess) return err;
     *args = da_args(e, blob);
-    kern->fn = e->es == 2 ? (const void*)mf_da_kernel_batched<uint16_t> : (const void*)mf_da_kernel_batched<uint32_t>;
+    kern->fn = da_kernel_for(e, true);
     kern->threads = kDaThreads;
-    kern->lds = (size_t)e->arena * e->es;
-    kern->bw = e->tw;
+    kern->lds = (size_t)e->arena * e->es * e->tiles;
+    kern->bw = e->tw * e->tiles;
     kern->bh = e->th;
     return hipSuccess;
 }

@@ -45,16 +45,19 @@ struct MfBatchedKernel {
 
 // Data-aware launcher: one per value class, any k up to mf_max_k().
 hipError_t mf_da_launch(const void* src, void* dst, int H, int W, long long pitch,
-                        int dtype, int k, int tw, int th, hipStream_t stream);
-bool mf_da_supports(int dtype, int k, int tw, int th);
-void mf_da_default_tile(int dtype, int k, int* tw, int* th);
+                        int dtype, int k, int tw, int th, int group, hipStream_t stream);
+bool mf_da_supports(int dtype, int k, int tw, int th, int group);
+void mf_da_default_tile(int dtype, int k, int* tw, int* th, int* group);
+// Data-aware entries for (dtype, k): fills up to cap (tw, th, group) triples,
+// returns the count.
+int mf_da_list(int dtype, int k, int* tw, int* th, int* group, int cap);
 // Batched data-aware kernel for (dtype class, k, tile); the blob pointer and
 // schedule offsets are filled into *args (see mf_da_batched_args).
 struct MfDaArgs {
     const uint32_t* blob;
-    int k, tw, th, c_off, r_off, nrounds, o_off;
+    int k, tw, th, c_off, r_off, nrounds, o_off, arena;
 };
-hipError_t mf_da_batched(int dtype, int k, int tw, int th, MfBatchedKernel* kern, MfDaArgs* args);
+hipError_t mf_da_batched(int dtype, int k, int tw, int th, int group, MfBatchedKernel* kern, MfDaArgs* args);
 
 // Differentiable form (mf_autograd.hip).
 hipError_t mf_ag_argmedian_launch(const float* src, const float* med, int32_t* idx, int64_t planes, int H,

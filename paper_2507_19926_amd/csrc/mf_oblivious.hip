@@ -51,28 +51,100 @@ template <> struct MfVTraits<uint32_t> { static constexpr bool PACK = false; };
 
 __device__ __forceinline__ int mf_clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
-// One work-group's block (bx, by) of one image.
-template <class NET, class V, int RY>
+// Footprint union of one block -> LDS raw buffer (swizzled layout).
+//
+// Rows are clamped per row (replicate border in y). Blocks whose columns stay
+// inside the image with a few bytes to spare take the fast path: every lane
+// first issues all of its aligned dword loads (no dependency between them, so
+// their latencies overlap), then unpacks them into LDS. Blocks touching the
+// left or right edge clamp element by element.
+template <class V, int K, int TW, int TH, int RY>
 __device__ __forceinline__ void
-mf_obl_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
-             int H, int W, long long pitch, int dtype, int bx, int by)
+mf_obl_load(const unsigned char* __restrict__ src, int H, int W, long long pitch, int dtype,
+            int X0, int Y0, V* __restrict__ raw)
 {
     constexpr bool PACK = MfVTraits<V>::PACK;
-    constexpr int K = NET::K, TW = NET::TW, TH = NET::TH, LC = NET::LC;
     constexpr int R = (K - 1) / 2;
-    constexpr int TX = 64;
     constexpr int TY = 4 * RY;
-    constexpr int BWH = TX * TW;            // block width of one packed half
-    constexpr int COLS = BWH + K - 1;       // footprint-union columns
-    constexpr int ROWS = TY * TH + K - 1;   // footprint-union rows
+    constexpr int BWH = 64 * TW;
+    constexpr int COLS = BWH + K - 1;
+    constexpr int ROWS = TY * TH + K - 1;
     constexpr int Q = (COLS + TW - 1) / TW;
-    __shared__ V raw[ROWS * TW * Q];
-    __shared__ V colb[TY * LC * TW * Q];
-
-    const int X0 = bx * (PACK ? 2 * BWH : BWH);
-    const int Y0 = by * (TY * TH);
-
-    // 1. footprint union -> LDS (clamped coordinates = replicate border)
+    const int es = PACK ? (dtype == MF_U8 ? 1 : 2) : 4;
+    // bytes of one half-row segment, rounded out to aligned dwords
+    const int seg_bytes = COLS * es;
+    const int gx0 = X0 - R;                               // first column of half A
+    const int span = PACK ? (BWH + COLS) : COLS;           // columns touched by the block
+    const bool fast = gx0 >= 4 && gx0 + span + 8 <= W;
+    if (fast) {
+        // a segment of seg_bytes starting `lead` (< 4) bytes into an aligned
+        // dword needs ceil((lead + seg_bytes) / 4) <= (seg_bytes + 6) / 4 dwords;
+        // they end at most 6 bytes past the segment, inside the row because
+        // of the 8-element margin of the fast-path test
+        constexpr int NDMAX = (COLS * (PACK ? 2 : 4) + 6) / 4;
+        constexpr int ITEMS = ROWS * NDMAX;
+        constexpr int U = (ITEMS + 255) / 256;
+        const int nd = (seg_bytes + 6) / 4;               // dwords per segment (<= NDMAX)
+        uint32_t va[U], vb[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int it = threadIdx.x + u * 256;
+            va[u] = vb[u] = 0;
+            if (it < ROWS * nd) {
+                const int rho = it / nd, d = it - rho * nd;
+                const int gy = mf_clampi(Y0 - R + rho, 0, H - 1);
+                const uintptr_t a = (uintptr_t)(src + (long long)gy * pitch + (long long)gx0 * es);
+                const uint32_t* p = (const uint32_t*)((a & ~(uintptr_t)3) + 4 * (uintptr_t)d);
+                va[u] = p[0];
+                if constexpr (PACK) vb[u] = p[BWH * es / 4];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int it = threadIdx.x + u * 256;
+            if (it < ROWS * nd) {
+                const int rho = it / nd, d = it - rho * nd;
+                const int gy = mf_clampi(Y0 - R + rho, 0, H - 1);
+                const uintptr_t a = (uintptr_t)(src + (long long)gy * pitch + (long long)gx0 * es);
+                const int lead = (int)(a & 3);            // bytes before the segment start
+                const int b0 = 4 * d - lead;              // segment byte of this dword's byte 0
+                V* rrow = raw + rho * TW * Q;
+                if constexpr (PACK) {
+                    if (es == 1) {
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) {
+                            const int c = b0 + b;
+                            if (c >= 0 && c < COLS) {
+                                V v;
+                                v.x = (va[u] >> (8 * b)) & 0xFF;
+                                v.y = (vb[u] >> (8 * b)) & 0xFF;
+                                rrow[(c % TW) * Q + c / TW] = v;
+                            }
+                        }
+                    } else {
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const int c = (b0 >> 1) + h;  // b0 is even for 16-bit data
+                            if (c >= 0 && c < COLS) {
+                                V v;
+                                v.x = (va[u] >> (16 * h)) & 0xFFFF;
+                                v.y = (vb[u] >> (16 * h)) & 0xFFFF;
+                                rrow[(c % TW) * Q + c / TW] = v;
+                            }
+                        }
+                    }
+                } else {
+                    const int c = b0 >> 2;                // 32-bit data is always aligned
+                    if (c >= 0 && c < COLS) {
+                        uint32_t b = va[u];
+                        if (dtype == MF_F32) b = mf_f32_to_key(b);
+                        rrow[(c % TW) * Q + c / TW] = b;
+                    }
+                }
+            }
+        }
+        return;
+    }
     for (int w = threadIdx.x; w < ROWS * COLS; w += 256) {
         const int rho = w / COLS, c = w - rho * COLS;
         const int gy = mf_clampi(Y0 - R + rho, 0, H - 1);
@@ -95,6 +167,31 @@ mf_obl_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ 
         }
         raw[(rho * TW + c % TW) * Q + c / TW] = v;
     }
+}
+
+// One work-group's block (bx, by) of one image.
+template <class NET, class V, int RY>
+__device__ __forceinline__ void
+mf_obl_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
+             int H, int W, long long pitch, int dtype, int bx, int by)
+{
+    constexpr bool PACK = MfVTraits<V>::PACK;
+    constexpr int K = NET::K, TW = NET::TW, TH = NET::TH, LC = NET::LC;
+    constexpr int R = (K - 1) / 2;
+    constexpr int TX = 64;
+    constexpr int TY = 4 * RY;
+    constexpr int BWH = TX * TW;            // block width of one packed half
+    constexpr int COLS = BWH + K - 1;       // footprint-union columns
+    constexpr int ROWS = TY * TH + K - 1;   // footprint-union rows
+    constexpr int Q = (COLS + TW - 1) / TW;
+    __shared__ V raw[ROWS * TW * Q];
+    __shared__ V colb[TY * LC * TW * Q];
+
+    const int X0 = bx * (PACK ? 2 * BWH : BWH);
+    const int Y0 = by * (TY * TH);
+
+    // 1. footprint union -> LDS (clamped coordinates = replicate border)
+    mf_obl_load<V, K, TW, TH, RY>(src, H, W, pitch, dtype, X0, Y0, raw);
     __syncthreads();
 
     // 2. sorted column segments over each tile row's core rows

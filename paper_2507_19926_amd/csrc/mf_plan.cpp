@@ -26,12 +26,12 @@ int32_t mf_internal_validate(const void* src, const void* dst, int64_t H, int64_
                              int32_t dtype, int32_t k, int32_t border);
 int32_t mf_internal_fail(int32_t code, const char* msg);
 int32_t mf_internal_resolve(int32_t dtype, int32_t k, int32_t* variant, int32_t* tw, int32_t* th,
-                            MfBatchedKernel* obl_p16, MfBatchedKernel* obl_u32);
+                            int32_t* group, MfBatchedKernel* obl_p16, MfBatchedKernel* obl_u32);
 
 namespace {
 
 struct Bucket {
-    int variant, k, tw, th, packed;
+    int variant, k, tw, th, group, packed;
     MfBatchedKernel kern;
     MfDaArgs da;
     std::vector<int> images;
@@ -155,15 +155,15 @@ int32_t mf_plan_create(const mf_image* imgs, int32_t n, mf_plan* out)
     std::map<std::tuple<int, int, int, int, int>, int> index;
     for (int i = 0; i < n; ++i) {
         const mf_image& m = imgs[i];
-        int32_t variant = 0, tw = 0, th = 0;
+        int32_t variant = 0, tw = 0, th = 0, group = 0;
         MfBatchedKernel kp16 = {}, ku32 = {};
-        rc = mf_internal_resolve(m.dtype, m.k, &variant, &tw, &th, &kp16, &ku32);
+        rc = mf_internal_resolve(m.dtype, m.k, &variant, &tw, &th, &group, &kp16, &ku32);
         if (rc) {
             plan_free(p);
             return rc;
         }
         const int packed = (m.dtype == MF_U8 || m.dtype == MF_U16) ? 1 : 0;
-        auto key = std::make_tuple(variant, m.k, tw, th, packed);
+        auto key = std::make_tuple(variant, m.k, tw * 8 + group, th, packed);
         auto it = index.find(key);
         if (it == index.end()) {
             Bucket b;
@@ -171,12 +171,13 @@ int32_t mf_plan_create(const mf_image* imgs, int32_t n, mf_plan* out)
             b.k = m.k;
             b.tw = tw;
             b.th = th;
+            b.group = group;
             b.packed = packed;
             memset(&b.da, 0, sizeof b.da);
             if (variant == MF_VARIANT_OBLIVIOUS) {
                 b.kern = packed ? kp16 : ku32;
             } else {
-                e = mf_da_batched(m.dtype, m.k, tw, th, &b.kern, &b.da);
+                e = mf_da_batched(m.dtype, m.k, tw, th, group, &b.kern, &b.da);
                 if (e != hipSuccess) {
                     plan_free(p);
                     return hip_fail(e, "data-aware batched kernel");

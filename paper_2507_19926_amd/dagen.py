@@ -39,7 +39,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-CHUNK = 16          # outputs per merge-path chunk
+CHUNK = 8           # outputs per merge-path chunk (the kernel's register network width)
 OFF_BITS = 18       # arena offsets and sizes share a 32-bit word
 MAX_OFF = 1 << OFF_BITS
 MAX_LEN = 1 << (32 - OFF_BITS)
@@ -58,6 +58,7 @@ class Node:
     consumers: list = field(default_factory=list)
     off: int = -1
     rnd: int = -1
+    role: str = ""
 
 
 class Dag:
@@ -65,6 +66,7 @@ class Dag:
         self.nodes: list[Node] = []
         self.fw = fw
         self.phase = 0
+        self.role = ""
         self._raw = {}
 
     def raw(self, x: int, y: int) -> tuple:
@@ -81,7 +83,8 @@ class Dag:
             return B
         if B[2] - B[1] == 0:
             return A
-        n = Node(len(self.nodes), (A[2] - A[1]) + (B[2] - B[1]), a=A, b=B, phase=self.phase)
+        n = Node(len(self.nodes), (A[2] - A[1]) + (B[2] - B[1]), a=A, b=B, phase=self.phase,
+                 role=self.role)
         self.nodes.append(n)
         return (n, 0, n.size)
 
@@ -122,13 +125,17 @@ def build_dag(k: int, tw: int, th: int):
     core_x = range(tw - 1, k)
 
     def col(x, ys):
+        D.role = "sort_col"
         return D.sort([D.raw(x, y) for y in ys])
 
     def row(y, xs):
+        D.role = "sort_row"
         return D.sort([D.raw(x, y) for x in xs])
 
     D.phase = 0
-    core = D.reduce([col(x, core_y) for x in core_x])
+    cols = [col(x, core_y) for x in core_x]
+    D.role = "core_init"
+    core = D.reduce(cols)
     core = trim(core, N - len(core_x) * len(core_y))
     xcols = {x: col(x, core_y) for x in list(range(0, tw - 1)) + list(range(k, k + tw - 1))}
     xrows = {y: row(y, core_x) for y in list(range(0, th - 1)) + list(range(k, k + th - 1))}
@@ -145,19 +152,35 @@ def build_dag(k: int, tw: int, th: int):
             hh = w // 2
             for cox, added in ((ox, range(ox + hh - 1, ox + w - 1)), (ox + hh, range(ox + k, ox + k + hh))):
                 D.phase = level + 1
-                c = D.merge(core, D.reduce([xcols[x] for x in added]))
+                D.role = "core_extra"
+                e = D.reduce([xcols[x] for x in added])
+                D.role = "core_merge"
+                c = D.merge(core, e)
                 c = trim(c, N - (k - hh + 1) * (k - h + 1))
                 ncols = {x: xcols[x] for x in list(range(cox, cox + hh - 1)) + list(range(cox + k, cox + k + hh - 1))}
-                nrows = {y: D.merge(r, D.sort([D.raw(x, y) for x in added])) for y, r in xrows.items()}
+                nrows = {}
+                for y, r in xrows.items():
+                    D.role = "sort_corner"
+                    cs = D.sort([D.raw(x, y) for x in added])
+                    D.role = "extend"
+                    nrows[y] = D.merge(r, cs)
                 children.append((cox, oy, hh, h, c, ncols, nrows))
         else:
             hh = h // 2
             for coy, added in ((oy, range(oy + hh - 1, oy + h - 1)), (oy + hh, range(oy + k, oy + k + hh))):
                 D.phase = level + 1
-                c = D.merge(core, D.reduce([xrows[y] for y in added]))
+                D.role = "core_extra"
+                e = D.reduce([xrows[y] for y in added])
+                D.role = "core_merge"
+                c = D.merge(core, e)
                 c = trim(c, N - (k - w + 1) * (k - hh + 1))
                 nrows = {y: xrows[y] for y in list(range(coy, coy + hh - 1)) + list(range(coy + k, coy + k + hh - 1))}
-                ncols = {x: D.merge(cl, D.sort([D.raw(x, y) for y in added])) for x, cl in xcols.items()}
+                ncols = {}
+                for x, cl in xcols.items():
+                    D.role = "sort_corner"
+                    cs = D.sort([D.raw(x, y) for y in added])
+                    D.role = "extend"
+                    ncols[x] = D.merge(cl, cs)
                 children.append((ox, coy, w, hh, c, ncols, nrows))
         for ch in children:
             recurse(*ch, level + 1)
@@ -324,7 +347,11 @@ def schedule(k: int, tw: int, th: int, chunk: int = CHUNK) -> Schedule:
             outputs.append(off + (lo - n.need_lo))
     assert all(0 <= o < peak for o in outputs)
     merge_outputs = sum(n.need_hi - n.need_lo for n in merges)
+    by_role = {}
+    for n in merges:
+        by_role[n.role] = by_role.get(n.role, 0) + (n.need_hi - n.need_lo)
     st = {"rounds": len(order), "chunks": len(chunks), "merge_outputs": merge_outputs,
+          "per_pixel_by_role": {r: round(v / (tw * th), 1) for r, v in sorted(by_role.items())},
           "per_pixel_outputs": merge_outputs / (tw * th), "arena": peak,
           "merges": len(merges)}
     return Schedule(k, tw, th, fw, fh, np.array(chunks, dtype=np.uint32).reshape(-1, 4),
@@ -391,3 +418,29 @@ def _merge_path_chunk(A, B, r0, n):
         else:
             out.append(B[j]); j += 1
     return out
+
+
+def register_merge_chunk(A, B, r0, n, width=CHUNK, sentinel=0xFFFF):
+    """The kernel's chunk procedure: co-rank search, then the n smallest of
+    A[i..i+width) and B[j..j+width) (missing positions padded with the
+    largest value) by a bitonic selection and a bitonic sort."""
+    na, nb = len(A), len(B)
+    lo, hi = max(0, r0 - nb), min(r0, na)
+    while lo < hi:
+        i = (lo + hi) // 2
+        if A[i] <= B[r0 - i - 1]:
+            lo = i + 1
+        else:
+            hi = i
+    i, j = lo, r0 - lo
+    va = [A[i + q] if i + q < na else sentinel for q in range(width)]
+    vb = [B[j + q] if j + q < nb else sentinel for q in range(width)]
+    va = [min(va[q], vb[width - 1 - q]) for q in range(width)]
+    step = width // 2
+    while step >= 1:
+        for q in range(width):
+            if q & step == 0:
+                x, y = va[q], va[q + step]
+                va[q], va[q + step] = min(x, y), max(x, y)
+        step //= 2
+    return va[:n]

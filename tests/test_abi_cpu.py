@@ -45,6 +45,7 @@ def _call(src=FAKE_SRC, dst=FAKE_DST, H=16, W=16, pitch=16, dtype=0, k=3, border
     (dict(H=0), -2), (dict(W=0), -2), (dict(H=-3), -2), (dict(W=2 ** 31), -2),
     (dict(pitch=15), -3), (dict(dtype=1, pitch=31), -3), (dict(dtype=2, pitch=62), -3),
     (dict(dtype=7), -4), (dict(dtype=-1), -4),
+    (dict(dtype=1, src=FAKE_SRC + 1, pitch=32), -3), (dict(dtype=3, dst=FAKE_DST + 2, pitch=64), -3),
     (dict(k=4), -5), (dict(k=0), -5), (dict(k=-3), -5), (dict(k=77), -5),
     (dict(border=1), -6),
     (dict(dst=FAKE_SRC + 100), -7), (dict(dst=FAKE_SRC - 255 + 16), -7), (dict(dst=FAKE_SRC), -7),
