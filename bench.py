@@ -29,6 +29,7 @@ METRIC = "Mpixel/s per k (uint8 30MP, k=3..75) + %roofline; batched vs per-image
 PAPER_L40S_MSAMPLE_S_K17 = 6720 * 4480 * 3 / 2.2e-3 / 1e6   # 2.2 ms teaser figure, context only
 
 HBM_PEAK_BPS = 8.0e12            # MI355X HBM3E, bytes/s
+LDS_PEAK_BPS = 256 * 128 * 2.4e9  # 128 B/clock/CU of LDS bandwidth x 256 CUs x 2.4 GHz = 78.6 TB/s
 VALU_LANES_PER_S = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock = 39.3e12 32-bit lane-ops/s
 
 
@@ -55,14 +56,15 @@ def algorithmic_ops_per_pixel(dtype_code: int, k: int):
     Oblivious: live min/max of the generated network per root tile / pixels,
     plus the column sort network (one sort of k-t_h+1 values per image column
     and tile row, i.e. per t_h pixels)."""
-    from paper_2507_19926_amd import _lib, netgen as ng
+    from paper_2507_19926_amd import _lib, dagen, netgen as ng
     variant, tw, th = _lib.query_config(dtype_code, k)
     if variant == _lib.MF_VARIANT_OBLIVIOUS:
         P = ng.build_tile_program(k, tw, th)
         net = ng.op_counts(P)["minmax"] / (tw * th)
         srt = ng.op_counts(ng.build_sort_program(k - th + 1))["minmax"] / th
         return variant, (tw, th), net + srt
-    return variant, (tw, th), None
+    # data-aware: merge outputs per pixel of the schedule
+    return variant, (tw, th), dagen.schedule(k, tw, th).stats["per_pixel_outputs"]
 
 
 def roofline(dtype_code: int, k: int, pixels_per_launch: int, launch_s: float):
@@ -70,6 +72,18 @@ def roofline(dtype_code: int, k: int, pixels_per_launch: int, launch_s: float):
     es = {0: 1, 1: 2, 2: 4, 3: 4}[dtype_code]
     bytes_per_launch = 2 * es * pixels_per_launch
     variant, tile, ops_px = algorithmic_ops_per_pixel(dtype_code, k)
+    if variant == _lib.MF_VARIANT_DATA_AWARE:
+        # each merge output is one LDS read and one LDS write of an element
+        # (2 bytes for 8/16-bit data, 4 for 32-bit)
+        lds_es = 2 if dtype_code in (0, 1) else 4
+        lds_bytes = ops_px * pixels_per_launch * 2 * lds_es
+        t_lds = lds_bytes / LDS_PEAK_BPS
+        t_hbm = bytes_per_launch / HBM_PEAK_BPS
+        if t_lds >= t_hbm:
+            achieved = lds_bytes / launch_s
+            return {"bound": "lds", "achieved": achieved / 1e9, "peak": LDS_PEAK_BPS / 1e9, "unit": "GB/s",
+                    "frac": achieved / LDS_PEAK_BPS, "traffic": None,
+                    "merge_outputs_per_pixel": round(ops_px, 2), "variant": variant, "tile": list(tile)}
     packed = dtype_code in (0, 1)
     valu_peak = VALU_LANES_PER_S * (2 if packed else 1)    # element-ops/s
     t_hbm = bytes_per_launch / HBM_PEAK_BPS

@@ -57,10 +57,32 @@ def _compile(src: str, obj: str, extra=()) -> tuple[str, str]:
     return obj, p.stderr
 
 
+def _write_auto_table() -> None:
+    """AUTO choices per (value class, k) from tuned.json (autotune.py), as
+    MF_AUTO(class, k, variant, tile_w, tile_h, group) lines; class 0 = 8/16-bit,
+    1 = 32-bit. Without tuned.json the table is empty and the library falls
+    back to its built-in order (oblivious first)."""
+    import json
+    lines = ["// Generated from tuned.json: measured fastest configuration per (class, k)."]
+    path = os.path.join(PKG, "tuned.json")
+    if os.path.exists(path):
+        with open(path) as f:
+            t = json.load(f)
+        for cls, code in (("p16", 0), ("u32", 1)):
+            for k, (variant, tw, th, group) in sorted(t.get(cls, {}).items(), key=lambda kv: int(kv[0])):
+                lines.append("MF_AUTO(%d, %d, %d, %d, %d, %d)" % (code, int(k), variant, tw, th, group))
+    text = "\n".join(lines) + "\n"
+    out = os.path.join(GEN, "mf_auto_table.inc")
+    if not os.path.exists(out) or open(out).read() != text:
+        with open(out, "w") as f:
+            f.write(text)
+
+
 def build(jobs: int | None = None, verbose: bool = False) -> str:
     """Generate, compile and link. Returns the path of libmedfilt.so."""
     os.makedirs(GEN, exist_ok=True)
     obl_srcs = emit_hip.generate(GEN, OBL_CONFIGS)
+    _write_auto_table()
     emit_da.generate(GEN)
     blob_cpp = os.path.join(GEN, "mf_da_blob.cpp")
     text = ("// Generated: host image of the data-aware schedules (copied to each device once).\n"

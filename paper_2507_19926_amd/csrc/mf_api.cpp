@@ -35,6 +35,16 @@ constexpr int kOblCount = sizeof(kOblTable) / sizeof(kOblTable[0]);
 
 constexpr int kMaxK = 75;
 
+// Measured AUTO choices (class 0: 8/16-bit data, class 1: 32-bit data).
+struct AutoEntry {
+    int cls, k, variant, tw, th, group;
+};
+const AutoEntry kAutoTable[] = {
+#define MF_AUTO(C, K, V, TW, TH, G) {C, K, V, TW, TH, G},
+#include "mf_auto_table.inc"
+#undef MF_AUTO
+    {-1, 0, 0, 0, 0, 0}};
+
 thread_local std::string g_last_error;
 
 int32_t fail(int32_t code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));

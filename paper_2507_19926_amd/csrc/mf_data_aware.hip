@@ -11,8 +11,11 @@
 //
 // Each round is a list of merge-path chunks: a lane finds the chunk's start in
 // its two sorted input windows with a co-rank binary search and then merges
-// up to 16 outputs sequentially. Only the ranks some later step can read are
-// produced (forgetting and pruning as output windows).
+// up to 32 outputs sequentially. A work-group holds T root tiles (T arenas)
+// that share the schedule; a lane runs its chunk for the T tiles side by side,
+// so T independent chains of LDS reads are in flight per lane. Only the ranks
+// some later step can read are produced (forgetting and pruning as output
+// windows).
 //
 // 8/16-bit data is held as 16-bit LDS elements, 32-bit data (uint32, float32
 // through an order-preserving key) as 32-bit elements.
@@ -47,13 +50,6 @@ __device__ __forceinline__ uint32_t mf_da_key_to_f32(uint32_t k)
 {
     return k ^ ((uint32_t)((int32_t)~k >> 31) | 0x80000000u);
 }
-
-template <class E> struct MfDaSent;
-template <> struct MfDaSent<uint16_t> { static constexpr uint16_t v = 0xFFFF; };
-template <> struct MfDaSent<uint32_t> { static constexpr uint32_t v = 0xFFFFFFFFu; };
-
-template <class E> __device__ __forceinline__ E mf_da_min(E a, E b) { return a < b ? a : b; }
-template <class E> __device__ __forceinline__ E mf_da_max(E a, E b) { return a < b ? b : a; }
 
 // T root tiles (bx*T + t, by) of one image, schedule `a`. LDS holds T arenas of
 // `arena` elements each; a lane executes each of its chunks for all T tiles
@@ -93,7 +89,6 @@ mf_da_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
     const uint4* __restrict__ chunks = reinterpret_cast<const uint4*>(blob + a.c_off);
     const uint32_t* __restrict__ rounds = blob + a.r_off;
     constexpr uint32_t kMask = (1u << 18) - 1;
-    constexpr int CH = MF_DA_CHUNK;
     for (int rd = 0; rd < a.nrounds; ++rd) {
         const int c1 = (int)rounds[rd + 1];
         int c = (int)rounds[rd] + threadIdx.x;
@@ -126,36 +121,33 @@ mf_da_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
                     any |= lo[t] < hi[t];
                 }
             }
-            // the next n outputs are the n smallest of A[i..i+CH) and B[j..j+CH):
-            // bitonic selection of the lowest CH, then a bitonic sort
+            // sequential two-pointer merge of n outputs, the T tiles side by
+            // side (T independent chains of dependent LDS reads)
+            int ii[T], jj[T];
+            E va[T], vb[T];
 #pragma unroll
             for (int t = 0; t < T; ++t) {
                 const E* A = lds + t * arena + ao;
                 const E* B = lds + t * arena + bo;
-                const int i = lo[t], j = r0 - lo[t];
-                E va[CH], vb[CH];
+                ii[t] = lo[t];
+                jj[t] = r0 - lo[t];
+                va[t] = ii[t] < na ? A[ii[t]] : (E)0;
+                vb[t] = jj[t] < nb ? B[jj[t]] : (E)0;
+            }
+            for (int q = 0; q < n; ++q) {
 #pragma unroll
-                for (int q = 0; q < CH; ++q) {
-                    va[q] = (i + q < na) ? A[i + q] : MfDaSent<E>::v;
-                    vb[q] = (j + q < nb) ? B[j + q] : MfDaSent<E>::v;
+                for (int t = 0; t < T; ++t) {
+                    const bool takeA = (ii[t] < na) && (jj[t] >= nb || va[t] <= vb[t]);
+                    lds[t * arena + oo + q] = takeA ? va[t] : vb[t];
+                    ii[t] += takeA ? 1 : 0;
+                    jj[t] += takeA ? 0 : 1;
+                    // one read refills the side just consumed; the index is
+                    // clamped into the arena (an exhausted side is never used)
+                    const int src_i = takeA ? ao + ii[t] : bo + jj[t];
+                    const E nv = lds[t * arena + min(src_i, arena - 1)];
+                    va[t] = takeA ? nv : va[t];
+                    vb[t] = takeA ? vb[t] : nv;
                 }
-#pragma unroll
-                for (int q = 0; q < CH; ++q) va[q] = mf_da_min(va[q], vb[CH - 1 - q]);
-#pragma unroll
-                for (int step = CH / 2; step >= 1; step >>= 1) {
-#pragma unroll
-                    for (int q = 0; q < CH; ++q) {
-                        if ((q & step) == 0) {
-                            const E x = va[q], y = va[q + step];
-                            va[q] = mf_da_min(x, y);
-                            va[q + step] = mf_da_max(x, y);
-                        }
-                    }
-                }
-                E* O = lds + t * arena + oo;
-#pragma unroll
-                for (int q = 0; q < CH; ++q)
-                    if (q < n) O[q] = va[q];
             }
             d = dn;
             c = cn;

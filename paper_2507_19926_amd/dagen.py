@@ -39,7 +39,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-CHUNK = 8           # outputs per merge-path chunk (the kernel's register network width)
+CHUNK = 32          # outputs per merge-path chunk
 OFF_BITS = 18       # arena offsets and sizes share a 32-bit word
 MAX_OFF = 1 << OFF_BITS
 MAX_LEN = 1 << (32 - OFF_BITS)
@@ -419,28 +419,3 @@ def _merge_path_chunk(A, B, r0, n):
             out.append(B[j]); j += 1
     return out
 
-
-def register_merge_chunk(A, B, r0, n, width=CHUNK, sentinel=0xFFFF):
-    """The kernel's chunk procedure: co-rank search, then the n smallest of
-    A[i..i+width) and B[j..j+width) (missing positions padded with the
-    largest value) by a bitonic selection and a bitonic sort."""
-    na, nb = len(A), len(B)
-    lo, hi = max(0, r0 - nb), min(r0, na)
-    while lo < hi:
-        i = (lo + hi) // 2
-        if A[i] <= B[r0 - i - 1]:
-            lo = i + 1
-        else:
-            hi = i
-    i, j = lo, r0 - lo
-    va = [A[i + q] if i + q < na else sentinel for q in range(width)]
-    vb = [B[j + q] if j + q < nb else sentinel for q in range(width)]
-    va = [min(va[q], vb[width - 1 - q]) for q in range(width)]
-    step = width // 2
-    while step >= 1:
-        for q in range(width):
-            if q & step == 0:
-                x, y = va[q], va[q + step]
-                va[q], va[q + step] = min(x, y), max(x, y)
-        step //= 2
-    return va[:n]

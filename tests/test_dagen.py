@@ -51,18 +51,3 @@ def test_library_tiles_fit_lds():
             assert S.arena * es <= emit_da.LDS_BYTES
             assert S.chunks.shape[1] == 4 and len(S.outputs) == key[1] * key[2]
 
-
-def test_register_merge_chunk_matches_sorted_merge():
-    g = wl.rng(1)
-    for trial in range(400):
-        na, nb = int(g.integers(0, 20)), int(g.integers(0, 20))
-        hiv = 4 if trial % 2 else 0x10000       # ties, and values equal to the sentinel
-        A = sorted(int(v) for v in g.integers(0, hiv, na))
-        B = sorted(int(v) for v in g.integers(0, hiv, nb))
-        if hiv == 0x10000:
-            A = sorted(min(v, 0xFFFF) for v in A)
-            B = sorted(min(v, 0xFFFF) for v in B)
-        full = sorted(A + B)
-        for r0 in range(0, na + nb):
-            for n in range(1, min(dg.CHUNK, na + nb - r0) + 1):
-                assert dg.register_merge_chunk(A, B, r0, n) == full[r0:r0 + n]
