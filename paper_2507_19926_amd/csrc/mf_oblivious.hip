@@ -51,73 +51,97 @@ template <> struct MfVTraits<uint32_t> { static constexpr bool PACK = false; };
 
 __device__ __forceinline__ int mf_clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
-// Footprint union of one block -> LDS raw buffer (swizzled layout).
-//
-// Rows are clamped per row (replicate border in y). Blocks whose columns stay
-// inside the image with a few bytes to spare take the fast path: every lane
-// first issues all of its aligned dword loads (no dependency between them, so
-// their latencies overlap), then unpacks them into LDS. Blocks touching the
-// left or right edge clamp element by element.
+// Geometry of a block: the union of its tiles' footprints.
+template <class V, int K, int TW, int TH, int RY>
+struct MfObGeom {
+    static constexpr bool PACK = MfVTraits<V>::PACK;
+    static constexpr int R = (K - 1) / 2;
+    static constexpr int TY = 4 * RY;
+    static constexpr int BWH = 64 * TW;            // block width of one packed half
+    static constexpr int COLS = BWH + K - 1;       // footprint-union columns
+    static constexpr int ROWS = TY * TH + K - 1;   // footprint-union rows
+    static constexpr int Q = (COLS + TW - 1) / TW;
+    // a segment of seg_bytes starting `lead` (< 4) bytes into an aligned
+    // dword needs ceil((lead + seg_bytes) / 4) <= (seg_bytes + 6) / 4 dwords;
+    // they end at most 6 bytes past the segment, inside the row because of
+    // the 8-element margin of the fast-path test
+    static constexpr int NDMAX = (COLS * (PACK ? 2 : 4) + 6) / 4;
+    static constexpr int U = (ROWS * NDMAX + 255) / 256;
+};
+
+// Global loads of one block's footprint union, held in registers between
+// issue and commit so that they can be in flight while the previous block's
+// network runs.
+template <class V, int K, int TW, int TH, int RY>
+struct MfObPrefetch {
+    using G = MfObGeom<V, K, TW, TH, RY>;
+    uint32_t va[G::U], vb[G::PACK ? G::U : 1];
+    bool fast;
+};
+
+// Blocks whose columns stay inside the image with an 8-element margin take
+// the fast path: aligned dword loads of whole row segments. Blocks touching
+// the left or right edge clamp element by element at commit time.
 template <class V, int K, int TW, int TH, int RY>
 __device__ __forceinline__ void
-mf_obl_load(const unsigned char* __restrict__ src, int H, int W, long long pitch, int dtype,
-            int X0, int Y0, V* __restrict__ raw)
+mf_obl_issue(const unsigned char* __restrict__ src, int H, int W, long long pitch, int dtype, int X0, int Y0,
+             MfObPrefetch<V, K, TW, TH, RY>& pf)
 {
-    constexpr bool PACK = MfVTraits<V>::PACK;
-    constexpr int R = (K - 1) / 2;
-    constexpr int TY = 4 * RY;
-    constexpr int BWH = 64 * TW;
-    constexpr int COLS = BWH + K - 1;
-    constexpr int ROWS = TY * TH + K - 1;
-    constexpr int Q = (COLS + TW - 1) / TW;
-    const int es = PACK ? (dtype == MF_U8 ? 1 : 2) : 4;
-    // bytes of one half-row segment, rounded out to aligned dwords
-    const int seg_bytes = COLS * es;
-    const int gx0 = X0 - R;                               // first column of half A
-    const int span = PACK ? (BWH + COLS) : COLS;           // columns touched by the block
-    const bool fast = gx0 >= 4 && gx0 + span + 8 <= W;
-    if (fast) {
-        // a segment of seg_bytes starting `lead` (< 4) bytes into an aligned
-        // dword needs ceil((lead + seg_bytes) / 4) <= (seg_bytes + 6) / 4 dwords;
-        // they end at most 6 bytes past the segment, inside the row because
-        // of the 8-element margin of the fast-path test
-        constexpr int NDMAX = (COLS * (PACK ? 2 : 4) + 6) / 4;
-        constexpr int ITEMS = ROWS * NDMAX;
-        constexpr int U = (ITEMS + 255) / 256;
-        const int nd = (seg_bytes + 6) / 4;               // dwords per segment (<= NDMAX)
-        uint32_t va[U], vb[U];
+    using G = MfObGeom<V, K, TW, TH, RY>;
+    const int es = G::PACK ? (dtype == MF_U8 ? 1 : 2) : 4;
+    const int gx0 = X0 - G::R;
+    const int span = G::PACK ? (G::BWH + G::COLS) : G::COLS;
+    pf.fast = gx0 >= 4 && gx0 + span + 8 <= W;
+    if (!pf.fast) return;
+    const int nd = (G::COLS * es + 6) / 4;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int it = threadIdx.x + u * 256;
-            va[u] = vb[u] = 0;
-            if (it < ROWS * nd) {
-                const int rho = it / nd, d = it - rho * nd;
-                const int gy = mf_clampi(Y0 - R + rho, 0, H - 1);
-                const uintptr_t a = (uintptr_t)(src + (long long)gy * pitch + (long long)gx0 * es);
-                const uint32_t* p = (const uint32_t*)((a & ~(uintptr_t)3) + 4 * (uintptr_t)d);
-                va[u] = p[0];
-                if constexpr (PACK) vb[u] = p[BWH * es / 4];
-            }
+    for (int u = 0; u < G::U; ++u) {
+        const int it = threadIdx.x + u * 256;
+        pf.va[u] = 0;
+        if constexpr (G::PACK) pf.vb[u] = 0;
+        if (it < G::ROWS * nd) {
+            const int rho = it / nd, d = it - rho * nd;
+            const int gy = mf_clampi(Y0 - G::R + rho, 0, H - 1);
+            const uintptr_t a = (uintptr_t)(src + (long long)gy * pitch + (long long)gx0 * es);
+            const uint32_t* p = (const uint32_t*)((a & ~(uintptr_t)3) + 4 * (uintptr_t)d);
+            pf.va[u] = p[0];
+            if constexpr (G::PACK) pf.vb[u] = p[G::BWH * es / 4];
         }
+    }
+}
+
+// Footprint union -> LDS raw buffer (swizzled layout), from the prefetched
+// registers or, for edge blocks, by clamped element loads.
+template <class V, int K, int TW, int TH, int RY>
+__device__ __forceinline__ void
+mf_obl_commit(const unsigned char* __restrict__ src, int H, int W, long long pitch, int dtype, int X0, int Y0,
+              const MfObPrefetch<V, K, TW, TH, RY>& pf, V* __restrict__ raw)
+{
+    using G = MfObGeom<V, K, TW, TH, RY>;
+    constexpr int Q = G::Q, COLS = G::COLS;
+    const int es = G::PACK ? (dtype == MF_U8 ? 1 : 2) : 4;
+    const int gx0 = X0 - G::R;
+    if (pf.fast) {
+        const int nd = (COLS * es + 6) / 4;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+        for (int u = 0; u < G::U; ++u) {
             const int it = threadIdx.x + u * 256;
-            if (it < ROWS * nd) {
+            if (it < G::ROWS * nd) {
                 const int rho = it / nd, d = it - rho * nd;
-                const int gy = mf_clampi(Y0 - R + rho, 0, H - 1);
+                const int gy = mf_clampi(Y0 - G::R + rho, 0, H - 1);
                 const uintptr_t a = (uintptr_t)(src + (long long)gy * pitch + (long long)gx0 * es);
                 const int lead = (int)(a & 3);            // bytes before the segment start
                 const int b0 = 4 * d - lead;              // segment byte of this dword's byte 0
                 V* rrow = raw + rho * TW * Q;
-                if constexpr (PACK) {
+                if constexpr (G::PACK) {
                     if (es == 1) {
 #pragma unroll
                         for (int b = 0; b < 4; ++b) {
                             const int c = b0 + b;
                             if (c >= 0 && c < COLS) {
                                 V v;
-                                v.x = (va[u] >> (8 * b)) & 0xFF;
-                                v.y = (vb[u] >> (8 * b)) & 0xFF;
+                                v.x = (pf.va[u] >> (8 * b)) & 0xFF;
+                                v.y = (pf.vb[u] >> (8 * b)) & 0xFF;
                                 rrow[(c % TW) * Q + c / TW] = v;
                             }
                         }
@@ -127,8 +151,8 @@ mf_obl_load(const unsigned char* __restrict__ src, int H, int W, long long pitch
                             const int c = (b0 >> 1) + h;  // b0 is even for 16-bit data
                             if (c >= 0 && c < COLS) {
                                 V v;
-                                v.x = (va[u] >> (16 * h)) & 0xFFFF;
-                                v.y = (vb[u] >> (16 * h)) & 0xFFFF;
+                                v.x = (pf.va[u] >> (16 * h)) & 0xFFFF;
+                                v.y = (pf.vb[u] >> (16 * h)) & 0xFFFF;
                                 rrow[(c % TW) * Q + c / TW] = v;
                             }
                         }
@@ -136,7 +160,7 @@ mf_obl_load(const unsigned char* __restrict__ src, int H, int W, long long pitch
                 } else {
                     const int c = b0 >> 2;                // 32-bit data is always aligned
                     if (c >= 0 && c < COLS) {
-                        uint32_t b = va[u];
+                        uint32_t b = pf.va[u];
                         if (dtype == MF_F32) b = mf_f32_to_key(b);
                         rrow[(c % TW) * Q + c / TW] = b;
                     }
@@ -145,14 +169,14 @@ mf_obl_load(const unsigned char* __restrict__ src, int H, int W, long long pitch
         }
         return;
     }
-    for (int w = threadIdx.x; w < ROWS * COLS; w += 256) {
+    for (int w = threadIdx.x; w < G::ROWS * COLS; w += 256) {
         const int rho = w / COLS, c = w - rho * COLS;
-        const int gy = mf_clampi(Y0 - R + rho, 0, H - 1);
+        const int gy = mf_clampi(Y0 - G::R + rho, 0, H - 1);
         const unsigned char* row = src + (long long)gy * pitch;
-        const int gxa = mf_clampi(X0 - R + c, 0, W - 1);
+        const int gxa = mf_clampi(X0 - G::R + c, 0, W - 1);
         V v;
-        if constexpr (PACK) {
-            const int gxb = mf_clampi(X0 + BWH - R + c, 0, W - 1);
+        if constexpr (G::PACK) {
+            const int gxb = mf_clampi(X0 + G::BWH - G::R + c, 0, W - 1);
             if (dtype == MF_U8) {
                 v.x = row[gxa];
                 v.y = row[gxb];
@@ -169,33 +193,14 @@ mf_obl_load(const unsigned char* __restrict__ src, int H, int W, long long pitch
     }
 }
 
-// One work-group's block (bx, by) of one image.
+// Sorted column segments of every tile row (initialisation, shared by the
+// horizontally adjacent tiles of the row).
 template <class NET, class V, int RY>
-__device__ __forceinline__ void
-mf_obl_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
-             int H, int W, long long pitch, int dtype, int bx, int by)
+__device__ __forceinline__ void mf_obl_colsort(const V* __restrict__ raw, V* __restrict__ colb)
 {
-    constexpr bool PACK = MfVTraits<V>::PACK;
-    constexpr int K = NET::K, TW = NET::TW, TH = NET::TH, LC = NET::LC;
-    constexpr int R = (K - 1) / 2;
-    constexpr int TX = 64;
-    constexpr int TY = 4 * RY;
-    constexpr int BWH = TX * TW;            // block width of one packed half
-    constexpr int COLS = BWH + K - 1;       // footprint-union columns
-    constexpr int ROWS = TY * TH + K - 1;   // footprint-union rows
-    constexpr int Q = (COLS + TW - 1) / TW;
-    __shared__ V raw[ROWS * TW * Q];
-    __shared__ V colb[TY * LC * TW * Q];
-
-    const int X0 = bx * (PACK ? 2 * BWH : BWH);
-    const int Y0 = by * (TY * TH);
-
-    // 1. footprint union -> LDS (clamped coordinates = replicate border)
-    mf_obl_load<V, K, TW, TH, RY>(src, H, W, pitch, dtype, X0, Y0, raw);
-    __syncthreads();
-
-    // 2. sorted column segments over each tile row's core rows
-    for (int it = threadIdx.x; it < TY * COLS; it += 256) {
+    using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY>;
+    constexpr int TW = NET::TW, TH = NET::TH, LC = NET::LC, Q = G::Q, COLS = G::COLS;
+    for (int it = threadIdx.x; it < G::TY * COLS; it += 256) {
         const int j = it / COLS, c = it - j * COLS;
         V a[LC];
 #pragma unroll
@@ -206,9 +211,17 @@ mf_obl_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ 
         for (int i = 0; i < LC; ++i)
             colb[((j * LC + i) * TW + c % TW) * Q + c / TW] = a[i];
     }
-    __syncthreads();
+}
 
-    // 3. per-lane hierarchical network
+// Per-lane hierarchical networks of one block, medians stored as produced.
+template <class NET, class V, int RY>
+__device__ __forceinline__ void
+mf_obl_networks(const V* __restrict__ raw, const V* __restrict__ colb, unsigned char* __restrict__ dst, int H,
+                int W, long long pitch, int dtype, int X0, int Y0)
+{
+    using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY>;
+    constexpr bool PACK = G::PACK;
+    constexpr int TW = NET::TW, TH = NET::TH, LC = NET::LC, Q = G::Q, BWH = G::BWH;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int ry = 0; ry < RY; ++ry) {
         const int j = wv * RY + ry;
@@ -234,6 +247,57 @@ mf_obl_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ 
             }
         };
         NET::template run<Q>(cb, rb, sink);
+    }
+}
+
+// One work-group's block (bx, by) of one image.
+template <class NET, class V, int RY>
+__device__ __forceinline__ void
+mf_obl_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
+             int H, int W, long long pitch, int dtype, int bx, int by)
+{
+    using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY>;
+    __shared__ V raw[G::ROWS * NET::TW * G::Q];
+    __shared__ V colb[G::TY * NET::LC * NET::TW * G::Q];
+    const int X0 = bx * (G::PACK ? 2 * G::BWH : G::BWH);
+    const int Y0 = by * (G::TY * NET::TH);
+    MfObPrefetch<V, NET::K, NET::TW, NET::TH, RY> pf;
+    mf_obl_issue(src, H, W, pitch, dtype, X0, Y0, pf);
+    mf_obl_commit(src, H, W, pitch, dtype, X0, Y0, pf, raw);
+    __syncthreads();
+    mf_obl_colsort<NET, V, RY>(raw, colb);
+    __syncthreads();
+    mf_obl_networks<NET, V, RY>(raw, colb, dst, H, W, pitch, dtype, X0, Y0);
+}
+
+// Persistent form: work-group w filters blocks [w*per, (w+1)*per) in
+// row-major order (neighbouring blocks, and their shared halos, stay on one
+// CU and one L2). The next block's global loads are issued before the
+// current block's networks run, so their latency hides behind VALU work.
+template <class NET, class V, int RY>
+__global__ void __launch_bounds__(256)
+mf_obl_kernel_persistent(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
+                         int H, int W, long long pitch, int dtype, int nbx, int nblocks, int per)
+{
+    using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY>;
+    __shared__ V raw[G::ROWS * NET::TW * G::Q];
+    __shared__ V colb[G::TY * NET::LC * NET::TW * G::Q];
+    const int b0 = blockIdx.x * per;
+    const int b1 = min(b0 + per, nblocks);
+    if (b0 >= b1) return;
+    const int bw = G::PACK ? 2 * G::BWH : G::BWH, bh = G::TY * NET::TH;
+    MfObPrefetch<V, NET::K, NET::TW, NET::TH, RY> pf;
+    mf_obl_issue(src, H, W, pitch, dtype, (b0 % nbx) * bw, (b0 / nbx) * bh, pf);
+    for (int b = b0; b < b1; ++b) {
+        const int X0 = (b % nbx) * bw, Y0 = (b / nbx) * bh;
+        __syncthreads();                       // previous networks are done with raw / colb
+        mf_obl_commit(src, H, W, pitch, dtype, X0, Y0, pf, raw);
+        __syncthreads();
+        mf_obl_colsort<NET, V, RY>(raw, colb);
+        __syncthreads();
+        if (b + 1 < b1)
+            mf_obl_issue(src, H, W, pitch, dtype, ((b + 1) % nbx) * bw, ((b + 1) / nbx) * bh, pf);
+        mf_obl_networks<NET, V, RY>(raw, colb, dst, H, W, pitch, dtype, X0, Y0);
     }
 }
 
@@ -282,8 +346,37 @@ static hipError_t mf_obl_launch(const void* src, void* dst, int H, int W, long l
     const int bw = (PACK ? 2 : 1) * 64 * NET::TW;
     const int bh = 4 * RY * NET::TH;
     const int nbx = (W + bw - 1) / bw, nby = (H + bh - 1) / bh;
-    hipLaunchKernelGGL((mf_obl_kernel<NET, V, RY>), dim3(nbx * nby), dim3(256), 0, stream,
-                       (const unsigned char*)src, (unsigned char*)dst, H, W, pitch, dtype, nbx);
+    const int nblocks = nbx * nby;
+    // resident work-groups of the persistent form, once per process from the
+    // occupancy calculator; 0 when the persistent form would spill registers
+    // to scratch (its prefetch registers live across the network), in which
+    // case every block gets its own work-group
+    static int resident = -1;
+    if (resident < 0) {
+        int per_cu = 0, dev = 0, cus = 0;
+        hipFuncAttributes attr;
+        const void* fn = (const void*)mf_obl_kernel_persistent<NET, V, RY>;
+        if (hipFuncGetAttributes(&attr, fn) != hipSuccess || attr.localSizeBytes > 0) {
+            resident = 0;
+        } else {
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mf_obl_kernel_persistent<NET, V, RY>, 256, 0) !=
+                    hipSuccess || per_cu < 1)
+                per_cu = 1;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+                cus = 256;
+            resident = per_cu * cus;
+        }
+    }
+    if (resident == 0 || nblocks <= 2 * resident) {
+        hipLaunchKernelGGL((mf_obl_kernel<NET, V, RY>), dim3(nblocks), dim3(256), 0, stream,
+                           (const unsigned char*)src, (unsigned char*)dst, H, W, pitch, dtype, nbx);
+        return hipGetLastError();
+    }
+    const int per = (nblocks + resident - 1) / resident;
+    const int grid = (nblocks + per - 1) / per;
+    hipLaunchKernelGGL((mf_obl_kernel_persistent<NET, V, RY>), dim3(grid), dim3(256), 0, stream,
+                       (const unsigned char*)src, (unsigned char*)dst, H, W, pitch, dtype, nbx, nblocks, per);
     return hipGetLastError();
 }
 
