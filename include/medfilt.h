@@ -69,6 +69,7 @@ typedef struct mf_options {
     int32_t tile_w;   /* root tile width, power of two <= k; 0 = library's   */
     int32_t tile_h;   /* root tile height, power of two <= k; 0 = library's  */
     int32_t group;    /* data-aware: root tiles per work-group (1, 2, 4);
+                         oblivious: waves per work-group (1, 4);
                          0 = library's                                      */
 } mf_options;
 

@@ -26,17 +26,18 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 # Oblivious configurations compiled into the library: (k, t_w, t_h, tile rows
-# per wave). The first entry for each k is the default; the others can be
-# requested through mf_options (and are what the tuner compares).
+# per wave, waves per work-group). The first entry for each k is the default;
+# the others can be requested through mf_options (and are what the tuner
+# compares).
 OBL_CONFIGS = [
-    (3, 2, 1, 8), (3, 1, 1, 8), (3, 2, 2, 4),
-    (5, 4, 2, 2), (5, 2, 2, 2),
-    (7, 4, 2, 2), (7, 2, 2, 2),
-    (9, 4, 4, 1), (9, 8, 2, 1),
-    (11, 4, 4, 1), (11, 4, 2, 2),
-    (13, 4, 4, 1),
-    (15, 4, 4, 1),
-    (17, 4, 4, 1),
+    (3, 2, 1, 8, 4), (3, 2, 1, 8, 1), (3, 1, 1, 8, 4), (3, 2, 2, 4, 4),
+    (5, 4, 2, 2, 4), (5, 4, 2, 4, 1), (5, 2, 2, 2, 4),
+    (7, 4, 2, 2, 4), (7, 4, 2, 4, 1), (7, 2, 2, 2, 4),
+    (9, 4, 4, 1, 4), (9, 4, 4, 2, 1), (9, 8, 2, 1, 4),
+    (11, 4, 4, 1, 4), (11, 4, 4, 2, 1), (11, 4, 2, 2, 4),
+    (13, 4, 4, 1, 4), (13, 4, 4, 1, 1),
+    (15, 4, 4, 1, 4), (15, 4, 4, 1, 1),
+    (17, 4, 4, 1, 4), (17, 4, 4, 1, 1),
 ]
 
 HIP_FLAGS = [

@@ -11,23 +11,23 @@
 
 #include "mf_internal.h"
 
-#define MF_OBL_ENTRY(K, TW, TH, RY) MF_OBL_DECLARE(K, TW, TH, RY)
+#define MF_OBL_ENTRY(K, TW, TH, RY, NW) MF_OBL_DECLARE(K, TW, TH, RY, NW)
 #include "mf_obl_table.inc"
 #undef MF_OBL_ENTRY
 
 namespace {
 
 struct OblEntry {
-    int k, tw, th, ry;
+    int k, tw, th, ry, nw;
     mf_launch_fn p16, u32;
     void (*batched_p16)(MfBatchedKernel*);
     void (*batched_u32)(MfBatchedKernel*);
 };
 
 const OblEntry kOblTable[] = {
-#define MF_OBL_ENTRY(K, TW, TH, RY)                                                                  \
-    {K, TW, TH, RY, MF_OBL_NAME(K, TW, TH, p16), MF_OBL_NAME(K, TW, TH, u32),                       \
-     MF_OBL_BATCHED_NAME(K, TW, TH, p16), MF_OBL_BATCHED_NAME(K, TW, TH, u32)},
+#define MF_OBL_ENTRY(K, TW, TH, RY, NW)                                                              \
+    {K, TW, TH, RY, NW, MF_OBL_NAME(K, TW, TH, RY, NW, p16), MF_OBL_NAME(K, TW, TH, RY, NW, u32),   \
+     MF_OBL_BATCHED_NAME(K, TW, TH, RY, NW, p16), MF_OBL_BATCHED_NAME(K, TW, TH, RY, NW, u32)},
 #include "mf_obl_table.inc"
 #undef MF_OBL_ENTRY
 };
@@ -72,12 +72,12 @@ int elem_size(int32_t dtype)
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
-const OblEntry* find_obl(int k, int tw, int th)
+const OblEntry* find_obl(int k, int tw, int th, int nw)
 {
     for (int i = 0; i < kOblCount; ++i) {
         const OblEntry& e = kOblTable[i];
-        if (e.k == k && (tw == 0 || e.tw == tw) && (th == 0 || e.th == th))
-            return &e;  // the table lists each k's preferred tile first
+        if (e.k == k && (tw == 0 || e.tw == tw) && (th == 0 || e.th == th) && (nw == 0 || e.nw == nw))
+            return &e;  // the table lists each k's preferred configuration first
     }
     return nullptr;
 }
@@ -99,7 +99,7 @@ int32_t resolve(int32_t dtype, int32_t k, const mf_options* opt, int32_t* varian
                     o.tile_h, k);
     *obl = nullptr;
     if (o.variant != MF_VARIANT_DATA_AWARE) {
-        const OblEntry* e = find_obl(k, o.tile_w, o.tile_h);
+        const OblEntry* e = find_obl(k, o.tile_w, o.tile_h, o.group == 1 || o.group == 4 ? o.group : 0);
         if (e) {
             *variant = MF_VARIANT_OBLIVIOUS;
             *tw = e->tw;
@@ -286,7 +286,7 @@ int32_t mf_list_configs(int32_t dtype, int32_t k, mf_options* out, int32_t cap)
                 out[n].variant = MF_VARIANT_OBLIVIOUS;
                 out[n].tile_w = kOblTable[i].tw;
                 out[n].tile_h = kOblTable[i].th;
-                out[n].group = 0;
+                out[n].group = kOblTable[i].nw;
             }
             ++n;
         }

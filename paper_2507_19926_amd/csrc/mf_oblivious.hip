@@ -8,8 +8,11 @@
 // through an order-preserving key) uses v_min_u32 / v_max_u32 (the compiler
 // fuses chains into v_min3 / v_max3).
 //
-// Work-group: 4 waves. A wave owns a row of 64 tile columns and RY tile rows;
-// the work-group's output block is (64 t_w [x2 packed]) x (4 RY t_h).
+// Work-group: NW waves (1 or 4). A wave owns a row of 64 tile columns and RY
+// tile rows; the work-group's output block is (64 t_w [x2 packed]) x
+// (NW RY t_h). With NW = 1 every wave is independent (its barriers are
+// wave-local), so one wave's load and sort phases overlap the networks of the
+// other waves of the CU.
 //   1. The union of the block's footprints is read from HBM once (coalesced,
 //      replicate border by clamping) into LDS.
 //   2. Every footprint column segment over a tile row's core rows is sorted
@@ -52,11 +55,12 @@ template <> struct MfVTraits<uint32_t> { static constexpr bool PACK = false; };
 __device__ __forceinline__ int mf_clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
 // Geometry of a block: the union of its tiles' footprints.
-template <class V, int K, int TW, int TH, int RY>
+template <class V, int K, int TW, int TH, int RY, int NW>
 struct MfObGeom {
     static constexpr bool PACK = MfVTraits<V>::PACK;
     static constexpr int R = (K - 1) / 2;
-    static constexpr int TY = 4 * RY;
+    static constexpr int NT = 64 * NW;             // threads of a work-group
+    static constexpr int TY = NW * RY;
     static constexpr int BWH = 64 * TW;            // block width of one packed half
     static constexpr int COLS = BWH + K - 1;       // footprint-union columns
     static constexpr int ROWS = TY * TH + K - 1;   // footprint-union rows
@@ -66,15 +70,15 @@ struct MfObGeom {
     // they end at most 6 bytes past the segment, inside the row because of
     // the 8-element margin of the fast-path test
     static constexpr int NDMAX = (COLS * (PACK ? 2 : 4) + 6) / 4;
-    static constexpr int U = (ROWS * NDMAX + 255) / 256;
+    static constexpr int U = (ROWS * NDMAX + NT - 1) / NT;
 };
 
 // Global loads of one block's footprint union, held in registers between
 // issue and commit so that they can be in flight while the previous block's
 // network runs.
-template <class V, int K, int TW, int TH, int RY>
+template <class V, int K, int TW, int TH, int RY, int NW>
 struct MfObPrefetch {
-    using G = MfObGeom<V, K, TW, TH, RY>;
+    using G = MfObGeom<V, K, TW, TH, RY, NW>;
     uint32_t va[G::U], vb[G::PACK ? G::U : 1];
     bool fast;
 };
@@ -82,12 +86,12 @@ struct MfObPrefetch {
 // Blocks whose columns stay inside the image with an 8-element margin take
 // the fast path: aligned dword loads of whole row segments. Blocks touching
 // the left or right edge clamp element by element at commit time.
-template <class V, int K, int TW, int TH, int RY>
+template <class V, int K, int TW, int TH, int RY, int NW>
 __device__ __forceinline__ void
 mf_obl_issue(const unsigned char* __restrict__ src, int H, int W, long long pitch, int dtype, int X0, int Y0,
-             MfObPrefetch<V, K, TW, TH, RY>& pf)
+             MfObPrefetch<V, K, TW, TH, RY, NW>& pf)
 {
-    using G = MfObGeom<V, K, TW, TH, RY>;
+    using G = MfObGeom<V, K, TW, TH, RY, NW>;
     const int es = G::PACK ? (dtype == MF_U8 ? 1 : 2) : 4;
     const int gx0 = X0 - G::R;
     const int span = G::PACK ? (G::BWH + G::COLS) : G::COLS;
@@ -96,7 +100,7 @@ mf_obl_issue(const unsigned char* __restrict__ src, int H, int W, long long pitc
     const int nd = (G::COLS * es + 6) / 4;
 #pragma unroll
     for (int u = 0; u < G::U; ++u) {
-        const int it = threadIdx.x + u * 256;
+        const int it = threadIdx.x + u * G::NT;
         pf.va[u] = 0;
         if constexpr (G::PACK) pf.vb[u] = 0;
         if (it < G::ROWS * nd) {
@@ -112,12 +116,12 @@ mf_obl_issue(const unsigned char* __restrict__ src, int H, int W, long long pitc
 
 // Footprint union -> LDS raw buffer (swizzled layout), from the prefetched
 // registers or, for edge blocks, by clamped element loads.
-template <class V, int K, int TW, int TH, int RY>
+template <class V, int K, int TW, int TH, int RY, int NW>
 __device__ __forceinline__ void
 mf_obl_commit(const unsigned char* __restrict__ src, int H, int W, long long pitch, int dtype, int X0, int Y0,
-              const MfObPrefetch<V, K, TW, TH, RY>& pf, V* __restrict__ raw)
+              const MfObPrefetch<V, K, TW, TH, RY, NW>& pf, V* __restrict__ raw)
 {
-    using G = MfObGeom<V, K, TW, TH, RY>;
+    using G = MfObGeom<V, K, TW, TH, RY, NW>;
     constexpr int Q = G::Q, COLS = G::COLS;
     const int es = G::PACK ? (dtype == MF_U8 ? 1 : 2) : 4;
     const int gx0 = X0 - G::R;
@@ -125,7 +129,7 @@ mf_obl_commit(const unsigned char* __restrict__ src, int H, int W, long long pit
         const int nd = (COLS * es + 6) / 4;
 #pragma unroll
         for (int u = 0; u < G::U; ++u) {
-            const int it = threadIdx.x + u * 256;
+            const int it = threadIdx.x + u * G::NT;
             if (it < G::ROWS * nd) {
                 const int rho = it / nd, d = it - rho * nd;
                 const int gy = mf_clampi(Y0 - G::R + rho, 0, H - 1);
@@ -169,7 +173,7 @@ mf_obl_commit(const unsigned char* __restrict__ src, int H, int W, long long pit
         }
         return;
     }
-    for (int w = threadIdx.x; w < G::ROWS * COLS; w += 256) {
+    for (int w = threadIdx.x; w < G::ROWS * COLS; w += G::NT) {
         const int rho = w / COLS, c = w - rho * COLS;
         const int gy = mf_clampi(Y0 - G::R + rho, 0, H - 1);
         const unsigned char* row = src + (long long)gy * pitch;
@@ -195,12 +199,12 @@ mf_obl_commit(const unsigned char* __restrict__ src, int H, int W, long long pit
 
 // Sorted column segments of every tile row (initialisation, shared by the
 // horizontally adjacent tiles of the row).
-template <class NET, class V, int RY>
+template <class NET, class V, int RY, int NW>
 __device__ __forceinline__ void mf_obl_colsort(const V* __restrict__ raw, V* __restrict__ colb)
 {
-    using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY>;
+    using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY, NW>;
     constexpr int TW = NET::TW, TH = NET::TH, LC = NET::LC, Q = G::Q, COLS = G::COLS;
-    for (int it = threadIdx.x; it < G::TY * COLS; it += 256) {
+    for (int it = threadIdx.x; it < G::TY * COLS; it += G::NT) {
         const int j = it / COLS, c = it - j * COLS;
         V a[LC];
 #pragma unroll
@@ -214,12 +218,12 @@ __device__ __forceinline__ void mf_obl_colsort(const V* __restrict__ raw, V* __r
 }
 
 // Per-lane hierarchical networks of one block, medians stored as produced.
-template <class NET, class V, int RY>
+template <class NET, class V, int RY, int NW>
 __device__ __forceinline__ void
 mf_obl_networks(const V* __restrict__ raw, const V* __restrict__ colb, unsigned char* __restrict__ dst, int H,
                 int W, long long pitch, int dtype, int X0, int Y0)
 {
-    using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY>;
+    using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY, NW>;
     constexpr bool PACK = G::PACK;
     constexpr int TW = NET::TW, TH = NET::TH, LC = NET::LC, Q = G::Q, BWH = G::BWH;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -251,69 +255,69 @@ mf_obl_networks(const V* __restrict__ raw, const V* __restrict__ colb, unsigned 
 }
 
 // One work-group's block (bx, by) of one image.
-template <class NET, class V, int RY>
+template <class NET, class V, int RY, int NW>
 __device__ __forceinline__ void
 mf_obl_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
              int H, int W, long long pitch, int dtype, int bx, int by)
 {
-    using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY>;
+    using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY, NW>;
     __shared__ V raw[G::ROWS * NET::TW * G::Q];
     __shared__ V colb[G::TY * NET::LC * NET::TW * G::Q];
     const int X0 = bx * (G::PACK ? 2 * G::BWH : G::BWH);
     const int Y0 = by * (G::TY * NET::TH);
-    MfObPrefetch<V, NET::K, NET::TW, NET::TH, RY> pf;
+    MfObPrefetch<V, NET::K, NET::TW, NET::TH, RY, NW> pf;
     mf_obl_issue(src, H, W, pitch, dtype, X0, Y0, pf);
     mf_obl_commit(src, H, W, pitch, dtype, X0, Y0, pf, raw);
     __syncthreads();
-    mf_obl_colsort<NET, V, RY>(raw, colb);
+    mf_obl_colsort<NET, V, RY, NW>(raw, colb);
     __syncthreads();
-    mf_obl_networks<NET, V, RY>(raw, colb, dst, H, W, pitch, dtype, X0, Y0);
+    mf_obl_networks<NET, V, RY, NW>(raw, colb, dst, H, W, pitch, dtype, X0, Y0);
 }
 
 // Persistent form: work-group w filters blocks [w*per, (w+1)*per) in
 // row-major order (neighbouring blocks, and their shared halos, stay on one
 // CU and one L2). The next block's global loads are issued before the
 // current block's networks run, so their latency hides behind VALU work.
-template <class NET, class V, int RY>
-__global__ void __launch_bounds__(256)
+template <class NET, class V, int RY, int NW>
+__global__ void __launch_bounds__(64 * NW)
 mf_obl_kernel_persistent(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
                          int H, int W, long long pitch, int dtype, int nbx, int nblocks, int per)
 {
-    using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY>;
+    using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY, NW>;
     __shared__ V raw[G::ROWS * NET::TW * G::Q];
     __shared__ V colb[G::TY * NET::LC * NET::TW * G::Q];
     const int b0 = blockIdx.x * per;
     const int b1 = min(b0 + per, nblocks);
     if (b0 >= b1) return;
     const int bw = G::PACK ? 2 * G::BWH : G::BWH, bh = G::TY * NET::TH;
-    MfObPrefetch<V, NET::K, NET::TW, NET::TH, RY> pf;
+    MfObPrefetch<V, NET::K, NET::TW, NET::TH, RY, NW> pf;
     mf_obl_issue(src, H, W, pitch, dtype, (b0 % nbx) * bw, (b0 / nbx) * bh, pf);
     for (int b = b0; b < b1; ++b) {
         const int X0 = (b % nbx) * bw, Y0 = (b / nbx) * bh;
         __syncthreads();                       // previous networks are done with raw / colb
         mf_obl_commit(src, H, W, pitch, dtype, X0, Y0, pf, raw);
         __syncthreads();
-        mf_obl_colsort<NET, V, RY>(raw, colb);
+        mf_obl_colsort<NET, V, RY, NW>(raw, colb);
         __syncthreads();
         if (b + 1 < b1)
             mf_obl_issue(src, H, W, pitch, dtype, ((b + 1) % nbx) * bw, ((b + 1) / nbx) * bh, pf);
-        mf_obl_networks<NET, V, RY>(raw, colb, dst, H, W, pitch, dtype, X0, Y0);
+        mf_obl_networks<NET, V, RY, NW>(raw, colb, dst, H, W, pitch, dtype, X0, Y0);
     }
 }
 
-template <class NET, class V, int RY>
-__global__ void __launch_bounds__(256)
+template <class NET, class V, int RY, int NW>
+__global__ void __launch_bounds__(64 * NW)
 mf_obl_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
               int H, int W, long long pitch, int dtype, int nbx)
 {
-    mf_obl_block<NET, V, RY>(src, dst, H, W, pitch, dtype, blockIdx.x % nbx, blockIdx.x / nbx);
+    mf_obl_block<NET, V, RY, NW>(src, dst, H, W, pitch, dtype, blockIdx.x % nbx, blockIdx.x / nbx);
 }
 
 // Batched form: the grid covers the blocks of every image of a job table
 // (images sharing k, root tile and value class); each work-group finds its
 // image by binary search over the jobs' first block indices.
-template <class NET, class V, int RY>
-__global__ void __launch_bounds__(256)
+template <class NET, class V, int RY, int NW>
+__global__ void __launch_bounds__(64 * NW)
 mf_obl_kernel_batched(const MfJob* __restrict__ jobs, int njobs)
 {
     const int b = blockIdx.x;
@@ -325,26 +329,26 @@ mf_obl_kernel_batched(const MfJob* __restrict__ jobs, int njobs)
     }
     const MfJob j = jobs[lo];
     const int lb = b - j.block_begin;
-    mf_obl_block<NET, V, RY>(j.src, j.dst, j.H, j.W, j.pitch, j.dtype, lb % j.nbx, lb / j.nbx);
+    mf_obl_block<NET, V, RY, NW>(j.src, j.dst, j.H, j.W, j.pitch, j.dtype, lb % j.nbx, lb / j.nbx);
 }
 
-template <class NET, class V, int RY>
+template <class NET, class V, int RY, int NW>
 static void mf_obl_batched(MfBatchedKernel* k)
 {
-    k->fn = (const void*)mf_obl_kernel_batched<NET, V, RY>;
-    k->threads = 256;
+    k->fn = (const void*)mf_obl_kernel_batched<NET, V, RY, NW>;
+    k->threads = 64 * NW;
     k->lds = 0;
     k->bw = (MfVTraits<V>::PACK ? 2 : 1) * 64 * NET::TW;
-    k->bh = 4 * RY * NET::TH;
+    k->bh = NW * RY * NET::TH;
 }
 
-template <class NET, class V, int RY>
+template <class NET, class V, int RY, int NW>
 static hipError_t mf_obl_launch(const void* src, void* dst, int H, int W, long long pitch,
                                 int dtype, hipStream_t stream)
 {
     constexpr bool PACK = MfVTraits<V>::PACK;
     const int bw = (PACK ? 2 : 1) * 64 * NET::TW;
-    const int bh = 4 * RY * NET::TH;
+    const int bh = NW * RY * NET::TH;
     const int nbx = (W + bw - 1) / bw, nby = (H + bh - 1) / bh;
     const int nblocks = nbx * nby;
     // resident work-groups of the persistent form, once per process from the
@@ -355,11 +359,12 @@ static hipError_t mf_obl_launch(const void* src, void* dst, int H, int W, long l
     if (resident < 0) {
         int per_cu = 0, dev = 0, cus = 0;
         hipFuncAttributes attr;
-        const void* fn = (const void*)mf_obl_kernel_persistent<NET, V, RY>;
+        const void* fn = (const void*)mf_obl_kernel_persistent<NET, V, RY, NW>;
         if (hipFuncGetAttributes(&attr, fn) != hipSuccess || attr.localSizeBytes > 0) {
             resident = 0;
         } else {
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mf_obl_kernel_persistent<NET, V, RY>, 256, 0) !=
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mf_obl_kernel_persistent<NET, V, RY, NW>,
+                                                             64 * NW, 0) !=
                     hipSuccess || per_cu < 1)
                 per_cu = 1;
             if (hipGetDevice(&dev) != hipSuccess ||
@@ -369,27 +374,33 @@ static hipError_t mf_obl_launch(const void* src, void* dst, int H, int W, long l
         }
     }
     if (resident == 0 || nblocks <= 2 * resident) {
-        hipLaunchKernelGGL((mf_obl_kernel<NET, V, RY>), dim3(nblocks), dim3(256), 0, stream,
+        hipLaunchKernelGGL((mf_obl_kernel<NET, V, RY, NW>), dim3(nblocks), dim3(64 * NW), 0, stream,
                            (const unsigned char*)src, (unsigned char*)dst, H, W, pitch, dtype, nbx);
         return hipGetLastError();
     }
     const int per = (nblocks + resident - 1) / resident;
     const int grid = (nblocks + per - 1) / per;
-    hipLaunchKernelGGL((mf_obl_kernel_persistent<NET, V, RY>), dim3(grid), dim3(256), 0, stream,
+    hipLaunchKernelGGL((mf_obl_kernel_persistent<NET, V, RY, NW>), dim3(grid), dim3(64 * NW), 0, stream,
                        (const unsigned char*)src, (unsigned char*)dst, H, W, pitch, dtype, nbx, nblocks, per);
     return hipGetLastError();
 }
 
-#define MF_OBL_INSTANTIATE(NET, RY)                                                       \
-    hipError_t mf_obl_launch_##NET##_p16(const void* s, void* d, int H, int W,            \
-                                         long long p, int dt, hipStream_t st)            \
+#define MF_OBL_INSTANTIATE(NET, RY, NW)                                                   \
+    hipError_t mf_obl_launch_##NET##_r##RY##w##NW##_p16(const void* s, void* d, int H, int W, \
+                                                     long long p, int dt, hipStream_t st) \
     {                                                                                     \
-        return mf_obl_launch<NET, us2, RY>(s, d, H, W, p, dt, st);                        \
+        return mf_obl_launch<NET, us2, RY, NW>(s, d, H, W, p, dt, st);                    \
     }                                                                                     \
-    hipError_t mf_obl_launch_##NET##_u32(const void* s, void* d, int H, int W,            \
-                                         long long p, int dt, hipStream_t st)            \
+    hipError_t mf_obl_launch_##NET##_r##RY##w##NW##_u32(const void* s, void* d, int H, int W, \
+                                                     long long p, int dt, hipStream_t st) \
     {                                                                                     \
-        return mf_obl_launch<NET, uint32_t, RY>(s, d, H, W, p, dt, st);                   \
+        return mf_obl_launch<NET, uint32_t, RY, NW>(s, d, H, W, p, dt, st);               \
     }                                                                                     \
-    void mf_obl_batched_##NET##_p16(MfBatchedKernel* k) { mf_obl_batched<NET, us2, RY>(k); }       \
-    void mf_obl_batched_##NET##_u32(MfBatchedKernel* k) { mf_obl_batched<NET, uint32_t, RY>(k); }
+    void mf_obl_batched_##NET##_r##RY##w##NW##_p16(MfBatchedKernel* k)                   \
+    {                                                                                     \
+        mf_obl_batched<NET, us2, RY, NW>(k);                                              \
+    }                                                                                     \
+    void mf_obl_batched_##NET##_r##RY##w##NW##_u32(MfBatchedKernel* k)                   \
+    {                                                                                     \
+        mf_obl_batched<NET, uint32_t, RY, NW>(k);                                         \
+    }

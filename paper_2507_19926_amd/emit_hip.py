@@ -85,7 +85,9 @@ def emit_sort(n: int) -> str:
     return "\n".join(lines)
 
 
-def emit_config_tu(k: int, tw: int, th: int, ry: int) -> str:
+def emit_config_tu(k: int, tw: int, th: int, shapes) -> str:
+    """One translation unit: the network for (k, tw, th) and one kernel
+    instantiation per (tile rows per wave, waves per work-group) shape."""
     P = ng.build_tile_program(k, tw, th)
     cnt = ng.op_counts(P)
     name = "MfNet_k%d_%dx%d" % (k, tw, th)
@@ -109,7 +111,7 @@ def emit_config_tu(k: int, tw: int, th: int, ry: int) -> str:
         "    }",
         "};",
         "",
-        "MF_OBL_INSTANTIATE(%s, %d)" % (name, ry),
+    ] + ["MF_OBL_INSTANTIATE(%s, %d, %d)" % (name, ry, nw) for (ry, nw) in shapes] + [
         "",
     ]
     return "\n".join(src)
@@ -120,17 +122,21 @@ def generate(out_dir: str, configs) -> list[str]:
     os.makedirs(out_dir, exist_ok=True)
     paths = []
     table = []
-    for (k, tw, th, ry) in configs:
+    tiles = {}
+    for (k, tw, th, ry, nw) in configs:
+        tiles.setdefault((k, tw, th), []).append((ry, nw))
+        table.append("MF_OBL_ENTRY(%d, %d, %d, %d, %d)" % (k, tw, th, ry, nw))
+    for (k, tw, th), shapes in tiles.items():
         path = os.path.join(out_dir, "mf_obl_k%d_%dx%d.hip" % (k, tw, th))
-        text = emit_config_tu(k, tw, th, ry)
+        text = emit_config_tu(k, tw, th, shapes)
         old = open(path).read() if os.path.exists(path) else None
         if old != text:
             with open(path, "w") as f:
                 f.write(text)
         paths.append(path)
-        table.append("MF_OBL_ENTRY(%d, %d, %d, %d)" % (k, tw, th, ry))
     tpath = os.path.join(out_dir, "mf_obl_table.inc")
-    text = "// Generated list of compiled oblivious configurations: (k, t_w, t_h, tile rows per wave)\n" \
+    text = "// Generated list of compiled oblivious configurations:\n" \
+        "// (k, t_w, t_h, tile rows per wave, waves per work-group)\n" \
         + "\n".join(table) + "\n"
     old = open(tpath).read() if os.path.exists(tpath) else None
     if old != text:
