@@ -48,15 +48,18 @@ mf_argmedian_kernel(const uint32_t* __restrict__ src, const uint32_t* __restrict
     const int y = Y0 + ty, x = X0 + tx;
     if (y >= H || x >= W) return;
     const uint32_t m = med[base + (long long)y * W + x];
+    // rows in order; within a row every read is independent of the match
+    // test, so the k reads of a row are in flight together
     int found = -1;
     for (int dy = 0; dy < k && found < 0; ++dy) {
         const uint32_t* row = tile + (ty + dy) * lw + tx;
-        for (int dx = 0; dx < k; ++dx) {
-            if (row[dx] == m) {
-                const int gy = clampi(y - r + dy, 0, H - 1), gx = clampi(x - r + dx, 0, W - 1);
-                found = gy * W + gx;
-                break;
-            }
+        int first = k;
+#pragma unroll 8
+        for (int dx = 0; dx < k; ++dx)
+            first = (row[dx] == m && dx < first) ? dx : first;
+        if (first < k) {
+            const int gy = clampi(y - r + dy, 0, H - 1), gx = clampi(x - r + first, 0, W - 1);
+            found = gy * W + gx;
         }
     }
     idx[base + (long long)y * W + x] = found;
