@@ -71,6 +71,9 @@ typedef struct mf_options {
     int32_t group;    /* data-aware: root tiles per work-group (1, 2, 4);
                          oblivious: waves per work-group (1, 4);
                          0 = library's                                      */
+    int32_t form;     /* oblivious: 1 = columns sorted once per work-group and
+                         shared by the tiles, 2 = each tile sorts its own
+                         columns (small k); 0 = library's                   */
 } mf_options;
 
 /* k x k median of one plane (Section 1 definition, Section 3 method).

@@ -26,12 +26,14 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 # Oblivious configurations compiled into the library: (k, t_w, t_h, tile rows
-# per wave, waves per work-group). The first entry for each k is the default;
-# the others can be requested through mf_options (and are what the tuner
-# compares).
+# per wave, waves per work-group[, inline column sort]). The first entry for
+# each k is the default; the others can be requested through mf_options (and
+# are what the tuner compares).
 OBL_CONFIGS = [
     (3, 2, 1, 8, 4), (3, 2, 1, 8, 1), (3, 1, 1, 8, 4), (3, 2, 2, 4, 4),
+    (3, 2, 1, 8, 4, True), (3, 2, 2, 4, 4, True), (3, 2, 2, 8, 1, True),
     (5, 4, 2, 2, 4), (5, 4, 2, 4, 1), (5, 2, 2, 2, 4),
+    (5, 4, 2, 2, 4, True), (5, 2, 2, 4, 4, True),
     (7, 4, 2, 2, 4), (7, 4, 2, 4, 1), (7, 2, 2, 2, 4),
     (9, 4, 4, 1, 4), (9, 4, 4, 2, 1), (9, 8, 2, 1, 4),
     (11, 4, 4, 1, 4), (11, 4, 4, 2, 1), (11, 4, 2, 2, 4),
@@ -60,7 +62,7 @@ def _compile(src: str, obj: str, extra=()) -> tuple[str, str]:
 
 def _write_auto_table() -> None:
     """AUTO choices per (value class, k) from tuned.json (autotune.py), as
-    MF_AUTO(class, k, variant, tile_w, tile_h, group) lines; class 0 = 8/16-bit,
+    MF_AUTO(class, k, variant, tile_w, tile_h, group, form) lines; class 0 = 8/16-bit,
     1 = 32-bit. Without tuned.json the table is empty and the library falls
     back to its built-in order (oblivious first)."""
     import json
@@ -70,8 +72,10 @@ def _write_auto_table() -> None:
         with open(path) as f:
             t = json.load(f)
         for cls, code in (("p16", 0), ("u32", 1)):
-            for k, (variant, tw, th, group) in sorted(t.get(cls, {}).items(), key=lambda kv: int(kv[0])):
-                lines.append("MF_AUTO(%d, %d, %d, %d, %d, %d)" % (code, int(k), variant, tw, th, group))
+            for k, cfg in sorted(t.get(cls, {}).items(), key=lambda kv: int(kv[0])):
+                variant, tw, th, group = cfg[:4]
+                form = cfg[4] if len(cfg) > 4 else 0
+                lines.append("MF_AUTO(%d, %d, %d, %d, %d, %d, %d)" % (code, int(k), variant, tw, th, group, form))
     text = "\n".join(lines) + "\n"
     out = os.path.join(GEN, "mf_auto_table.inc")
     if not os.path.exists(out) or open(out).read() != text:

@@ -11,23 +11,23 @@
 
 #include "mf_internal.h"
 
-#define MF_OBL_ENTRY(K, TW, TH, RY, NW) MF_OBL_DECLARE(K, TW, TH, RY, NW)
+#define MF_OBL_ENTRY(NET, K, TW, TH, RY, NW, INL) MF_OBL_DECLARE(NET, RY, NW)
 #include "mf_obl_table.inc"
 #undef MF_OBL_ENTRY
 
 namespace {
 
 struct OblEntry {
-    int k, tw, th, ry, nw;
+    int k, tw, th, ry, nw, inl;
     mf_launch_fn p16, u32;
     void (*batched_p16)(MfBatchedKernel*);
     void (*batched_u32)(MfBatchedKernel*);
 };
 
 const OblEntry kOblTable[] = {
-#define MF_OBL_ENTRY(K, TW, TH, RY, NW)                                                              \
-    {K, TW, TH, RY, NW, MF_OBL_NAME(K, TW, TH, RY, NW, p16), MF_OBL_NAME(K, TW, TH, RY, NW, u32),   \
-     MF_OBL_BATCHED_NAME(K, TW, TH, RY, NW, p16), MF_OBL_BATCHED_NAME(K, TW, TH, RY, NW, u32)},
+#define MF_OBL_ENTRY(NET, K, TW, TH, RY, NW, INL)                                                    \
+    {K, TW, TH, RY, NW, INL, MF_OBL_NAME(NET, RY, NW, p16), MF_OBL_NAME(NET, RY, NW, u32),          \
+     MF_OBL_BATCHED_NAME(NET, RY, NW, p16), MF_OBL_BATCHED_NAME(NET, RY, NW, u32)},
 #include "mf_obl_table.inc"
 #undef MF_OBL_ENTRY
 };
@@ -37,13 +37,13 @@ constexpr int kMaxK = 75;
 
 // Measured AUTO choices (class 0: 8/16-bit data, class 1: 32-bit data).
 struct AutoEntry {
-    int cls, k, variant, tw, th, group;
+    int cls, k, variant, tw, th, group, form;
 };
 const AutoEntry kAutoTable[] = {
-#define MF_AUTO(C, K, V, TW, TH, G) {C, K, V, TW, TH, G},
+#define MF_AUTO(C, K, V, TW, TH, G, F) {C, K, V, TW, TH, G, F},
 #include "mf_auto_table.inc"
 #undef MF_AUTO
-    {-1, 0, 0, 0, 0, 0}};
+    {-1, 0, 0, 0, 0, 0, 0}};
 
 thread_local std::string g_last_error;
 
@@ -72,11 +72,12 @@ int elem_size(int32_t dtype)
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
-const OblEntry* find_obl(int k, int tw, int th, int nw)
+const OblEntry* find_obl(int k, int tw, int th, int nw, int form)
 {
     for (int i = 0; i < kOblCount; ++i) {
         const OblEntry& e = kOblTable[i];
-        if (e.k == k && (tw == 0 || e.tw == tw) && (th == 0 || e.th == th) && (nw == 0 || e.nw == nw))
+        if (e.k == k && (tw == 0 || e.tw == tw) && (th == 0 || e.th == th) && (nw == 0 || e.nw == nw) &&
+            (form == 0 || (form == 2) == (e.inl != 0)))
             return &e;  // the table lists each k's preferred configuration first
     }
     return nullptr;
@@ -99,7 +100,8 @@ int32_t resolve(int32_t dtype, int32_t k, const mf_options* opt, int32_t* varian
                     o.tile_h, k);
     *obl = nullptr;
     if (o.variant != MF_VARIANT_DATA_AWARE) {
-        const OblEntry* e = find_obl(k, o.tile_w, o.tile_h, o.group == 1 || o.group == 4 ? o.group : 0);
+        const OblEntry* e =
+            find_obl(k, o.tile_w, o.tile_h, o.group == 1 || o.group == 4 ? o.group : 0, o.form);
         if (e) {
             *variant = MF_VARIANT_OBLIVIOUS;
             *tw = e->tw;
@@ -287,6 +289,7 @@ int32_t mf_list_configs(int32_t dtype, int32_t k, mf_options* out, int32_t cap)
                 out[n].tile_w = kOblTable[i].tw;
                 out[n].tile_h = kOblTable[i].th;
                 out[n].group = kOblTable[i].nw;
+                out[n].form = kOblTable[i].inl ? 2 : 1;
             }
             ++n;
         }
@@ -298,6 +301,7 @@ int32_t mf_list_configs(int32_t dtype, int32_t k, mf_options* out, int32_t cap)
                 out[n].tile_w = tw[i];
                 out[n].tile_h = th[i];
                 out[n].group = gr[i];
+                out[n].form = 0;
             }
             ++n;
         }

@@ -32,17 +32,16 @@ struct MfBatchedKernel {
     int bw, bh;
 };
 
-#define MF_OBL_NAME(K, TW, TH, RY, NW, VC) mf_obl_launch_MfNet_k##K##_##TW##x##TH##_r##RY##w##NW##_##VC
-#define MF_OBL_BATCHED_NAME(K, TW, TH, RY, NW, VC) \
-    mf_obl_batched_MfNet_k##K##_##TW##x##TH##_r##RY##w##NW##_##VC
+#define MF_OBL_NAME(NET, RY, NW, VC) mf_obl_launch_##NET##_r##RY##w##NW##_##VC
+#define MF_OBL_BATCHED_NAME(NET, RY, NW, VC) mf_obl_batched_##NET##_r##RY##w##NW##_##VC
 
-#define MF_OBL_DECLARE(K, TW, TH, RY, NW)                                            \
-    hipError_t MF_OBL_NAME(K, TW, TH, RY, NW, p16)(const void*, void*, int, int,    \
-                                                   long long, int, hipStream_t);    \
-    hipError_t MF_OBL_NAME(K, TW, TH, RY, NW, u32)(const void*, void*, int, int,    \
-                                                   long long, int, hipStream_t);    \
-    void MF_OBL_BATCHED_NAME(K, TW, TH, RY, NW, p16)(MfBatchedKernel*);             \
-    void MF_OBL_BATCHED_NAME(K, TW, TH, RY, NW, u32)(MfBatchedKernel*);
+#define MF_OBL_DECLARE(NET, RY, NW)                                                \
+    hipError_t MF_OBL_NAME(NET, RY, NW, p16)(const void*, void*, int, int,        \
+                                             long long, int, hipStream_t);        \
+    hipError_t MF_OBL_NAME(NET, RY, NW, u32)(const void*, void*, int, int,        \
+                                             long long, int, hipStream_t);        \
+    void MF_OBL_BATCHED_NAME(NET, RY, NW, p16)(MfBatchedKernel*);                 \
+    void MF_OBL_BATCHED_NAME(NET, RY, NW, u32)(MfBatchedKernel*);
 
 // Data-aware launcher: one per value class, any k up to mf_max_k().
 hipError_t mf_da_launch(const void* src, void* dst, int H, int W, long long pitch,

@@ -262,15 +262,17 @@ mf_obl_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ 
 {
     using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY, NW>;
     __shared__ V raw[G::ROWS * NET::TW * G::Q];
-    __shared__ V colb[G::TY * NET::LC * NET::TW * G::Q];
+    __shared__ V colb[NET::INLINE_COLS ? 1 : G::TY * NET::LC * NET::TW * G::Q];
     const int X0 = bx * (G::PACK ? 2 * G::BWH : G::BWH);
     const int Y0 = by * (G::TY * NET::TH);
     MfObPrefetch<V, NET::K, NET::TW, NET::TH, RY, NW> pf;
     mf_obl_issue(src, H, W, pitch, dtype, X0, Y0, pf);
     mf_obl_commit(src, H, W, pitch, dtype, X0, Y0, pf, raw);
     __syncthreads();
-    mf_obl_colsort<NET, V, RY, NW>(raw, colb);
-    __syncthreads();
+    if constexpr (!NET::INLINE_COLS) {
+        mf_obl_colsort<NET, V, RY, NW>(raw, colb);
+        __syncthreads();
+    }
     mf_obl_networks<NET, V, RY, NW>(raw, colb, dst, H, W, pitch, dtype, X0, Y0);
 }
 
@@ -285,7 +287,7 @@ mf_obl_kernel_persistent(const unsigned char* __restrict__ src, unsigned char* _
 {
     using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY, NW>;
     __shared__ V raw[G::ROWS * NET::TW * G::Q];
-    __shared__ V colb[G::TY * NET::LC * NET::TW * G::Q];
+    __shared__ V colb[NET::INLINE_COLS ? 1 : G::TY * NET::LC * NET::TW * G::Q];
     const int b0 = blockIdx.x * per;
     const int b1 = min(b0 + per, nblocks);
     if (b0 >= b1) return;
@@ -297,8 +299,10 @@ mf_obl_kernel_persistent(const unsigned char* __restrict__ src, unsigned char* _
         __syncthreads();                       // previous networks are done with raw / colb
         mf_obl_commit(src, H, W, pitch, dtype, X0, Y0, pf, raw);
         __syncthreads();
-        mf_obl_colsort<NET, V, RY, NW>(raw, colb);
-        __syncthreads();
+        if constexpr (!NET::INLINE_COLS) {
+            mf_obl_colsort<NET, V, RY, NW>(raw, colb);
+            __syncthreads();
+        }
         if (b + 1 < b1)
             mf_obl_issue(src, H, W, pitch, dtype, ((b + 1) % nbx) * bw, ((b + 1) / nbx) * bh, pf);
         mf_obl_networks<NET, V, RY, NW>(raw, colb, dst, H, W, pitch, dtype, X0, Y0);

@@ -85,12 +85,16 @@ def emit_sort(n: int) -> str:
     return "\n".join(lines)
 
 
-def emit_config_tu(k: int, tw: int, th: int, shapes) -> str:
+def net_name(k: int, tw: int, th: int, inline: bool) -> str:
+    return "MfNet_k%d_%dx%d%s" % (k, tw, th, "i" if inline else "")
+
+
+def emit_config_tu(k: int, tw: int, th: int, shapes, inline: bool = False) -> str:
     """One translation unit: the network for (k, tw, th) and one kernel
     instantiation per (tile rows per wave, waves per work-group) shape."""
-    P = ng.build_tile_program(k, tw, th)
+    P = ng.build_tile_program(k, tw, th, inline_cols=inline)
     cnt = ng.op_counts(P)
-    name = "MfNet_k%d_%dx%d" % (k, tw, th)
+    name = net_name(k, tw, th, inline)
     lc = k - th + 1
     body = _net_body(P, k, tw, th, indent="        ")
     src = [
@@ -103,6 +107,7 @@ def emit_config_tu(k: int, tw: int, th: int, shapes) -> str:
         "",
         "struct %s {" % name,
         "    static constexpr int K = %d, TW = %d, TH = %d, LC = %d;" % (k, tw, th, lc),
+        "    static constexpr bool INLINE_COLS = %s;" % ("true" if inline else "false"),
         "    template <class V> static __device__ __forceinline__ void sort_column(V* a) { mf_sort_%d(a); }" % lc,
         "    template <int Q, class V, class Sink>",
         "    static __device__ __forceinline__ void run(const V* __restrict__ col,",
@@ -123,12 +128,14 @@ def generate(out_dir: str, configs) -> list[str]:
     paths = []
     table = []
     tiles = {}
-    for (k, tw, th, ry, nw) in configs:
-        tiles.setdefault((k, tw, th), []).append((ry, nw))
-        table.append("MF_OBL_ENTRY(%d, %d, %d, %d, %d)" % (k, tw, th, ry, nw))
-    for (k, tw, th), shapes in tiles.items():
-        path = os.path.join(out_dir, "mf_obl_k%d_%dx%d.hip" % (k, tw, th))
-        text = emit_config_tu(k, tw, th, shapes)
+    for cfg in configs:
+        (k, tw, th, ry, nw), inline = cfg[:5], (len(cfg) > 5 and cfg[5])
+        tiles.setdefault((k, tw, th, inline), []).append((ry, nw))
+        table.append("MF_OBL_ENTRY(%s, %d, %d, %d, %d, %d, %d)"
+                     % (net_name(k, tw, th, inline), k, tw, th, ry, nw, 1 if inline else 0))
+    for (k, tw, th, inline), shapes in tiles.items():
+        path = os.path.join(out_dir, "mf_obl_k%d_%dx%d%s.hip" % (k, tw, th, "i" if inline else ""))
+        text = emit_config_tu(k, tw, th, shapes, inline)
         old = open(path).read() if os.path.exists(path) else None
         if old != text:
             with open(path, "w") as f:
@@ -136,7 +143,7 @@ def generate(out_dir: str, configs) -> list[str]:
         paths.append(path)
     tpath = os.path.join(out_dir, "mf_obl_table.inc")
     text = "// Generated list of compiled oblivious configurations:\n" \
-        "// (k, t_w, t_h, tile rows per wave, waves per work-group)\n" \
+        "// (network, k, t_w, t_h, tile rows per wave, waves per work-group, inline column sort)\n" \
         + "\n".join(table) + "\n"
     old = open(tpath).read() if os.path.exists(tpath) else None
     if old != text:

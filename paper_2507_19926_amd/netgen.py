@@ -208,10 +208,13 @@ class _State:
     xrows: dict = field(default_factory=dict)   # y -> sorted list over core cols
 
 
-def build_tile_program(k: int, tw: int, th: int) -> Prog:
+def build_tile_program(k: int, tw: int, th: int, inline_cols: bool = False) -> Prog:
     """Straight-line selection network for one tw x th root tile.
 
     outputs[py*tw + px] is the median of the window of pixel (px, py).
+    With inline_cols the tile sorts its own footprint columns from raw loads
+    (pruned to the ranks it uses) instead of loading pre-sorted shared
+    columns: no shared column buffer, more work per tile (small k).
     """
     assert k % 2 == 1 and k >= 1
     assert tw >= 1 and th >= 1 and (tw & (tw - 1)) == 0 and (th & (th - 1)) == 0
@@ -221,6 +224,8 @@ def build_tile_program(k: int, tw: int, th: int) -> Prog:
     Lc = k - th + 1
 
     def col(x):
+        if inline_cols:
+            return sort(P, [P.load(("raw", x, y)) for y in range(th - 1, k)])
         return [P.load(("col", x, i)) for i in range(Lc)]
 
     def raw(x, y):

@@ -123,3 +123,11 @@ def test_tile_program_matches_oracle(k, tw, th):
     ties = wl.tie_heavy_plane(21, 26, np.uint8, levels=3, seed=k)
     np.testing.assert_array_equal(ng.evaluate_on_image(P, ties, k, tw, th),
                                   oracle.median_filter(ties, k))
+
+
+@pytest.mark.parametrize("k,tw,th", [(3, 2, 1), (3, 2, 2), (5, 4, 2), (5, 2, 2), (7, 4, 2)])
+def test_inline_column_program_matches_oracle(k, tw, th):
+    P = ng.build_tile_program(k, tw, th, inline_cols=True)
+    assert all(op[1][0] == "raw" for op in P.ops if op[0] == ng.LD)
+    img = wl.uniform_plane(23, 37, np.uint8, seed=k)
+    np.testing.assert_array_equal(ng.evaluate_on_image(P, img, k, tw, th), oracle.median_filter(img, k))
