@@ -98,7 +98,32 @@ int32_t resolve(int32_t dtype, int32_t k, const mf_options* opt, int32_t* varian
         o.tile_w < 0 || o.tile_h < 0)
         return fail(MF_ERR_CONFIG, "root tile %dx%d is not a pair of powers of two <= k=%d", o.tile_w,
                     o.tile_h, k);
+    if (o.form < 0 || o.form > 2) return fail(MF_ERR_CONFIG, "form %d not in {0, 1, 2}", o.form);
     *obl = nullptr;
+    // measured choice for this (value class, k), when nothing was requested
+    if (o.variant == MF_VARIANT_AUTO && !o.tile_w && !o.tile_h && !o.group && !o.form) {
+        const int cls = (dtype == MF_U8 || dtype == MF_U16) ? 0 : 1;
+        for (const AutoEntry& a : kAutoTable) {
+            if (a.cls != cls || a.k != k) continue;
+            if (a.variant == MF_VARIANT_OBLIVIOUS) {
+                const OblEntry* e = find_obl(k, a.tw, a.th, a.group, a.form);
+                if (e) {
+                    *variant = MF_VARIANT_OBLIVIOUS;
+                    *tw = e->tw;
+                    *th = e->th;
+                    *obl = e;
+                    return MF_OK;
+                }
+            } else if (mf_da_supports(dtype, k, a.tw, a.th, a.group)) {
+                *variant = MF_VARIANT_DATA_AWARE;
+                *tw = a.tw;
+                *th = a.th;
+                if (group) *group = a.group;
+                return MF_OK;
+            }
+            break;  // a stale entry: fall back to the built-in order
+        }
+    }
     if (o.variant != MF_VARIANT_DATA_AWARE) {
         const OblEntry* e =
             find_obl(k, o.tile_w, o.tile_h, o.group == 1 || o.group == 4 ? o.group : 0, o.form);
