@@ -67,6 +67,29 @@ def algorithmic_ops_per_pixel(dtype_code: int, k: int):
     return variant, (tw, th), dagen.schedule(k, tw, th).stats["per_pixel_outputs"]
 
 
+def measured_traffic(k: int, tile):
+    """HBM bytes per launch from the committed counter measurement of this
+    kernel (profiles/traffic_*.json), or None when there is none or the
+    kernel's sources changed since it was taken."""
+    import glob
+    import hashlib
+    for path in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json")):
+        with open(path) as f:
+            t = json.load(f)
+        if "k=%d" % k not in t.get("workload", "") or "%dx%d" % tuple(tile) not in t.get("kernel", ""):
+            continue
+        h = hashlib.sha256()
+        try:
+            for src in t["source_files"]:
+                with open(os.path.join(ROOT, src), "rb") as f:
+                    h.update(f.read())
+        except OSError:
+            return None
+        if h.hexdigest()[:16] == t["source_sha256_16"]:
+            return t["traffic_bytes_per_launch"]
+    return None
+
+
 def roofline(dtype_code: int, k: int, pixels_per_launch: int, launch_s: float):
     from paper_2507_19926_amd import _lib
     es = {0: 1, 1: 2, 2: 4, 3: 4}[dtype_code]
@@ -256,6 +279,9 @@ def main():
     wall, launch_s = run(args.k, args.steps, args.warmup)
     value = px_step * args.steps / wall / 1e6
     roof = roofline(_lib.MF_U8, args.k, H * W, launch_s)
+    roof["traffic"] = measured_traffic(args.k, roof["tile"]) if roof["variant"] == _lib.MF_VARIANT_OBLIVIOUS else None
+    roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+    roof["algorithmic_bytes_per_launch"] = 2 * H * W
     per_k = {}
     if args.sweep_steps > 0 and not args.only_headline:
         for k in wl.RGB30_KS:
