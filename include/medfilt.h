@@ -74,6 +74,7 @@ typedef struct mf_options {
     int32_t form;     /* oblivious: 1 = columns sorted once per work-group and
                          shared by the tiles, 2 = each tile sorts its own
                          columns (small k); 0 = library's                   */
+    int32_t rows;     /* oblivious: tile rows per wave; 0 = library's       */
 } mf_options;
 
 /* k x k median of one plane (Section 1 definition, Section 3 method).

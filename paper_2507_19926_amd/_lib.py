@@ -31,7 +31,7 @@ class MfError(RuntimeError):
 
 class mf_options(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
-                ("group", ctypes.c_int32), ("form", ctypes.c_int32)]
+                ("group", ctypes.c_int32), ("form", ctypes.c_int32), ("rows", ctypes.c_int32)]
 
 
 class mf_image(ctypes.Structure):
@@ -93,18 +93,20 @@ def check(code: int) -> None:
         raise MfError(code, lib().mf_last_error().decode())
 
 
-def options(variant: int = MF_VARIANT_AUTO, tile=None, group: int = 0, form: int = 0) -> mf_options:
+def options(variant: int = MF_VARIANT_AUTO, tile=None, group: int = 0, form: int = 0,
+            rows: int = 0) -> mf_options:
     o = mf_options()
     o.variant = variant
     if tile is not None:
         o.tile_w, o.tile_h = int(tile[0]), int(tile[1])
     o.group = int(group)
     o.form = int(form)
+    o.rows = int(rows)
     return o
 
 
 def list_configs(dtype_code: int, k: int):
-    """Every compiled (variant, tile_w, tile_h, group, form) for dtype and k, default first."""
+    """Every compiled (variant, tile_w, tile_h, group, form, rows) for dtype and k, default first."""
     L = lib()
     n = L.mf_list_configs(dtype_code, k, None, 0)
     if n < 0:
@@ -113,7 +115,7 @@ def list_configs(dtype_code: int, k: int):
     m = L.mf_list_configs(dtype_code, k, arr, n)
     if m < 0:
         check(m)
-    return [(o.variant, o.tile_w, o.tile_h, o.group, o.form) for o in arr[:n]]
+    return [(o.variant, o.tile_w, o.tile_h, o.group, o.form, o.rows) for o in arr[:n]]
 
 
 def query_config(dtype_code: int, k: int, variant: int = MF_VARIANT_AUTO, tile=None):

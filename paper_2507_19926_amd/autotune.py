@@ -6,7 +6,7 @@ type (Section 4.3); this script does that for this library. It enumerates the
 configurations the library was built with (``mf_list_configs``), times each on
 a seeded synthetic plane of the class's dtype, and writes a JSON table:
 
-    {"p16": {"<k>": [variant, tile_w, tile_h, group, form], ...},
+    {"p16": {"<k>": [variant, tile_w, tile_h, group, form, rows], ...},
      "u32": {...}, "device": ..., "timings_ms": {...}}
 
 ``p16`` covers uint8/uint16 (two 16-bit values per VGPR), ``u32`` covers
@@ -31,8 +31,8 @@ CLASSES = {"p16": 0, "u32": 2}   # class -> representative mf_dtype
 def _time_config(x, y, k, cfg, reps, stream):
     import torch
     from .ops import median_filter
-    variant, tw, th, group, form = cfg
-    kw = dict(variant=variant, tile=(tw, th), group=group, form=form, out=y)
+    variant, tw, th, group, form, rows = cfg
+    kw = dict(variant=variant, tile=(tw, th), group=group, form=form, rows=rows, out=y)
     median_filter(x, k, **kw)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -32,9 +32,10 @@ ARCH = "gfx950"
 OBL_CONFIGS = [
     (3, 2, 1, 8, 4), (3, 2, 1, 8, 1), (3, 1, 1, 8, 4), (3, 2, 2, 4, 4),
     (3, 2, 1, 8, 4, True), (3, 2, 2, 4, 4, True), (3, 2, 2, 8, 1, True),
+    (3, 2, 1, 2, 4), (3, 2, 2, 1, 4), (3, 2, 1, 2, 4, True), (3, 2, 2, 1, 4, True),
     (5, 4, 2, 2, 4), (5, 4, 2, 4, 1), (5, 2, 2, 2, 4),
-    (5, 4, 2, 2, 4, True), (5, 2, 2, 4, 4, True),
-    (7, 4, 2, 2, 4), (7, 4, 2, 4, 1), (7, 2, 2, 2, 4),
+    (5, 4, 2, 2, 4, True), (5, 2, 2, 4, 4, True), (5, 4, 2, 1, 4), (5, 2, 2, 1, 4, True),
+    (7, 4, 2, 2, 4), (7, 4, 2, 4, 1), (7, 2, 2, 2, 4), (7, 4, 2, 1, 4),
     (9, 4, 4, 1, 4), (9, 4, 4, 2, 1), (9, 8, 2, 1, 4),
     (11, 4, 4, 1, 4), (11, 4, 4, 2, 1), (11, 4, 2, 2, 4),
     (13, 4, 4, 1, 4), (13, 4, 4, 1, 1),
@@ -62,7 +63,7 @@ def _compile(src: str, obj: str, extra=()) -> tuple[str, str]:
 
 def _write_auto_table() -> None:
     """AUTO choices per (value class, k) from tuned.json (autotune.py), as
-    MF_AUTO(class, k, variant, tile_w, tile_h, group, form) lines; class 0 = 8/16-bit,
+    MF_AUTO(class, k, variant, tile_w, tile_h, group, form, rows) lines; class 0 = 8/16-bit,
     1 = 32-bit. Without tuned.json the table is empty and the library falls
     back to its built-in order (oblivious first)."""
     import json
@@ -75,7 +76,9 @@ def _write_auto_table() -> None:
             for k, cfg in sorted(t.get(cls, {}).items(), key=lambda kv: int(kv[0])):
                 variant, tw, th, group = cfg[:4]
                 form = cfg[4] if len(cfg) > 4 else 0
-                lines.append("MF_AUTO(%d, %d, %d, %d, %d, %d, %d)" % (code, int(k), variant, tw, th, group, form))
+                rows = cfg[5] if len(cfg) > 5 else 0
+                lines.append("MF_AUTO(%d, %d, %d, %d, %d, %d, %d, %d)"
+                             % (code, int(k), variant, tw, th, group, form, rows))
     text = "\n".join(lines) + "\n"
     out = os.path.join(GEN, "mf_auto_table.inc")
     if not os.path.exists(out) or open(out).read() != text:

@@ -37,13 +37,13 @@ constexpr int kMaxK = 75;
 
 // Measured AUTO choices (class 0: 8/16-bit data, class 1: 32-bit data).
 struct AutoEntry {
-    int cls, k, variant, tw, th, group, form;
+    int cls, k, variant, tw, th, group, form, rows;
 };
 const AutoEntry kAutoTable[] = {
-#define MF_AUTO(C, K, V, TW, TH, G, F) {C, K, V, TW, TH, G, F},
+#define MF_AUTO(C, K, V, TW, TH, G, F, R) {C, K, V, TW, TH, G, F, R},
 #include "mf_auto_table.inc"
 #undef MF_AUTO
-    {-1, 0, 0, 0, 0, 0, 0}};
+    {-1, 0, 0, 0, 0, 0, 0, 0}};
 
 thread_local std::string g_last_error;
 
@@ -72,12 +72,12 @@ int elem_size(int32_t dtype)
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
-const OblEntry* find_obl(int k, int tw, int th, int nw, int form)
+const OblEntry* find_obl(int k, int tw, int th, int nw, int form, int rows)
 {
     for (int i = 0; i < kOblCount; ++i) {
         const OblEntry& e = kOblTable[i];
         if (e.k == k && (tw == 0 || e.tw == tw) && (th == 0 || e.th == th) && (nw == 0 || e.nw == nw) &&
-            (form == 0 || (form == 2) == (e.inl != 0)))
+            (form == 0 || (form == 2) == (e.inl != 0)) && (rows == 0 || e.ry == rows))
             return &e;  // the table lists each k's preferred configuration first
     }
     return nullptr;
@@ -101,12 +101,13 @@ int32_t resolve(int32_t dtype, int32_t k, const mf_options* opt, int32_t* varian
     if (o.form < 0 || o.form > 2) return fail(MF_ERR_CONFIG, "form %d not in {0, 1, 2}", o.form);
     *obl = nullptr;
     // measured choice for this (value class, k), when nothing was requested
-    if (o.variant == MF_VARIANT_AUTO && !o.tile_w && !o.tile_h && !o.group && !o.form) {
+    if (o.rows < 0) return fail(MF_ERR_CONFIG, "rows %d must be >= 0", o.rows);
+    if (o.variant == MF_VARIANT_AUTO && !o.tile_w && !o.tile_h && !o.group && !o.form && !o.rows) {
         const int cls = (dtype == MF_U8 || dtype == MF_U16) ? 0 : 1;
         for (const AutoEntry& a : kAutoTable) {
             if (a.cls != cls || a.k != k) continue;
             if (a.variant == MF_VARIANT_OBLIVIOUS) {
-                const OblEntry* e = find_obl(k, a.tw, a.th, a.group, a.form);
+                const OblEntry* e = find_obl(k, a.tw, a.th, a.group, a.form, a.rows);
                 if (e) {
                     *variant = MF_VARIANT_OBLIVIOUS;
                     *tw = e->tw;
@@ -126,7 +127,7 @@ int32_t resolve(int32_t dtype, int32_t k, const mf_options* opt, int32_t* varian
     }
     if (o.variant != MF_VARIANT_DATA_AWARE) {
         const OblEntry* e =
-            find_obl(k, o.tile_w, o.tile_h, o.group == 1 || o.group == 4 ? o.group : 0, o.form);
+            find_obl(k, o.tile_w, o.tile_h, o.group == 1 || o.group == 4 ? o.group : 0, o.form, o.rows);
         if (e) {
             *variant = MF_VARIANT_OBLIVIOUS;
             *tw = e->tw;
@@ -315,6 +316,7 @@ int32_t mf_list_configs(int32_t dtype, int32_t k, mf_options* out, int32_t cap)
                 out[n].tile_h = kOblTable[i].th;
                 out[n].group = kOblTable[i].nw;
                 out[n].form = kOblTable[i].inl ? 2 : 1;
+                out[n].rows = kOblTable[i].ry;
             }
             ++n;
         }
@@ -327,6 +329,7 @@ int32_t mf_list_configs(int32_t dtype, int32_t k, mf_options* out, int32_t cap)
                 out[n].tile_h = th[i];
                 out[n].group = gr[i];
                 out[n].form = 0;
+                out[n].rows = 0;
             }
             ++n;
         }

@@ -25,7 +25,7 @@ def _stream_handle(dev: torch.device):
 
 def median_filter(x: torch.Tensor, k: int, out: torch.Tensor | None = None,
                   variant: int = _lib.MF_VARIANT_AUTO, tile=None, group: int = 0,
-                  form: int = 0) -> torch.Tensor:
+                  form: int = 0, rows: int = 0) -> torch.Tensor:
     """Exact k x k median (replicate border) of every (H, W) plane of x.
 
     x: a device tensor of shape (..., H, W) whose last dimension is contiguous;
@@ -47,7 +47,7 @@ def median_filter(x: torch.Tensor, k: int, out: torch.Tensor | None = None,
     es = x.element_size()
     pitch = x.stride(-2) * es
     stream = _stream_handle(x.device)
-    opt = _lib.options(variant, tile, group, form)
+    opt = _lib.options(variant, tile, group, form, rows)
     L = _lib.lib()
     planes_x = x.reshape(-1, H, W) if x.dim() > 2 else x.unsqueeze(0)
     planes_o = out.reshape(-1, H, W) if out.dim() > 2 else out.unsqueeze(0)

@@ -41,16 +41,16 @@ def test_gpu_present():
     assert name.startswith("gfx950"), name
 
 
-OBL = [(c[0], c[1], c[2], c[4], 2 if (len(c) > 5 and c[5]) else 1) for c in mfbuild.OBL_CONFIGS]
+OBL = [(c[0], c[1], c[2], c[4], 2 if (len(c) > 5 and c[5]) else 1, c[3]) for c in mfbuild.OBL_CONFIGS]
 
 
-@pytest.mark.parametrize("k,tw,th,nw,form", OBL)
+@pytest.mark.parametrize("k,tw,th,nw,form,rows", OBL)
 @pytest.mark.parametrize("dtype", DTYPES)
-def test_oblivious_configs_match_oracle(k, tw, th, nw, form, dtype):
+def test_oblivious_configs_match_oracle(k, tw, th, nw, form, rows, dtype):
     # ragged: several work-groups in each direction plus partial tiles
     H, W = 45 + 7 * k, 1100 + k
     img = _img(dtype, H, W, seed=k * 10 + tw)
-    got = _gpu(img, k, variant=_lib.MF_VARIANT_OBLIVIOUS, tile=(tw, th), group=nw, form=form)
+    got = _gpu(img, k, variant=_lib.MF_VARIANT_OBLIVIOUS, tile=(tw, th), group=nw, form=form, rows=rows)
     want = oracle.median_filter(img, k)
     if not _eq(got, want):
         bad = np.argwhere(got.view(np.uint8).reshape(H, -1) != want.view(np.uint8).reshape(H, -1))
@@ -154,12 +154,12 @@ def test_full_size_rgb30_sampled(k):
         assert np.array_equal(got[c][ys, xs], want), (k, c)
 
 
-@pytest.mark.parametrize("k,tw,th,nw,form", [c for c in OBL if c[0] in (3, 9, 17)])
-def test_oblivious_large_image_persistent(k, tw, th, nw, form):
+@pytest.mark.parametrize("k,tw,th,nw,form,rows", [c for c in OBL if c[0] in (3, 9, 17)])
+def test_oblivious_large_image_persistent(k, tw, th, nw, form, rows):
     """A plane big enough for the persistent launch (several blocks per
     work-group), checked at sampled pixels."""
     img = wl.uniform_plane(2100, 3000, np.uint8, seed=k + nw)
-    got = _gpu(img, k, variant=_lib.MF_VARIANT_OBLIVIOUS, tile=(tw, th), group=nw, form=form)
+    got = _gpu(img, k, variant=_lib.MF_VARIANT_OBLIVIOUS, tile=(tw, th), group=nw, form=form, rows=rows)
     g = wl.rng(k)
     ys = np.concatenate([[0, 2099, 0, 2099], g.integers(0, 2100, 3000)])
     xs = np.concatenate([[0, 0, 2999, 2999], g.integers(0, 3000, 3000)])
