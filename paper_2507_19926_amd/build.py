@@ -41,6 +41,7 @@ OBL_CONFIGS = [
     (13, 4, 4, 1, 4), (13, 4, 4, 1, 1),
     (15, 4, 4, 1, 4), (15, 4, 4, 1, 1),
     (17, 4, 4, 1, 4), (17, 4, 4, 1, 1),
+    (19, 4, 4, 1, 4),
 ]
 
 HIP_FLAGS = [

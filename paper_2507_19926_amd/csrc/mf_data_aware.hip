@@ -11,7 +11,7 @@
 //
 // Each round is a list of merge-path chunks: a lane finds the chunk's start in
 // its two sorted input windows with a co-rank binary search and then merges
-// up to 32 outputs sequentially. A work-group holds T root tiles (T arenas)
+// up to 16 outputs sequentially. A work-group holds T root tiles (T arenas)
 // that share the schedule; a lane runs its chunk for the T tiles side by side,
 // so T independent chains of LDS reads are in flight per lane. Only the ranks
 // some later step can read are produced (forgetting and pruning as output
@@ -33,7 +33,7 @@ struct DaEntry {
 const DaEntry kDaTable[] = {MF_DA_TABLE_ENTRIES};
 constexpr int kDaCount = sizeof(kDaTable) / sizeof(kDaTable[0]);
 
-constexpr int kDaThreads = 256;
+constexpr int kDaThreads = 512;
 
 }  // namespace
 

@@ -355,38 +355,41 @@ static hipError_t mf_obl_launch(const void* src, void* dst, int H, int W, long l
     const int bh = NW * RY * NET::TH;
     const int nbx = (W + bw - 1) / bw, nby = (H + bh - 1) / bh;
     const int nblocks = nbx * nby;
-    // resident work-groups of the persistent form, once per process from the
-    // occupancy calculator. 0 (never persistent) when the persistent form
-    // would spill to scratch or fit fewer work-groups per CU than the plain
-    // form: its prefetch registers live across the networks.
-    static int resident = -1;
-    if (resident < 0) {
-        int per_cu = 0, per_cu_plain = 0, dev = 0, cus = 0;
-        hipFuncAttributes attr;
-        const void* fn = (const void*)mf_obl_kernel_persistent<NET, V, RY, NW>;
-        if (hipFuncGetAttributes(&attr, fn) != hipSuccess || attr.localSizeBytes > 0 ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mf_obl_kernel_persistent<NET, V, RY, NW>, 64 * NW,
-                                                         0) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_plain, mf_obl_kernel<NET, V, RY, NW>, 64 * NW, 0) !=
-                hipSuccess ||
-            per_cu < 1 || per_cu < per_cu_plain) {
-            resident = 0;
-        } else {
-            if (hipGetDevice(&dev) != hipSuccess ||
-                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-                cus = 256;
-            resident = per_cu * cus;
+    if constexpr (NET::PERSISTENT) {
+        // resident work-groups of the persistent form, once per process from
+        // the occupancy calculator. 0 (never persistent) when the persistent
+        // form would spill to scratch or fit fewer work-groups per CU than the
+        // plain form: its prefetch registers live across the networks.
+        static int resident = -1;
+        if (resident < 0) {
+            int per_cu = 0, per_cu_plain = 0, dev = 0, cus = 0;
+            hipFuncAttributes attr;
+            const void* fn = (const void*)mf_obl_kernel_persistent<NET, V, RY, NW>;
+            if (hipFuncGetAttributes(&attr, fn) != hipSuccess || attr.localSizeBytes > 0 ||
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mf_obl_kernel_persistent<NET, V, RY, NW>,
+                                                             64 * NW, 0) != hipSuccess ||
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_plain, mf_obl_kernel<NET, V, RY, NW>, 64 * NW,
+                                                             0) != hipSuccess ||
+                per_cu < 1 || per_cu < per_cu_plain) {
+                resident = 0;
+            } else {
+                if (hipGetDevice(&dev) != hipSuccess ||
+                    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+                    cus = 256;
+                resident = per_cu * cus;
+            }
+        }
+        if (resident > 0 && nblocks > 2 * resident) {
+            const int per = (nblocks + resident - 1) / resident;
+            const int grid = (nblocks + per - 1) / per;
+            hipLaunchKernelGGL((mf_obl_kernel_persistent<NET, V, RY, NW>), dim3(grid), dim3(64 * NW), 0, stream,
+                               (const unsigned char*)src, (unsigned char*)dst, H, W, pitch, dtype, nbx, nblocks,
+                               per);
+            return hipGetLastError();
         }
     }
-    if (resident == 0 || nblocks <= 2 * resident) {
-        hipLaunchKernelGGL((mf_obl_kernel<NET, V, RY, NW>), dim3(nblocks), dim3(64 * NW), 0, stream,
-                           (const unsigned char*)src, (unsigned char*)dst, H, W, pitch, dtype, nbx);
-        return hipGetLastError();
-    }
-    const int per = (nblocks + resident - 1) / resident;
-    const int grid = (nblocks + per - 1) / per;
-    hipLaunchKernelGGL((mf_obl_kernel_persistent<NET, V, RY, NW>), dim3(grid), dim3(64 * NW), 0, stream,
-                       (const unsigned char*)src, (unsigned char*)dst, H, W, pitch, dtype, nbx, nblocks, per);
+    hipLaunchKernelGGL((mf_obl_kernel<NET, V, RY, NW>), dim3(nblocks), dim3(64 * NW), 0, stream,
+                       (const unsigned char*)src, (unsigned char*)dst, H, W, pitch, dtype, nbx);
     return hipGetLastError();
 }
 

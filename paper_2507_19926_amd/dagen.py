@@ -39,7 +39,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-CHUNK = 32          # outputs per merge-path chunk
+CHUNK = 16          # outputs per merge-path chunk
 OFF_BITS = 18       # arena offsets and sizes share a 32-bit word
 MAX_OFF = 1 << OFF_BITS
 MAX_LEN = 1 << (32 - OFF_BITS)
