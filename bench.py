@@ -307,21 +307,21 @@ def main():
         t = time.perf_counter()
         oracle.median_filter(base[0], args.k, rows=(0, probe), nthreads=nthreads)
         dt = time.perf_counter() - t
-        # rows of the frame (plane after plane) that take about cpu_seconds
-        rows = int(min(3 * H, max(probe, probe * args.cpu_seconds / max(dt, 1e-6))))
+        # rows of the frame (plane after plane, whole frames repeated if one
+        # frame is shorter than that) that take about cpu_seconds
+        rows = int(min(8 * 3 * H, max(probe, probe * args.cpu_seconds / max(dt, 1e-6))))
         t = time.perf_counter()
         done = 0
-        for c in range(3):
-            n = min(H, rows - done)
-            if n <= 0:
-                break
-            oracle.median_filter(base[c], args.k, rows=(0, n), nthreads=nthreads)
+        while done < rows:
+            c = (done // H) % 3
+            n = min(H - done % H, rows - done)
+            oracle.median_filter(base[c], args.k, rows=(done % H, done % H + n), nthreads=nthreads)
             done += n
         dt = time.perf_counter() - t
         cpu = {"value": round(done * W / dt / 1e6, 3), "unit": "Mpixel/s", "cores": nthreads,
                "kind": "oracle",
-               "sample": "%d of the %d rows of the 3-plane frame (%d px) at k=%d, %.1f s"
-                         % (done, 3 * H, done * W, args.k, dt)}
+               "sample": "%d rows of 6720 px (%.2f passes over the 3-plane frame, %d px) at k=%d, %.1f s"
+                         % (done, done / (3 * H), done * W, args.k, dt)}
 
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mpixel/s", "n_gpus": 1,
