@@ -14,7 +14,9 @@
 // wave-local), so one wave's load and sort phases overlap the networks of the
 // other waves of the CU.
 //   1. The union of the block's footprints is read from HBM once (coalesced,
-//      replicate border by clamping) into LDS.
+//      replicate border by clamping) into LDS. The persistent form copies the
+//      next block's union with LDS-direct loads while this block's networks
+//      run.
 //   2. Every footprint column segment over a tile row's core rows is sorted
 //      once by one lane (odd-even merge sort in registers) and written back
 //      to LDS: horizontally adjacent tiles share these sorted columns
@@ -71,11 +73,18 @@ struct MfObGeom {
     // the 8-element margin of the fast-path test
     static constexpr int NDMAX = (COLS * (PACK ? 2 : 4) + 6) / 4;
     static constexpr int U = (ROWS * NDMAX + NT - 1) / NT;
+    // Staging buffer of the persistent form: every footprint row as whole
+    // 16-byte chunks of the source row. A row needs the dwords the commit
+    // reads, which end at most 18 bytes past SPAN elements from the first
+    // chunk's start (see mf_obl_stage_commit).
+    static constexpr int SPAN = PACK ? BWH + COLS : COLS;   // elements of a row, both halves
+    static constexpr int NCH = (18 + SPAN * (PACK ? 2 : 4) + 15) / 16;   // chunks per row, widest type
+    // whole 64-chunk groups: one wave instruction fills 64 consecutive chunks
+    static constexpr int STG_CHUNKS = (ROWS * NCH + 63) / 64 * 64;
 };
 
-// Global loads of one block's footprint union, held in registers between
-// issue and commit so that they can be in flight while the previous block's
-// network runs.
+// Global loads of one block's footprint union (plain and batched forms),
+// issued all at once into registers, then scattered into LDS.
 template <class V, int K, int TW, int TH, int RY, int NW>
 struct MfObPrefetch {
     using G = MfObGeom<V, K, TW, TH, RY, NW>;
@@ -114,65 +123,58 @@ mf_obl_issue(const unsigned char* __restrict__ src, int H, int W, long long pitc
     }
 }
 
-// Footprint union -> LDS raw buffer (swizzled layout), from the prefetched
-// registers or, for edge blocks, by clamped element loads.
+// Scatter the elements of one source dword into the raw buffer's row. b0 is
+// the footprint column of the dword's byte 0 (may be negative); vb is the
+// dword at the same position of the right half (packed types only).
 template <class V, int K, int TW, int TH, int RY, int NW>
-__device__ __forceinline__ void
-mf_obl_commit(const unsigned char* __restrict__ src, int H, int W, long long pitch, int dtype, int X0, int Y0,
-              const MfObPrefetch<V, K, TW, TH, RY, NW>& pf, V* __restrict__ raw)
+__device__ __forceinline__ void mf_obl_put_dword(V* __restrict__ rrow, int b0, uint32_t va, uint32_t vb, int es,
+                                                 int dtype)
 {
     using G = MfObGeom<V, K, TW, TH, RY, NW>;
     constexpr int Q = G::Q, COLS = G::COLS;
-    const int es = G::PACK ? (dtype == MF_U8 ? 1 : 2) : 4;
-    const int gx0 = X0 - G::R;
-    if (pf.fast) {
-        const int nd = (COLS * es + 6) / 4;
+    if constexpr (G::PACK) {
+        if (es == 1) {
 #pragma unroll
-        for (int u = 0; u < G::U; ++u) {
-            const int it = threadIdx.x + u * G::NT;
-            if (it < G::ROWS * nd) {
-                const int rho = it / nd, d = it - rho * nd;
-                const int gy = mf_clampi(Y0 - G::R + rho, 0, H - 1);
-                const uintptr_t a = (uintptr_t)(src + (long long)gy * pitch + (long long)gx0 * es);
-                const int lead = (int)(a & 3);            // bytes before the segment start
-                const int b0 = 4 * d - lead;              // segment byte of this dword's byte 0
-                V* rrow = raw + rho * TW * Q;
-                if constexpr (G::PACK) {
-                    if (es == 1) {
+            for (int b = 0; b < 4; ++b) {
+                const int c = b0 + b;
+                if (c >= 0 && c < COLS) {
+                    V v;
+                    v.x = (va >> (8 * b)) & 0xFF;
+                    v.y = (vb >> (8 * b)) & 0xFF;
+                    rrow[(c % TW) * Q + c / TW] = v;
+                }
+            }
+        } else {
 #pragma unroll
-                        for (int b = 0; b < 4; ++b) {
-                            const int c = b0 + b;
-                            if (c >= 0 && c < COLS) {
-                                V v;
-                                v.x = (pf.va[u] >> (8 * b)) & 0xFF;
-                                v.y = (pf.vb[u] >> (8 * b)) & 0xFF;
-                                rrow[(c % TW) * Q + c / TW] = v;
-                            }
-                        }
-                    } else {
-#pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            const int c = (b0 >> 1) + h;  // b0 is even for 16-bit data
-                            if (c >= 0 && c < COLS) {
-                                V v;
-                                v.x = (pf.va[u] >> (16 * h)) & 0xFFFF;
-                                v.y = (pf.vb[u] >> (16 * h)) & 0xFFFF;
-                                rrow[(c % TW) * Q + c / TW] = v;
-                            }
-                        }
-                    }
-                } else {
-                    const int c = b0 >> 2;                // 32-bit data is always aligned
-                    if (c >= 0 && c < COLS) {
-                        uint32_t b = pf.va[u];
-                        if (dtype == MF_F32) b = mf_f32_to_key(b);
-                        rrow[(c % TW) * Q + c / TW] = b;
-                    }
+            for (int h = 0; h < 2; ++h) {
+                const int c = (b0 >> 1) + h;  // b0 is even for 16-bit data
+                if (c >= 0 && c < COLS) {
+                    V v;
+                    v.x = (va >> (16 * h)) & 0xFFFF;
+                    v.y = (vb >> (16 * h)) & 0xFFFF;
+                    rrow[(c % TW) * Q + c / TW] = v;
                 }
             }
         }
-        return;
+    } else {
+        const int c = b0 >> 2;                // 32-bit data is always aligned
+        if (c >= 0 && c < COLS) {
+            uint32_t b = va;
+            if (dtype == MF_F32) b = mf_f32_to_key(b);
+            rrow[(c % TW) * Q + c / TW] = b;
+        }
     }
+}
+
+// Footprint union with clamped coordinates, element by element (blocks at
+// the left or right image edge).
+template <class V, int K, int TW, int TH, int RY, int NW>
+__device__ __forceinline__ void
+mf_obl_load_clamped(const unsigned char* __restrict__ src, int H, int W, long long pitch, int dtype, int X0, int Y0,
+                    V* __restrict__ raw)
+{
+    using G = MfObGeom<V, K, TW, TH, RY, NW>;
+    constexpr int Q = G::Q, COLS = G::COLS;
     for (int w = threadIdx.x; w < G::ROWS * COLS; w += G::NT) {
         const int rho = w / COLS, c = w - rho * COLS;
         const int gy = mf_clampi(Y0 - G::R + rho, 0, H - 1);
@@ -194,6 +196,103 @@ mf_obl_commit(const unsigned char* __restrict__ src, int H, int W, long long pit
             v = b;
         }
         raw[(rho * TW + c % TW) * Q + c / TW] = v;
+    }
+}
+
+// Footprint union -> LDS raw buffer (swizzled layout), from the prefetched
+// registers or, for edge blocks, by clamped element loads.
+template <class V, int K, int TW, int TH, int RY, int NW>
+__device__ __forceinline__ void
+mf_obl_commit(const unsigned char* __restrict__ src, int H, int W, long long pitch, int dtype, int X0, int Y0,
+              const MfObPrefetch<V, K, TW, TH, RY, NW>& pf, V* __restrict__ raw)
+{
+    using G = MfObGeom<V, K, TW, TH, RY, NW>;
+    constexpr int Q = G::Q, COLS = G::COLS;
+    const int es = G::PACK ? (dtype == MF_U8 ? 1 : 2) : 4;
+    const int gx0 = X0 - G::R;
+    if (pf.fast) {
+        const int nd = (COLS * es + 6) / 4;
+#pragma unroll
+        for (int u = 0; u < G::U; ++u) {
+            const int it = threadIdx.x + u * G::NT;
+            if (it < G::ROWS * nd) {
+                const int rho = it / nd, d = it - rho * nd;
+                const int gy = mf_clampi(Y0 - G::R + rho, 0, H - 1);
+                const uintptr_t a = (uintptr_t)(src + (long long)gy * pitch + (long long)gx0 * es);
+                const int lead = (int)(a & 3);            // bytes before the segment start
+                mf_obl_put_dword<V, K, TW, TH, RY, NW>(raw + rho * TW * Q, 4 * d - lead, pf.va[u],
+                                                       G::PACK ? pf.vb[u] : 0u, es, dtype);
+            }
+        }
+        return;
+    }
+    mf_obl_load_clamped<V, K, TW, TH, RY, NW>(src, H, W, pitch, dtype, X0, Y0, raw);
+}
+
+// Persistent form, stage 1a: start copying the footprint union of block
+// (X0, Y0) from HBM into the LDS staging buffer with LDS-direct buffer loads
+// (buffer_load_dwordx4 ... lds), which use no registers, so the copy runs
+// while the networks of the current block execute. Row rho of the footprint
+// lands in chunks [rho * nch, (rho + 1) * nch) as the 16-byte-aligned source
+// bytes from the chunk holding its first element. Returns false (nothing
+// issued) for blocks whose chunks would leave the source rows (left/right
+// image edge) and when the caller's buffers are not 16-byte aligned; those
+// blocks take the clamped element loads instead.
+template <class V, int K, int TW, int TH, int RY, int NW>
+__device__ __forceinline__ bool
+mf_obl_stage_issue(const unsigned char* __restrict__ src, int H, int W, long long pitch, int dtype, int X0, int Y0,
+                   int aligned, uint4* stage)
+{
+    using G = MfObGeom<V, K, TW, TH, RY, NW>;
+    const int es = G::PACK ? (dtype == MF_U8 ? 1 : 2) : 4;
+    const int gx0 = X0 - G::R;
+    const int cb = (gx0 * es) & ~15;                  // first chunk, bytes from the row start
+    const int nch = (18 + G::SPAN * es + 15) >> 4;
+    if (!aligned || gx0 < 0 || cb + 16 * nch > W * es) return false;
+    const int gyb = mf_clampi(Y0 - G::R, 0, H - 1);
+    const int gyl = mf_clampi(Y0 - G::R + G::ROWS - 1, 0, H - 1);
+    // the descriptor covers exactly the footprint's rows (the host checks
+    // that ROWS * pitch fits in 31 bits)
+    const uint32_t nrec = (uint32_t)((long long)(gyl - gyb) * pitch + (long long)W * es);
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(src + (long long)gyb * pitch), (short)0, (int)nrec, 0x00020000);
+    const int total = G::ROWS * nch;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    for (int first = wv * 64; first < total; first += G::NT) {
+        const int i = first + lane;
+        if (i < total) {
+            const int rho = i / nch, ch = i - rho * nch;
+            const int gy = mf_clampi(Y0 - G::R + rho, 0, H - 1);
+            const uint32_t off = (uint32_t)((long long)(gy - gyb) * pitch) + (uint32_t)(cb + 16 * ch);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(stage + first),
+                                                     16, off, 0, 0, 0);
+        }
+    }
+    return true;
+}
+
+// Persistent form, stage 1b: staging buffer -> raw buffer (swizzled, packed
+// layout). Reads the same dwords as the register path: dword d of row rho
+// starts at footprint column 4d - lead, at staging byte (gx0*es mod 16) rounded
+// down to 4, plus 4d (+ BWH*es for the right half); the last byte read is below
+// 12 + 4*nd + BWH*es <= 18 + SPAN*es, inside the row's nch chunks.
+template <class V, int K, int TW, int TH, int RY, int NW>
+__device__ __forceinline__ void mf_obl_stage_commit(const uint4* stage, int dtype, int X0, V* __restrict__ raw)
+{
+    using G = MfObGeom<V, K, TW, TH, RY, NW>;
+    constexpr int Q = G::Q, COLS = G::COLS;
+    const int es = G::PACK ? (dtype == MF_U8 ? 1 : 2) : 4;
+    const int gx0 = X0 - G::R;
+    const int nch = (18 + G::SPAN * es + 15) >> 4;
+    const int a4 = ((gx0 * es) & 15) >> 2, lead = (gx0 * es) & 3;
+    const int nd = (COLS * es + 6) / 4;
+    const uint32_t* st = (const uint32_t*)stage;
+    for (int it = threadIdx.x; it < G::ROWS * nd; it += G::NT) {
+        const int rho = it / nd, d = it - rho * nd;
+        const uint32_t* srow = st + rho * nch * 4 + a4;
+        const uint32_t va = srow[d];
+        const uint32_t vb = G::PACK ? srow[d + G::BWH * es / 4] : 0u;
+        mf_obl_put_dword<V, K, TW, TH, RY, NW>(raw + rho * TW * Q, 4 * d - lead, va, vb, es, dtype);
     }
 }
 
@@ -277,34 +376,44 @@ mf_obl_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ 
 }
 
 // Persistent form: work-group w filters blocks [w*per, (w+1)*per) in
-// row-major order (neighbouring blocks, and their shared halos, stay on one
-// CU and one L2). The next block's global loads are issued before the
-// current block's networks run, so their latency hides behind VALU work.
+// column-major order, so consecutive blocks of a work-group are vertical
+// neighbours whose shared halo rows are still in this XCD's L2. The next
+// block's footprint is copied into the LDS staging buffer by LDS-direct loads
+// issued before the current block's networks run; their latency hides behind
+// the networks and they hold no registers.
 template <class NET, class V, int RY, int NW>
 __global__ void __launch_bounds__(64 * NW)
 mf_obl_kernel_persistent(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
-                         int H, int W, long long pitch, int dtype, int nbx, int nblocks, int per)
+                         int H, int W, long long pitch, int dtype, int nby, int nblocks, int per, int aligned)
 {
     using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY, NW>;
     __shared__ V raw[G::ROWS * NET::TW * G::Q];
     __shared__ V colb[NET::INLINE_COLS ? 1 : G::TY * NET::LC * NET::TW * G::Q];
+    __shared__ uint4 stage[G::STG_CHUNKS];
     const int b0 = blockIdx.x * per;
     const int b1 = min(b0 + per, nblocks);
     if (b0 >= b1) return;
     const int bw = G::PACK ? 2 * G::BWH : G::BWH, bh = G::TY * NET::TH;
-    MfObPrefetch<V, NET::K, NET::TW, NET::TH, RY, NW> pf;
-    mf_obl_issue(src, H, W, pitch, dtype, (b0 % nbx) * bw, (b0 / nbx) * bh, pf);
+    bool staged = mf_obl_stage_issue<V, NET::K, NET::TW, NET::TH, RY, NW>(
+        src, H, W, pitch, dtype, (b0 / nby) * bw, (b0 % nby) * bh, aligned, stage);
     for (int b = b0; b < b1; ++b) {
-        const int X0 = (b % nbx) * bw, Y0 = (b / nbx) * bh;
-        __syncthreads();                       // previous networks are done with raw / colb
-        mf_obl_commit(src, H, W, pitch, dtype, X0, Y0, pf, raw);
+        const int X0 = (b / nby) * bw, Y0 = (b % nby) * bh;
+        // this wave's staging copies have landed; after the barrier everyone's
+        // have, and the previous networks are done with raw / colb
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
+        if (staged)
+            mf_obl_stage_commit<V, NET::K, NET::TW, NET::TH, RY, NW>(stage, dtype, X0, raw);
+        else
+            mf_obl_load_clamped<V, NET::K, NET::TW, NET::TH, RY, NW>(src, H, W, pitch, dtype, X0, Y0, raw);
+        __syncthreads();                       // raw is complete, stage is free
+        staged = b + 1 < b1 && mf_obl_stage_issue<V, NET::K, NET::TW, NET::TH, RY, NW>(
+                                   src, H, W, pitch, dtype, ((b + 1) / nby) * bw, ((b + 1) % nby) * bh, aligned,
+                                   stage);
         if constexpr (!NET::INLINE_COLS) {
             mf_obl_colsort<NET, V, RY, NW>(raw, colb);
             __syncthreads();
         }
-        if (b + 1 < b1)
-            mf_obl_issue(src, H, W, pitch, dtype, ((b + 1) % nbx) * bw, ((b + 1) / nbx) * bh, pf);
         mf_obl_networks<NET, V, RY, NW>(raw, colb, dst, H, W, pitch, dtype, X0, Y0);
     }
 }
@@ -382,9 +491,14 @@ static hipError_t mf_obl_launch(const void* src, void* dst, int H, int W, long l
         if (resident > 0 && nblocks > 2 * resident) {
             const int per = (nblocks + resident - 1) / resident;
             const int grid = (nblocks + per - 1) / per;
+            using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY, NW>;
+            // LDS-direct staging needs 16-byte aligned rows and buffer offsets
+            // of the footprint rows below 2^31
+            const int aligned = ((uintptr_t)src % 16 == 0 && pitch % 16 == 0 &&
+                                 (long long)(G::ROWS + 1) * pitch < (1LL << 31)) ? 1 : 0;
             hipLaunchKernelGGL((mf_obl_kernel_persistent<NET, V, RY, NW>), dim3(grid), dim3(64 * NW), 0, stream,
-                               (const unsigned char*)src, (unsigned char*)dst, H, W, pitch, dtype, nbx, nblocks,
-                               per);
+                               (const unsigned char*)src, (unsigned char*)dst, H, W, pitch, dtype, nby, nblocks,
+                               per, aligned);
             return hipGetLastError();
         }
     }

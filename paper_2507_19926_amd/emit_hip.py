@@ -108,7 +108,7 @@ def emit_config_tu(k: int, tw: int, th: int, shapes, inline: bool = False) -> st
         "struct %s {" % name,
         "    static constexpr int K = %d, TW = %d, TH = %d, LC = %d;" % (k, tw, th, lc),
         "    static constexpr bool INLINE_COLS = %s;" % ("true" if inline else "false"),
-        "    static constexpr bool PERSISTENT = %s;" % ("true" if k <= 17 else "false"),
+        "    static constexpr bool PERSISTENT = %s;" % ("true" if k <= 19 else "false"),
         "    template <class V> static __device__ __forceinline__ void sort_column(V* a) { mf_sort_%d(a); }" % lc,
         "    template <int Q, class V, class Sink>",
         "    static __device__ __forceinline__ void run(const V* __restrict__ col,",

@@ -154,6 +154,49 @@ def test_full_size_rgb30_sampled(k):
         assert np.array_equal(got[c][ys, xs], want), (k, c)
 
 
+def _check_rows_and_points(img, got, k, seed):
+    """Full rows at the top, bottom and across a block boundary (every column,
+    so both left/right edge blocks and interior blocks), plus random points."""
+    H, W = img.shape
+    for a, b in ((0, 24), (H // 2 - 12, H // 2 + 12), (H - 24, H)):
+        want = oracle.median_filter(img, k, rows=(a, b))
+        assert _eq(got[a:b], want), (k, a, b)
+    g = wl.rng(seed)
+    ys, xs = g.integers(0, H, 2000), g.integers(0, W, 2000)
+    assert np.array_equal(got[ys, xs], oracle.median_points(img, k, ys, xs))
+
+
+@pytest.mark.parametrize("k", [3, 9, 17, 19])
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("placement", ["aligned", "offset16", "offset4", "pitch_odd"])
+def test_persistent_staging_placements(k, dtype, placement):
+    """The persistent form stages footprints with LDS-direct 16-byte loads
+    when the rows are 16-byte aligned and falls back to element loads
+    otherwise: an aligned plane, a view starting 16 bytes into a buffer, a
+    view starting 4 bytes in (unaligned) and a pitch that is not a multiple of
+    16 must all give the oracle's result. The plane is big enough for several
+    blocks per work-group."""
+    H, W = 1500, 2600
+    img = _img(dtype, H, W, seed=k * 7 + len(placement))
+    es = np.dtype(dtype).itemsize
+    tdt = TORCH_DT[np.dtype(dtype)]
+    if placement == "aligned":
+        x = _dev(img)
+        out = torch.empty_like(x)
+    else:
+        lead = {"offset16": 16, "offset4": 4, "pitch_odd": 0}[placement] // es
+        pitch = W + 16 // es + (1 if placement == "pitch_odd" else 0)
+        n = H * pitch + lead + W
+        xb = torch.zeros(n * es, dtype=torch.uint8, device="cuda").view(tdt)
+        x = xb[lead:lead + H * pitch].view(H, pitch)[:, :W]
+        x.copy_(_dev(img))
+        ob = torch.zeros(n * es, dtype=torch.uint8, device="cuda").view(tdt)
+        out = ob[lead:lead + H * pitch].view(H, pitch)[:, :W]
+    median_filter(x, k, out=out)
+    torch.cuda.synchronize()
+    _check_rows_and_points(img, out.cpu().numpy(), k, seed=k)
+
+
 @pytest.mark.parametrize("k,tw,th,nw,form,rows", [c for c in OBL if c[0] in (3, 9, 17)])
 def test_oblivious_large_image_persistent(k, tw, th, nw, form, rows):
     """A plane big enough for the persistent launch (several blocks per
