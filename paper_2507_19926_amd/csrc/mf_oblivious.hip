@@ -175,7 +175,12 @@ mf_obl_load_clamped(const unsigned char* __restrict__ src, int H, int W, long lo
 {
     using G = MfObGeom<V, K, TW, TH, RY, NW>;
     constexpr int Q = G::Q, COLS = G::COLS;
-    for (int w = threadIdx.x; w < G::ROWS * COLS; w += G::NT) {
+    constexpr int UC = (G::ROWS * COLS + G::NT - 1) / G::NT;
+    // unrolled: every load of the thread is in flight at once
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+        const int w = threadIdx.x + u * G::NT;
+        if (w >= G::ROWS * COLS) break;
         const int rho = w / COLS, c = w - rho * COLS;
         const int gy = mf_clampi(Y0 - G::R + rho, 0, H - 1);
         const unsigned char* row = src + (long long)gy * pitch;
@@ -287,7 +292,11 @@ __device__ __forceinline__ void mf_obl_stage_commit(const uint4* stage, int dtyp
     const int a4 = ((gx0 * es) & 15) >> 2, lead = (gx0 * es) & 3;
     const int nd = (COLS * es + 6) / 4;
     const uint32_t* st = (const uint32_t*)stage;
-    for (int it = threadIdx.x; it < G::ROWS * nd; it += G::NT) {
+    // unrolled (nd <= NDMAX): the thread's LDS reads are all in flight at once
+#pragma unroll
+    for (int u = 0; u < G::U; ++u) {
+        const int it = threadIdx.x + u * G::NT;
+        if (it >= G::ROWS * nd) break;
         const int rho = it / nd, d = it - rho * nd;
         const uint32_t* srow = st + rho * nch * 4 + a4;
         const uint32_t va = srow[d];
@@ -303,6 +312,8 @@ __device__ __forceinline__ void mf_obl_colsort(const V* __restrict__ raw, V* __r
 {
     using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY, NW>;
     constexpr int TW = NET::TW, TH = NET::TH, LC = NET::LC, Q = G::Q, COLS = G::COLS;
+    // two column segments per thread in flight hide the LDS latency
+#pragma unroll 2
     for (int it = threadIdx.x; it < G::TY * COLS; it += G::NT) {
         const int j = it / COLS, c = it - j * COLS;
         V a[LC];
@@ -376,15 +387,15 @@ mf_obl_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ 
 }
 
 // Persistent form: work-group w filters blocks [w*per, (w+1)*per) in
-// column-major order, so consecutive blocks of a work-group are vertical
-// neighbours whose shared halo rows are still in this XCD's L2. The next
-// block's footprint is copied into the LDS staging buffer by LDS-direct loads
-// issued before the current block's networks run; their latency hides behind
-// the networks and they hold no registers.
+// row-major order (edge blocks, which load element by element, spread evenly
+// over the work-groups). The next block's footprint is copied into the LDS
+// staging buffer by LDS-direct loads issued before the current block's
+// networks run; their latency hides behind the networks and they hold no
+// registers.
 template <class NET, class V, int RY, int NW>
 __global__ void __launch_bounds__(64 * NW)
 mf_obl_kernel_persistent(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
-                         int H, int W, long long pitch, int dtype, int nby, int nblocks, int per, int aligned)
+                         int H, int W, long long pitch, int dtype, int nbx, int nblocks, int per, int aligned)
 {
     using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY, NW>;
     __shared__ V raw[G::ROWS * NET::TW * G::Q];
@@ -395,9 +406,9 @@ mf_obl_kernel_persistent(const unsigned char* __restrict__ src, unsigned char* _
     if (b0 >= b1) return;
     const int bw = G::PACK ? 2 * G::BWH : G::BWH, bh = G::TY * NET::TH;
     bool staged = mf_obl_stage_issue<V, NET::K, NET::TW, NET::TH, RY, NW>(
-        src, H, W, pitch, dtype, (b0 / nby) * bw, (b0 % nby) * bh, aligned, stage);
+        src, H, W, pitch, dtype, (b0 % nbx) * bw, (b0 / nbx) * bh, aligned, stage);
     for (int b = b0; b < b1; ++b) {
-        const int X0 = (b / nby) * bw, Y0 = (b % nby) * bh;
+        const int X0 = (b % nbx) * bw, Y0 = (b / nbx) * bh;
         // this wave's staging copies have landed; after the barrier everyone's
         // have, and the previous networks are done with raw / colb
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -408,7 +419,7 @@ mf_obl_kernel_persistent(const unsigned char* __restrict__ src, unsigned char* _
             mf_obl_load_clamped<V, NET::K, NET::TW, NET::TH, RY, NW>(src, H, W, pitch, dtype, X0, Y0, raw);
         __syncthreads();                       // raw is complete, stage is free
         staged = b + 1 < b1 && mf_obl_stage_issue<V, NET::K, NET::TW, NET::TH, RY, NW>(
-                                   src, H, W, pitch, dtype, ((b + 1) / nby) * bw, ((b + 1) % nby) * bh, aligned,
+                                   src, H, W, pitch, dtype, ((b + 1) % nbx) * bw, ((b + 1) / nbx) * bh, aligned,
                                    stage);
         if constexpr (!NET::INLINE_COLS) {
             mf_obl_colsort<NET, V, RY, NW>(raw, colb);
@@ -497,7 +508,7 @@ static hipError_t mf_obl_launch(const void* src, void* dst, int H, int W, long l
             const int aligned = ((uintptr_t)src % 16 == 0 && pitch % 16 == 0 &&
                                  (long long)(G::ROWS + 1) * pitch < (1LL << 31)) ? 1 : 0;
             hipLaunchKernelGGL((mf_obl_kernel_persistent<NET, V, RY, NW>), dim3(grid), dim3(64 * NW), 0, stream,
-                               (const unsigned char*)src, (unsigned char*)dst, H, W, pitch, dtype, nby, nblocks,
+                               (const unsigned char*)src, (unsigned char*)dst, H, W, pitch, dtype, nbx, nblocks,
                                per, aligned);
             return hipGetLastError();
         }
