@@ -56,6 +56,16 @@ template <> struct MfVTraits<uint32_t> { static constexpr bool PACK = false; };
 
 __device__ __forceinline__ int mf_clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
+// threadIdx.x as a value the compiler cannot see through: inside the
+// persistent loop, addresses derived from it are recomputed per block instead
+// of being hoisted out of the loop and held in registers across the networks.
+__device__ __forceinline__ int mf_tid()
+{
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 // Geometry of a block: the union of its tiles' footprints.
 template <class V, int K, int TW, int TH, int RY, int NW>
 struct MfObGeom {
@@ -107,9 +117,10 @@ mf_obl_issue(const unsigned char* __restrict__ src, int H, int W, long long pitc
     pf.fast = gx0 >= 4 && gx0 + span + 8 <= W;
     if (!pf.fast) return;
     const int nd = (G::COLS * es + 6) / 4;
+    const int tid = mf_tid();
 #pragma unroll
     for (int u = 0; u < G::U; ++u) {
-        const int it = threadIdx.x + u * G::NT;
+        const int it = tid + u * G::NT;
         pf.va[u] = 0;
         if constexpr (G::PACK) pf.vb[u] = 0;
         if (it < G::ROWS * nd) {
@@ -176,10 +187,11 @@ mf_obl_load_clamped(const unsigned char* __restrict__ src, int H, int W, long lo
     using G = MfObGeom<V, K, TW, TH, RY, NW>;
     constexpr int Q = G::Q, COLS = G::COLS;
     constexpr int UC = (G::ROWS * COLS + G::NT - 1) / G::NT;
+    const int tid = mf_tid();
     // unrolled: every load of the thread is in flight at once
 #pragma unroll
     for (int u = 0; u < UC; ++u) {
-        const int w = threadIdx.x + u * G::NT;
+        const int w = tid + u * G::NT;
         if (w >= G::ROWS * COLS) break;
         const int rho = w / COLS, c = w - rho * COLS;
         const int gy = mf_clampi(Y0 - G::R + rho, 0, H - 1);
@@ -217,9 +229,10 @@ mf_obl_commit(const unsigned char* __restrict__ src, int H, int W, long long pit
     const int gx0 = X0 - G::R;
     if (pf.fast) {
         const int nd = (COLS * es + 6) / 4;
+        const int tid = mf_tid();
 #pragma unroll
         for (int u = 0; u < G::U; ++u) {
-            const int it = threadIdx.x + u * G::NT;
+            const int it = tid + u * G::NT;
             if (it < G::ROWS * nd) {
                 const int rho = it / nd, d = it - rho * nd;
                 const int gy = mf_clampi(Y0 - G::R + rho, 0, H - 1);
@@ -262,7 +275,8 @@ mf_obl_stage_issue(const unsigned char* __restrict__ src, int H, int W, long lon
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc((void*)(src + (long long)gyb * pitch), (short)0, (int)nrec, 0x00020000);
     const int total = G::ROWS * nch;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int tid = mf_tid();
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     for (int first = wv * 64; first < total; first += G::NT) {
         const int i = first + lane;
         if (i < total) {
@@ -292,11 +306,9 @@ __device__ __forceinline__ void mf_obl_stage_commit(const uint4* stage, int dtyp
     const int a4 = ((gx0 * es) & 15) >> 2, lead = (gx0 * es) & 3;
     const int nd = (COLS * es + 6) / 4;
     const uint32_t* st = (const uint32_t*)stage;
-    // unrolled (nd <= NDMAX): the thread's LDS reads are all in flight at once
-#pragma unroll
-    for (int u = 0; u < G::U; ++u) {
-        const int it = threadIdx.x + u * G::NT;
-        if (it >= G::ROWS * nd) break;
+    const int tid = mf_tid();
+#pragma unroll 2
+    for (int it = tid; it < G::ROWS * nd; it += G::NT) {
         const int rho = it / nd, d = it - rho * nd;
         const uint32_t* srow = st + rho * nch * 4 + a4;
         const uint32_t va = srow[d];
@@ -312,9 +324,10 @@ __device__ __forceinline__ void mf_obl_colsort(const V* __restrict__ raw, V* __r
 {
     using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY, NW>;
     constexpr int TW = NET::TW, TH = NET::TH, LC = NET::LC, Q = G::Q, COLS = G::COLS;
+    const int tid = mf_tid();
     // two column segments per thread in flight hide the LDS latency
 #pragma unroll 2
-    for (int it = threadIdx.x; it < G::TY * COLS; it += G::NT) {
+    for (int it = tid; it < G::TY * COLS; it += G::NT) {
         const int j = it / COLS, c = it - j * COLS;
         V a[LC];
 #pragma unroll
@@ -327,40 +340,114 @@ __device__ __forceinline__ void mf_obl_colsort(const V* __restrict__ raw, V* __r
     }
 }
 
-// Per-lane hierarchical networks of one block, medians stored as produced.
-template <class NET, class V, int RY, int NW>
+// Per-lane hierarchical networks of one block. With OUT_LDS = false each
+// median is stored to HBM as soon as it is known; with OUT_LDS = true it goes
+// to the block's LDS output tile (no bounds checks, no branches) and
+// mf_obl_store_out writes the tile with 16-byte stores later.
+template <class NET, class V, int RY, int NW, bool OUT_LDS = false>
 __device__ __forceinline__ void
 mf_obl_networks(const V* __restrict__ raw, const V* __restrict__ colb, unsigned char* __restrict__ dst, int H,
-                int W, long long pitch, int dtype, int X0, int Y0)
+                int W, long long pitch, int dtype, int X0, int Y0, unsigned char* __restrict__ out = nullptr)
 {
     using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY, NW>;
     constexpr bool PACK = G::PACK;
     constexpr int TW = NET::TW, TH = NET::TH, LC = NET::LC, Q = G::Q, BWH = G::BWH;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int tid = mf_tid();
+    const int lane = tid & 63, wv = tid >> 6;
     for (int ry = 0; ry < RY; ++ry) {
         const int j = wv * RY + ry;
         const V* cb = colb + j * LC * TW * Q + lane;
         const V* rb = raw + j * TH * TW * Q + lane;
-        const int ty = Y0 + j * TH, tx = X0 + lane * TW;
-        auto sink = [&](int px, int py, V v) {
-            const int y = ty + py;
-            if (y >= H) return;
-            unsigned char* row = dst + (long long)y * pitch;
-            const int xa = tx + px;
-            if constexpr (PACK) {
-                const int xb = xa + BWH;
-                if (dtype == MF_U8) {
-                    if (xa < W) row[xa] = (unsigned char)v.x;
-                    if (xb < W) row[xb] = (unsigned char)v.y;
+        if constexpr (OUT_LDS) {
+            // packed: row-major tile of 2*BWH elements of es bytes per row
+            // (lanes write consecutive dwords for 8-bit data); 32-bit: planes
+            // (row, px) of 64 lane-consecutive words (conflict-free)
+            auto sink = [&](int px, int py, V v) {
+                const int y = j * TH + py;
+                if constexpr (PACK) {
+                    const int xa = lane * TW + px;
+                    if (dtype == MF_U8) {
+                        out[y * 2 * BWH + xa] = (unsigned char)v.x;
+                        out[y * 2 * BWH + xa + BWH] = (unsigned char)v.y;
+                    } else {
+                        ((uint16_t*)out)[y * 2 * BWH + xa] = v.x;
+                        ((uint16_t*)out)[y * 2 * BWH + xa + BWH] = v.y;
+                    }
                 } else {
-                    if (xa < W) ((uint16_t*)row)[xa] = v.x;
-                    if (xb < W) ((uint16_t*)row)[xb] = v.y;
+                    ((uint32_t*)out)[(y * TW + px) * 64 + lane] = (dtype == MF_F32) ? mf_key_to_f32(v) : v;
                 }
-            } else {
-                if (xa < W) ((uint32_t*)row)[xa] = (dtype == MF_F32) ? mf_key_to_f32(v) : v;
+            };
+            NET::template run<Q>(cb, rb, sink);
+        } else {
+            const int ty = Y0 + j * TH, tx = X0 + lane * TW;
+            auto sink = [&](int px, int py, V v) {
+                const int y = ty + py;
+                if (y >= H) return;
+                unsigned char* row = dst + (long long)y * pitch;
+                const int xa = tx + px;
+                if constexpr (PACK) {
+                    const int xb = xa + BWH;
+                    if (dtype == MF_U8) {
+                        if (xa < W) row[xa] = (unsigned char)v.x;
+                        if (xb < W) row[xb] = (unsigned char)v.y;
+                    } else {
+                        if (xa < W) ((uint16_t*)row)[xa] = v.x;
+                        if (xb < W) ((uint16_t*)row)[xb] = v.y;
+                    }
+                } else {
+                    if (xa < W) ((uint32_t*)row)[xa] = (dtype == MF_F32) ? mf_key_to_f32(v) : v;
+                }
+            };
+            NET::template run<Q>(cb, rb, sink);
+        }
+    }
+}
+
+// LDS output tile of block (X0, Y0) -> HBM: 16-byte stores when the block is
+// inside the image and the rows are 16-byte aligned, element stores with
+// bounds checks otherwise.
+template <class NET, class V, int RY, int NW>
+__device__ __forceinline__ void mf_obl_store_out(const unsigned char* __restrict__ out, unsigned char* __restrict__ dst,
+                                                 int H, int W, long long pitch, int dtype, int X0, int Y0,
+                                                 int aligned)
+{
+    using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY, NW>;
+    constexpr int TW = NET::TW, BH = G::TY * NET::TH;
+    constexpr int BW = G::PACK ? 2 * G::BWH : G::BWH;
+    const int es = G::PACK ? (dtype == MF_U8 ? 1 : 2) : 4;
+    const int cpr = BW * es / 16;                        // 16-byte chunks per tile row
+    const bool whole = aligned && X0 + BW <= W;
+    const int tid = mf_tid();
+#pragma unroll 2
+    for (int i = tid; i < BH * cpr; i += G::NT) {
+        const int y = i / cpr, cx = i - y * cpr;
+        if (Y0 + y >= H) break;                          // rows only grow with i
+        unsigned char* row = dst + (long long)(Y0 + y) * pitch + (long long)X0 * es;
+        uint32_t w[4];
+        if constexpr (G::PACK) {
+            const uint4 q = *(const uint4*)(out + y * BW * es + cx * 16);
+            w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int x = 4 * cx + e;
+                w[e] = ((const uint32_t*)out)[(y * TW + x % TW) * 64 + x / TW];
             }
-        };
-        NET::template run<Q>(cb, rb, sink);
+        }
+        if (whole) {
+            *(uint4*)(row + cx * 16) = make_uint4(w[0], w[1], w[2], w[3]);
+        } else {
+            const int x0 = cx * 16 / es;                 // first element of the chunk
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int x = x0 + e / es;
+                if (e % es == 0 && X0 + x < W) {
+                    if (es == 1) row[x] = (unsigned char)(w[e / 4] >> (8 * (e % 4)));
+                    else if (es == 2) ((uint16_t*)row)[x] = (uint16_t)(w[e / 4] >> (8 * (e % 4)));
+                    else ((uint32_t*)row)[x] = w[e / 4];
+                }
+            }
+        }
     }
 }
 
@@ -388,45 +475,59 @@ mf_obl_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ 
 
 // Persistent form: work-group w filters blocks [w*per, (w+1)*per) in
 // row-major order (edge blocks, which load element by element, spread evenly
-// over the work-groups). The next block's footprint is copied into the LDS
-// staging buffer by LDS-direct loads issued before the current block's
-// networks run; their latency hides behind the networks and they hold no
-// registers.
+// over the work-groups), with no work-group turnover between blocks. Per
+// block:
+//   * the footprint union was copied into the LDS staging buffer by
+//     LDS-direct loads issued during the previous block's networks (no
+//     registers held, latency hidden); it is scattered into the raw buffer;
+//   * the previous block's medians go from the LDS output tile to HBM with
+//     16-byte stores, which complete during this block's networks;
+//   * the next block's staging copy is issued, columns are sorted, and the
+//     networks write this block's medians into the output tile.
 template <class NET, class V, int RY, int NW>
 __global__ void __launch_bounds__(64 * NW)
 mf_obl_kernel_persistent(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
                          int H, int W, long long pitch, int dtype, int nbx, int nblocks, int per, int aligned)
 {
     using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY, NW>;
+    constexpr int BW = G::PACK ? 2 * G::BWH : G::BWH, BH = G::TY * NET::TH;
     __shared__ V raw[G::ROWS * NET::TW * G::Q];
     __shared__ V colb[NET::INLINE_COLS ? 1 : G::TY * NET::LC * NET::TW * G::Q];
     __shared__ uint4 stage[G::STG_CHUNKS];
+    __shared__ uint4 out[BH * BW * (G::PACK ? 2 : 4) / 16];
+    static_assert(sizeof(raw) + sizeof(colb) + sizeof(stage) + sizeof(out) <= 160 * 1024, "LDS budget");
     const int b0 = blockIdx.x * per;
     const int b1 = min(b0 + per, nblocks);
     if (b0 >= b1) return;
-    const int bw = G::PACK ? 2 * G::BWH : G::BWH, bh = G::TY * NET::TH;
     bool staged = mf_obl_stage_issue<V, NET::K, NET::TW, NET::TH, RY, NW>(
-        src, H, W, pitch, dtype, (b0 % nbx) * bw, (b0 / nbx) * bh, aligned, stage);
+        src, H, W, pitch, dtype, (b0 % nbx) * BW, (b0 / nbx) * BH, aligned, stage);
     for (int b = b0; b < b1; ++b) {
-        const int X0 = (b % nbx) * bw, Y0 = (b / nbx) * bh;
-        // this wave's staging copies have landed; after the barrier everyone's
-        // have, and the previous networks are done with raw / colb
+        const int X0 = (b % nbx) * BW, Y0 = (b / nbx) * BH;
+        // this wave's staging copies and stores have completed; after the
+        // barrier everyone's have, and the previous networks are done
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         if (staged)
             mf_obl_stage_commit<V, NET::K, NET::TW, NET::TH, RY, NW>(stage, dtype, X0, raw);
         else
             mf_obl_load_clamped<V, NET::K, NET::TW, NET::TH, RY, NW>(src, H, W, pitch, dtype, X0, Y0, raw);
-        __syncthreads();                       // raw is complete, stage is free
+        if (b > b0)
+            mf_obl_store_out<NET, V, RY, NW>((const unsigned char*)out, dst, H, W, pitch, dtype,
+                                             ((b - 1) % nbx) * BW, ((b - 1) / nbx) * BH, aligned);
+        __syncthreads();                       // raw complete; stage and out free
         staged = b + 1 < b1 && mf_obl_stage_issue<V, NET::K, NET::TW, NET::TH, RY, NW>(
-                                   src, H, W, pitch, dtype, ((b + 1) % nbx) * bw, ((b + 1) / nbx) * bh, aligned,
+                                   src, H, W, pitch, dtype, ((b + 1) % nbx) * BW, ((b + 1) / nbx) * BH, aligned,
                                    stage);
         if constexpr (!NET::INLINE_COLS) {
             mf_obl_colsort<NET, V, RY, NW>(raw, colb);
             __syncthreads();
         }
-        mf_obl_networks<NET, V, RY, NW>(raw, colb, dst, H, W, pitch, dtype, X0, Y0);
+        mf_obl_networks<NET, V, RY, NW, true>(raw, colb, dst, H, W, pitch, dtype, X0, Y0,
+                                              (unsigned char*)out);
     }
+    __syncthreads();
+    mf_obl_store_out<NET, V, RY, NW>((const unsigned char*)out, dst, H, W, pitch, dtype, ((b1 - 1) % nbx) * BW,
+                                     ((b1 - 1) / nbx) * BH, aligned);
 }
 
 template <class NET, class V, int RY, int NW>
@@ -503,9 +604,9 @@ static hipError_t mf_obl_launch(const void* src, void* dst, int H, int W, long l
             const int per = (nblocks + resident - 1) / resident;
             const int grid = (nblocks + per - 1) / per;
             using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY, NW>;
-            // LDS-direct staging needs 16-byte aligned rows and buffer offsets
-            // of the footprint rows below 2^31
-            const int aligned = ((uintptr_t)src % 16 == 0 && pitch % 16 == 0 &&
+            // LDS-direct staging and 16-byte output stores need 16-byte
+            // aligned rows; buffer offsets of the footprint rows stay below 2^31
+            const int aligned = ((uintptr_t)src % 16 == 0 && (uintptr_t)dst % 16 == 0 && pitch % 16 == 0 &&
                                  (long long)(G::ROWS + 1) * pitch < (1LL << 31)) ? 1 : 0;
             hipLaunchKernelGGL((mf_obl_kernel_persistent<NET, V, RY, NW>), dim3(grid), dim3(64 * NW), 0, stream,
                                (const unsigned char*)src, (unsigned char*)dst, H, W, pitch, dtype, nbx, nblocks,

@@ -22,40 +22,12 @@ import os
 from . import netgen as ng
 
 
-# LDS loads are issued this many min/max ops ahead of their first use (about
-# the LDS latency at one wave per SIMD: ~40 ops x 4 cycles), and the compiler
-# may reorder only within windows of WINDOW ops, so the distance survives
-# scheduling.
-LOAD_LEAD = 40
-WINDOW = 16
-
-
-def hoisted_order(P: ng.Prog, order: list[int], lead: int = LOAD_LEAD) -> list[int]:
-    """The demand order with every load moved `lead` min/max ops before the
-    first op that reads it (or to the start)."""
-    alu = [v for v in order if P.ops[v][0] != ng.LD]
-    first_use = {}
-    for j, v in enumerate(alu):
-        for a in P.ops[v][1:3]:
-            first_use.setdefault(a, j)
-    slots: dict[int, list[int]] = {}
-    for v in order:
-        if P.ops[v][0] == ng.LD:
-            slots.setdefault(max(0, first_use.get(v, 0) - lead), []).append(v)
-    out = []
-    for j, v in enumerate(alu):
-        out.extend(slots.get(j, ()))
-        out.append(v)
-    return out
-
-
 def _net_body(P: ng.Prog, k: int, tw: int, th: int, indent: str = "    ") -> list[str]:
     """Emit the live ops. Every load stays inside the root footprint
     (x < k+tw-1, y < k+th-1) and the sorted column length (i < k-th+1): the
     kernel's LDS buffers are sized for exactly that."""
     lines = []
-    order = hoisted_order(P, ng.demand_order(P))
-    nalu = 0
+    order = ng.demand_order(P)
     out_index = {}
     for i, o in enumerate(P.outputs):
         out_index.setdefault(o, []).append(i)
@@ -72,9 +44,6 @@ def _net_body(P: ng.Prog, k: int, tw: int, th: int, indent: str = "    ") -> lis
                 assert 0 <= x < k + tw - 1 and 0 <= y < k + th - 1, op
                 lines.append("%sconst V v%d = raw[(%d) * Q + %d];" % (indent, v, y * tw + x % tw, x // tw))
         else:
-            if nalu % WINDOW == 0 and nalu:
-                lines.append("%s__builtin_amdgcn_sched_barrier(0);" % indent)
-            nalu += 1
             lines.append("%sconst V v%d = %s(v%d, v%d);"
                          % (indent, v, "vmin" if op[0] == ng.MIN else "vmax", op[1], op[2]))
         for i in out_index.get(v, ()):
@@ -138,7 +107,7 @@ def emit_config_tu(k: int, tw: int, th: int, shapes, inline: bool = False) -> st
         "struct %s {" % name,
         "    static constexpr int K = %d, TW = %d, TH = %d, LC = %d;" % (k, tw, th, lc),
         "    static constexpr bool INLINE_COLS = %s;" % ("true" if inline else "false"),
-        "    static constexpr bool PERSISTENT = %s;" % ("true" if k <= 19 else "false"),
+        "    static constexpr bool PERSISTENT = %s;" % ("true" if k <= 17 else "false"),
         "    template <class V> static __device__ __forceinline__ void sort_column(V* a) { mf_sort_%d(a); }" % lc,
         "    template <int Q, class V, class Sink>",
         "    static __device__ __forceinline__ void run(const V* __restrict__ col,",
