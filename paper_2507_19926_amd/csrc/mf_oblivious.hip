@@ -252,26 +252,32 @@ mf_obl_commit(const unsigned char* __restrict__ src, int H, int W, long long pit
 // (buffer_load_dwordx4 ... lds), which use no registers, so the copy runs
 // while the networks of the current block execute. Row rho of the footprint
 // lands in chunks [rho * nch, (rho + 1) * nch) as the 16-byte-aligned source
-// bytes from the chunk holding its first element. Returns false (nothing
-// issued) for blocks whose chunks would leave the source rows (left/right
-// image edge) and when the caller's buffers are not 16-byte aligned; those
-// blocks take the clamped element loads instead.
+// bytes from cb, the chunk holding the row's first in-image element.
+// Returns 1 for blocks whose footprint columns are all inside the image, 2
+// for blocks at the left or right edge (commit clamps columns), 0 (nothing
+// issued) when the caller's rows are not 16-byte aligned, or when the chunks
+// would read past the end of the plane (right-edge blocks whose footprint
+// reaches the last row); those blocks load element by element instead.
+// Chunks may run past the end of a row into the next one (never past the
+// last row's data): such bytes are never used.
 template <class V, int K, int TW, int TH, int RY, int NW>
-__device__ __forceinline__ bool
+__device__ __forceinline__ int
 mf_obl_stage_issue(const unsigned char* __restrict__ src, int H, int W, long long pitch, int dtype, int X0, int Y0,
                    int aligned, uint4* stage)
 {
     using G = MfObGeom<V, K, TW, TH, RY, NW>;
     const int es = G::PACK ? (dtype == MF_U8 ? 1 : 2) : 4;
     const int gx0 = X0 - G::R;
-    const int cb = (gx0 * es) & ~15;                  // first chunk, bytes from the row start
+    const int cb = (max(gx0, 0) * es) & ~15;          // first chunk, bytes from the row start
     const int nch = (18 + G::SPAN * es + 15) >> 4;
-    if (!aligned || gx0 < 0 || cb + 16 * nch > W * es) return false;
+    const long long ce = cb + 16 * nch, row_bytes = (long long)W * es;
     const int gyb = mf_clampi(Y0 - G::R, 0, H - 1);
     const int gyl = mf_clampi(Y0 - G::R + G::ROWS - 1, 0, H - 1);
-    // the descriptor covers exactly the footprint's rows (the host checks
-    // that ROWS * pitch fits in 31 bits)
-    const uint32_t nrec = (uint32_t)((long long)(gyl - gyb) * pitch + (long long)W * es);
+    if (!aligned || !(ce <= row_bytes || (ce <= row_bytes + pitch && gyl < H - 1))) return 0;
+    // the descriptor covers the footprint's rows, up to the last chunk's end
+    // (the host checks that ROWS * pitch fits in 31 bits); anything past it
+    // would read as 0
+    const uint32_t nrec = (uint32_t)((long long)(gyl - gyb) * pitch + max(row_bytes, ce));
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc((void*)(src + (long long)gyb * pitch), (short)0, (int)nrec, 0x00020000);
     const int total = G::ROWS * nch;
@@ -287,7 +293,47 @@ mf_obl_stage_issue(const unsigned char* __restrict__ src, int H, int W, long lon
                                                      16, off, 0, 0, 0);
         }
     }
-    return true;
+    return (gx0 >= 0 && gx0 + G::SPAN <= W) ? 1 : 2;
+}
+
+// Persistent form, stage 1b for edge blocks: staging buffer -> raw buffer
+// with clamped columns. The element of global column gx sits at staging byte
+// gx*es - cb of its row; for every gx the block uses,
+// max(gx0, 0) <= gx <= gx0 + SPAN - 1, so it lies in [0, 16*nch).
+template <class V, int K, int TW, int TH, int RY, int NW>
+__device__ __forceinline__ void mf_obl_stage_commit_clamped(const uint4* stage, int W, int dtype, int X0,
+                                                            V* __restrict__ raw)
+{
+    using G = MfObGeom<V, K, TW, TH, RY, NW>;
+    constexpr int Q = G::Q, COLS = G::COLS;
+    const int es = G::PACK ? (dtype == MF_U8 ? 1 : 2) : 4;
+    const int gx0 = X0 - G::R;
+    const int cb = (max(gx0, 0) * es) & ~15;
+    const int nch = (18 + G::SPAN * es + 15) >> 4;
+    const unsigned char* st = (const unsigned char*)stage;
+    const int tid = mf_tid();
+#pragma unroll 4
+    for (int w = tid; w < G::ROWS * COLS; w += G::NT) {
+        const int rho = w / COLS, c = w - rho * COLS;
+        const unsigned char* srow = st + rho * nch * 16;
+        const int gxa = mf_clampi(gx0 + c, 0, W - 1) * es - cb;
+        V v;
+        if constexpr (G::PACK) {
+            const int gxb = mf_clampi(gx0 + G::BWH + c, 0, W - 1) * es - cb;
+            if (es == 1) {
+                v.x = srow[gxa];
+                v.y = srow[gxb];
+            } else {
+                v.x = *(const uint16_t*)(srow + gxa);
+                v.y = *(const uint16_t*)(srow + gxb);
+            }
+        } else {
+            uint32_t b = *(const uint32_t*)(srow + gxa);
+            if (dtype == MF_F32) b = mf_f32_to_key(b);
+            v = b;
+        }
+        raw[(rho * TW + c % TW) * Q + c / TW] = v;
+    }
 }
 
 // Persistent form, stage 1b: staging buffer -> raw buffer (swizzled, packed
@@ -474,9 +520,8 @@ mf_obl_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ 
 }
 
 // Persistent form: work-group w filters blocks [w*per, (w+1)*per) in
-// row-major order (edge blocks, which load element by element, spread evenly
-// over the work-groups), with no work-group turnover between blocks. Per
-// block:
+// row-major order (edge blocks spread evenly over the work-groups), with no
+// work-group turnover between blocks. Per block:
 //   * the footprint union was copied into the LDS staging buffer by
 //     LDS-direct loads issued during the previous block's networks (no
 //     registers held, latency hidden); it is scattered into the raw buffer;
@@ -499,7 +544,7 @@ mf_obl_kernel_persistent(const unsigned char* __restrict__ src, unsigned char* _
     const int b0 = blockIdx.x * per;
     const int b1 = min(b0 + per, nblocks);
     if (b0 >= b1) return;
-    bool staged = mf_obl_stage_issue<V, NET::K, NET::TW, NET::TH, RY, NW>(
+    int staged = mf_obl_stage_issue<V, NET::K, NET::TW, NET::TH, RY, NW>(
         src, H, W, pitch, dtype, (b0 % nbx) * BW, (b0 / nbx) * BH, aligned, stage);
     for (int b = b0; b < b1; ++b) {
         const int X0 = (b % nbx) * BW, Y0 = (b / nbx) * BH;
@@ -507,15 +552,17 @@ mf_obl_kernel_persistent(const unsigned char* __restrict__ src, unsigned char* _
         // barrier everyone's have, and the previous networks are done
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
-        if (staged)
+        if (staged == 1)
             mf_obl_stage_commit<V, NET::K, NET::TW, NET::TH, RY, NW>(stage, dtype, X0, raw);
+        else if (staged == 2)
+            mf_obl_stage_commit_clamped<V, NET::K, NET::TW, NET::TH, RY, NW>(stage, W, dtype, X0, raw);
         else
             mf_obl_load_clamped<V, NET::K, NET::TW, NET::TH, RY, NW>(src, H, W, pitch, dtype, X0, Y0, raw);
         if (b > b0)
             mf_obl_store_out<NET, V, RY, NW>((const unsigned char*)out, dst, H, W, pitch, dtype,
                                              ((b - 1) % nbx) * BW, ((b - 1) / nbx) * BH, aligned);
         __syncthreads();                       // raw complete; stage and out free
-        staged = b + 1 < b1 && mf_obl_stage_issue<V, NET::K, NET::TW, NET::TH, RY, NW>(
+        staged = b + 1 >= b1 ? 0 : mf_obl_stage_issue<V, NET::K, NET::TW, NET::TH, RY, NW>(
                                    src, H, W, pitch, dtype, ((b + 1) % nbx) * BW, ((b + 1) / nbx) * BH, aligned,
                                    stage);
         if constexpr (!NET::INLINE_COLS) {
