@@ -73,7 +73,10 @@ typedef struct mf_options {
                          0 = library's                                      */
     int32_t form;     /* oblivious: 1 = columns sorted once per work-group and
                          shared by the tiles, 2 = each tile sorts its own
-                         columns (small k); 0 = library's                   */
+                         columns (small k), 3 = column-strip streaming form
+                         (k = 3 only: root tile 1x1, each sorted column
+                         shared by three windows, rows streamed through
+                         registers); 0 = library's                          */
     int32_t rows;     /* oblivious: tile rows per wave; 0 = library's       */
 } mf_options;
 

@@ -17,8 +17,11 @@
 
 namespace {
 
+// form: 1 = column segments sorted once per work-group and shared, 2 = each
+// tile sorts its own columns, 3 = column-strip streaming form (k = 3, no
+// batched kernel of its own).
 struct OblEntry {
-    int k, tw, th, ry, nw, inl;
+    int k, tw, th, ry, nw, form;
     mf_launch_fn p16, u32;
     void (*batched_p16)(MfBatchedKernel*);
     void (*batched_u32)(MfBatchedKernel*);
@@ -26,10 +29,11 @@ struct OblEntry {
 
 const OblEntry kOblTable[] = {
 #define MF_OBL_ENTRY(NET, K, TW, TH, RY, NW, INL)                                                    \
-    {K, TW, TH, RY, NW, INL, MF_OBL_NAME(NET, RY, NW, p16), MF_OBL_NAME(NET, RY, NW, u32),          \
+    {K, TW, TH, RY, NW, (INL) ? 2 : 1, MF_OBL_NAME(NET, RY, NW, p16), MF_OBL_NAME(NET, RY, NW, u32), \
      MF_OBL_BATCHED_NAME(NET, RY, NW, p16), MF_OBL_BATCHED_NAME(NET, RY, NW, u32)},
 #include "mf_obl_table.inc"
 #undef MF_OBL_ENTRY
+    {3, 1, 1, 16, 4, 3, mf_strip3_launch_p16, mf_strip3_launch_u32, nullptr, nullptr},
 };
 constexpr int kOblCount = sizeof(kOblTable) / sizeof(kOblTable[0]);
 
@@ -72,12 +76,13 @@ int elem_size(int32_t dtype)
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// The column-strip form is only returned when asked for (form 3).
 const OblEntry* find_obl(int k, int tw, int th, int nw, int form, int rows)
 {
     for (int i = 0; i < kOblCount; ++i) {
         const OblEntry& e = kOblTable[i];
         if (e.k == k && (tw == 0 || e.tw == tw) && (th == 0 || e.th == th) && (nw == 0 || e.nw == nw) &&
-            (form == 0 || (form == 2) == (e.inl != 0)) && (rows == 0 || e.ry == rows))
+            (form == 0 ? e.form != 3 : e.form == form) && (rows == 0 || e.ry == rows))
             return &e;  // the table lists each k's preferred configuration first
     }
     return nullptr;
@@ -98,7 +103,7 @@ int32_t resolve(int32_t dtype, int32_t k, const mf_options* opt, int32_t* varian
         o.tile_w < 0 || o.tile_h < 0)
         return fail(MF_ERR_CONFIG, "root tile %dx%d is not a pair of powers of two <= k=%d", o.tile_w,
                     o.tile_h, k);
-    if (o.form < 0 || o.form > 2) return fail(MF_ERR_CONFIG, "form %d not in {0, 1, 2}", o.form);
+    if (o.form < 0 || o.form > 3) return fail(MF_ERR_CONFIG, "form %d not in {0, 1, 2, 3}", o.form);
     *obl = nullptr;
     // measured choice for this (value class, k), when nothing was requested
     if (o.rows < 0) return fail(MF_ERR_CONFIG, "rows %d must be >= 0", o.rows);
@@ -196,6 +201,9 @@ int32_t mf_internal_resolve(int32_t dtype, int32_t k, int32_t* variant, int32_t*
     const OblEntry* e = nullptr;
     int32_t rc = resolve(dtype, k, nullptr, variant, tw, th, &e, group);
     if (rc) return rc;
+    // the column-strip form has no batched kernel: plans use k's default
+    // network
+    if (e && e->form == 3) e = find_obl(k, 0, 0, 0, 0, 0);
     if (e) {
         e->batched_p16(obl_p16);
         e->batched_u32(obl_u32);
@@ -315,7 +323,7 @@ int32_t mf_list_configs(int32_t dtype, int32_t k, mf_options* out, int32_t cap)
                 out[n].tile_w = kOblTable[i].tw;
                 out[n].tile_h = kOblTable[i].th;
                 out[n].group = kOblTable[i].nw;
-                out[n].form = kOblTable[i].inl ? 2 : 1;
+                out[n].form = kOblTable[i].form;
                 out[n].rows = kOblTable[i].ry;
             }
             ++n;

@@ -43,6 +43,12 @@ struct MfBatchedKernel {
     void MF_OBL_BATCHED_NAME(NET, RY, NW, p16)(MfBatchedKernel*);                 \
     void MF_OBL_BATCHED_NAME(NET, RY, NW, u32)(MfBatchedKernel*);
 
+// Column-strip form for k = 3 (mf_strip.hip), per value class.
+hipError_t mf_strip3_launch_p16(const void* src, void* dst, int H, int W, long long pitch, int dtype,
+                                hipStream_t stream);
+hipError_t mf_strip3_launch_u32(const void* src, void* dst, int H, int W, long long pitch, int dtype,
+                                hipStream_t stream);
+
 // Data-aware launcher: one per value class, any k up to mf_max_k().
 hipError_t mf_da_launch(const void* src, void* dst, int H, int W, long long pitch,
                         int dtype, int k, int tw, int th, int group, hipStream_t stream);

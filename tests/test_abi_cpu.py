@@ -80,6 +80,27 @@ def test_query_config():
     assert _lib.lib().mf_max_k() >= 75
 
 
+def test_strip_form_listed_and_resolved():
+    """The column-strip form exists for k = 3 only, is the last oblivious
+    entry (never the default), and a request for it resolves to root tile
+    1x1."""
+    for dtype in range(4):
+        cfgs = _lib.list_configs(dtype, 3)
+        obl = [c for c in cfgs if c[0] == _lib.MF_VARIANT_OBLIVIOUS]
+        assert obl[-1] == (_lib.MF_VARIANT_OBLIVIOUS, 1, 1, 4, 3, 16)
+        assert cfgs[0][4] != 3
+        assert all(c[4] != 3 for c in _lib.list_configs(dtype, 5))
+    L = _lib.lib()
+    v, tw, th = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    o = _lib.options(_lib.MF_VARIANT_OBLIVIOUS, (1, 1), 4, 3, 16)
+    assert L.mf_query_config(0, 3, ctypes.byref(o), ctypes.byref(v), ctypes.byref(tw), ctypes.byref(th)) == 0
+    assert (v.value, tw.value, th.value) == (_lib.MF_VARIANT_OBLIVIOUS, 1, 1)
+    o = _lib.options(_lib.MF_VARIANT_OBLIVIOUS, None, 0, 3, 0)
+    assert L.mf_query_config(0, 5, ctypes.byref(o), ctypes.byref(v), ctypes.byref(tw), ctypes.byref(th)) == -10
+    o = _lib.options(_lib.MF_VARIANT_OBLIVIOUS, None, 0, 4, 0)
+    assert L.mf_query_config(0, 3, ctypes.byref(o), ctypes.byref(v), ctypes.byref(tw), ctypes.byref(th)) == -10
+
+
 def test_autograd_entry_validation():
     L = _lib.lib()
     A, B, C = 0x10000000, 0x20000000, 0x30000000

@@ -166,18 +166,11 @@ def _check_rows_and_points(img, got, k, seed):
     assert _eq(got[ys, xs], oracle.median_points(img, k, ys, xs))   # bit patterns (NaN payloads)
 
 
-@pytest.mark.parametrize("k", [3, 9, 17, 19])
-@pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("placement", ["aligned", "offset16", "offset4", "pitch_odd"])
-def test_persistent_staging_placements(k, dtype, placement):
-    """The persistent form stages footprints with LDS-direct 16-byte loads
-    when the rows are 16-byte aligned and falls back to element loads
-    otherwise: an aligned plane, a view starting 16 bytes into a buffer, a
-    view starting 4 bytes in (unaligned) and a pitch that is not a multiple of
-    16 must all give the oracle's result. The plane is big enough for several
-    blocks per work-group."""
-    H, W = 1500, 2600
-    img = _img(dtype, H, W, seed=k * 7 + len(placement))
+def _placed(img, dtype, placement):
+    """(x, out) device views of img: a plain tensor, or views into bigger
+    buffers starting 16 or 4 bytes in, or with a pitch that is not a multiple
+    of 16 bytes."""
+    H, W = img.shape
     es = np.dtype(dtype).itemsize
     tdt = TORCH_DT[np.dtype(dtype)]
     if placement == "aligned":
@@ -192,9 +185,56 @@ def test_persistent_staging_placements(k, dtype, placement):
         x.copy_(_dev(img))
         ob = torch.zeros(n * es, dtype=torch.uint8, device="cuda").view(tdt)
         out = ob[lead:lead + H * pitch].view(H, pitch)[:, :W]
+    return x, out
+
+
+PLACEMENTS = ["aligned", "offset16", "offset4", "pitch_odd"]
+
+
+@pytest.mark.parametrize("k", [3, 9, 17, 19])
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("placement", PLACEMENTS)
+def test_persistent_staging_placements(k, dtype, placement):
+    """The persistent form stages footprints with LDS-direct 16-byte loads
+    when the rows are 16-byte aligned and falls back to element loads
+    otherwise: an aligned plane, a view starting 16 bytes into a buffer, a
+    view starting 4 bytes in (unaligned) and a pitch that is not a multiple of
+    16 must all give the oracle's result. The plane is big enough for several
+    blocks per work-group."""
+    H, W = 1500, 2600
+    img = _img(dtype, H, W, seed=k * 7 + len(placement))
+    x, out = _placed(img, dtype, placement)
     median_filter(x, k, out=out)
     torch.cuda.synchronize()
     _check_rows_and_points(img, out.cpu().numpy(), k, seed=k)
+
+
+STRIP = dict(variant=_lib.MF_VARIANT_OBLIVIOUS, tile=(1, 1), group=4, form=3, rows=16)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("shape", [(1, 1), (1, 9), (7, 1), (2, 3), (17, 33), (63, 1023), (64, 1024),
+                                   (65, 1025), (130, 2049), (301, 4099)])
+def test_strip_form_k3(dtype, shape):
+    """Column-strip form (k = 3): whole images against the oracle, from one
+    pixel to several strips and work-groups in each direction with ragged
+    right and bottom edges (partial chunks, lanes past the image)."""
+    H, W = shape
+    img = _img(dtype, H, W, seed=H * 31 + W)
+    assert _eq(_gpu(img, 3, **STRIP), oracle.median_filter(img, 3))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("placement", PLACEMENTS)
+def test_strip_form_placements(dtype, placement):
+    """Column-strip form with 16-byte chunk loads and stores on aligned rows
+    and element loads and stores otherwise."""
+    H, W = 1500, 2600
+    img = _img(dtype, H, W, seed=5 + len(placement))
+    x, out = _placed(img, dtype, placement)
+    median_filter(x, 3, out=out, **STRIP)
+    torch.cuda.synchronize()
+    assert _eq(out.cpu().numpy(), oracle.median_filter(img, 3))
 
 
 @pytest.mark.parametrize("k,tw,th,nw,form,rows", [c for c in OBL if c[0] in (3, 9, 17)])
