@@ -44,7 +44,7 @@ def _time_config(x, y, k, cfg, reps, stream):
     return e0.elapsed_time(e1) / reps
 
 
-def tune(side: int = 2048, ks=None, verbose: bool = True) -> dict:
+def tune(shape=(4480, 6720), ks=None, verbose: bool = True) -> dict:
     import numpy as np
     import torch
 
@@ -52,11 +52,12 @@ def tune(side: int = 2048, ks=None, verbose: bool = True) -> dict:
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     ks = ks or list(range(3, 76, 2))
-    table = {"device": torch.cuda.get_device_properties(0).gcnArchName, "side": side,
+    H, W = shape
+    table = {"device": torch.cuda.get_device_properties(0).gcnArchName, "shape": [H, W],
              "timings_ms": {}}
     for cls, code in CLASSES.items():
         dt = np.uint8 if code == 0 else np.uint32
-        x = torch.from_numpy(wl.uniform_plane(side, side, dt, seed=77)).to(dev)
+        x = torch.from_numpy(wl.uniform_plane(H, W, dt, seed=77)).to(dev)
         y = torch.empty_like(x)
         best = {}
         for k in ks:
@@ -77,9 +78,10 @@ def tune(side: int = 2048, ks=None, verbose: bool = True) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=TUNED)
-    ap.add_argument("--side", type=int, default=2048)
+    ap.add_argument("--shape", type=int, nargs=2, default=(4480, 6720),
+                    help="plane rows and columns to time on (default: one 30 MP plane)")
     args = ap.parse_args()
-    t = tune(side=args.side)
+    t = tune(shape=tuple(args.shape))
     with open(args.out, "w") as f:
         json.dump(t, f, indent=1, sort_keys=True)
     print("wrote", args.out)

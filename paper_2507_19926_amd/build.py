@@ -42,6 +42,7 @@ OBL_CONFIGS = [
     (15, 4, 4, 1, 4), (15, 4, 4, 1, 1),
     (17, 4, 4, 1, 4), (17, 4, 4, 1, 1),
     (19, 4, 4, 1, 4),
+    (21, 4, 4, 1, 4),
 ]
 
 HIP_FLAGS = [
