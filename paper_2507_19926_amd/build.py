@@ -53,10 +53,24 @@ HIP_FLAGS = [
 ]
 
 
-def _compile(src: str, obj: str, extra=()) -> tuple[str, str]:
+def _up_to_date(obj: str) -> bool:
+    """True when obj and its dependency file exist and no dependency is newer."""
+    dep = obj + ".d"
+    if not (os.path.exists(obj) and os.path.exists(dep)):
+        return False
+    t = os.path.getmtime(obj)
+    with open(dep) as f:
+        text = f.read().replace("\\\n", " ")
+    files = text.split(":", 1)[1].split() if ":" in text else []
+    return all(os.path.exists(d) and os.path.getmtime(d) <= t for d in files)
+
+
+def _compile(src: str, obj: str, extra=(), incremental: bool = False) -> tuple[str, str]:
+    if incremental and _up_to_date(obj):
+        return obj, ""
     cmd = [HIPCC] + HIP_FLAGS + list(extra) + [
         "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-I", GEN,
-        "-c", src, "-o", obj]
+        "-MD", "-MF", obj + ".d", "-c", src, "-o", obj]
     p = subprocess.run(cmd, capture_output=True, text=True)
     if p.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), p.stderr[-6000:]))
@@ -88,8 +102,10 @@ def _write_auto_table() -> None:
             f.write(text)
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
-    """Generate, compile and link. Returns the path of libmedfilt.so."""
+def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
+    """Generate, compile and link. Returns the path of libmedfilt.so. With
+    incremental=True, objects whose sources and headers are unchanged since
+    they were compiled are reused."""
     os.makedirs(GEN, exist_ok=True)
     obl_srcs = emit_hip.generate(GEN, OBL_CONFIGS)
     _write_auto_table()
@@ -112,7 +128,9 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
             obj = os.path.join(BUILD, os.path.basename(s) + ".o")
             objs.append(obj)
             extra = ["-x", "hip"] if s.endswith(".hip") else []
-            futs.append(ex.submit(_compile, s, obj, extra))
+            # the schedule blob is pulled in by .incbin, which the dependency
+            # file does not list: always rebuilt
+            futs.append(ex.submit(_compile, s, obj, extra, incremental and s != blob_cpp))
         for f in futs:
             _, err = f.result()
             if verbose and err.strip():
@@ -133,4 +151,4 @@ def clean() -> None:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))

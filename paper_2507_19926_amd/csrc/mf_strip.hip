@@ -78,27 +78,37 @@ mf_strip3_kernel(const unsigned char* __restrict__ src, unsigned char* __restric
     const bool whole = aligned && x0 + P <= W; // the 16-byte chunk lies inside the row
 
     // the chunk of every input row y0-1 .. y0+R (replicate border by clamping)
+    // Each branch issues all of its loads before it uses any, so their
+    // latencies overlap (a wave at the right edge runs both branches).
     uint4 raw[R + 2];
     uint32_t hv[R + 2];                       // lane 0: pixel x0-1; lane 63: pixel x0+P
-    const bool edge_lane = lane == 0 || lane == 63;
-    const int hx = lane == 0 ? max(x0 - 1, 0) : min(x0 + P, W - 1);
+    if (whole) {
 #pragma unroll
-    for (int i = 0; i < R + 2; ++i) {
-        const int gy = min(max(y0 - 1 + i, 0), H - 1);
-        const unsigned char* row = src + (long long)gy * pitch;
-        if (whole) {
-            raw[i] = *(const uint4*)(row + (long long)x0 * ES);
-        } else {
+        for (int i = 0; i < R + 2; ++i) {
+            const int gy = min(max(y0 - 1 + i, 0), H - 1);
+            raw[i] = *(const uint4*)(src + (long long)gy * pitch + (long long)x0 * ES);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < R + 2; ++i) {
+            const int gy = min(max(y0 - 1 + i, 0), H - 1);
+            const unsigned char* row = src + (long long)gy * pitch;
             uint32_t w[4] = {0, 0, 0, 0};
 #pragma unroll
-            for (int e = 0; e < P; ++e) {
-                const uint32_t v = strip_load1<ES>(row, min(x0 + e, W - 1));
-                w[e * ES / 4] |= v << (8 * ((e * ES) % 4));
-            }
+            for (int e = 0; e < P; ++e)
+                w[e * ES / 4] |= strip_load1<ES>(row, min(x0 + e, W - 1)) << (8 * ((e * ES) % 4));
             raw[i] = make_uint4(w[0], w[1], w[2], w[3]);
         }
-        hv[i] = 0;
-        if (edge_lane) hv[i] = strip_load1<ES>(row, min(hx, W - 1));
+    }
+#pragma unroll
+    for (int i = 0; i < R + 2; ++i) hv[i] = 0;
+    if (lane == 0 || lane == 63) {
+        const int hx = lane == 0 ? max(x0 - 1, 0) : min(x0 + P, W - 1);
+#pragma unroll
+        for (int i = 0; i < R + 2; ++i) {
+            const int gy = min(max(y0 - 1 + i, 0), H - 1);
+            hv[i] = strip_load1<ES>(src + (long long)gy * pitch, hx);
+        }
     }
 
     // row i as P + 2 keys: [0] = column x0-1, [1..P] = the chunk, [P+1] = x0+P
