@@ -88,6 +88,16 @@ mf_strip3_kernel(const unsigned char* __restrict__ src, unsigned char* __restric
             const int gy = min(max(y0 - 1 + i, 0), H - 1);
             raw[i] = *(const uint4*)(src + (long long)gy * pitch + (long long)x0 * ES);
         }
+    } else if (x0 >= W) {
+        // past the right edge: every pixel is column W-1 (replicate border)
+#pragma unroll
+        for (int i = 0; i < R + 2; ++i) {
+            const int gy = min(max(y0 - 1 + i, 0), H - 1);
+            uint32_t v = strip_load1<ES>(src + (long long)gy * pitch, W - 1);
+            if constexpr (ES == 1) v *= 0x01010101u;
+            if constexpr (ES == 2) v *= 0x00010001u;
+            raw[i] = make_uint4(v, v, v, v);
+        }
     } else {
 #pragma unroll
         for (int i = 0; i < R + 2; ++i) {
