@@ -303,7 +303,8 @@ def main():
     if not args.no_cpu:
         import oracle  # CPU baseline only
         nthreads = len(os.sched_getaffinity(0))
-        probe = 16
+        probe = 64
+        oracle.median_filter(base[0], args.k, rows=(0, 16), nthreads=nthreads)   # warm-up (threads, caches)
         t = time.perf_counter()
         oracle.median_filter(base[0], args.k, rows=(0, probe), nthreads=nthreads)
         dt = time.perf_counter() - t
