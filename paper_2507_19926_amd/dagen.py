@@ -39,7 +39,9 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-CHUNK = 16          # outputs per merge-path chunk
+CHUNK = 4           # shortest merge-path chunk (outputs)
+LANES = 512         # threads of a data-aware work-group: a round's outputs are
+                    # cut into about this many chunks
 OFF_BITS = 18       # arena offsets and sizes share a 32-bit word
 MAX_OFF = 1 << OFF_BITS
 MAX_LEN = 1 << (32 - OFF_BITS)
@@ -247,7 +249,11 @@ def _window_inputs(n: Node):
     return res[0], res[1], r0
 
 
-def schedule(k: int, tw: int, th: int, chunk: int = CHUNK) -> Schedule:
+def schedule(k: int, tw: int, th: int, chunk: int = CHUNK, lanes: int = LANES) -> Schedule:
+    """Rounds of windowed merges for root tile tw x th. Every round's outputs
+    are cut into chunks of max(chunk, ceil(outputs / lanes)) so that one
+    round keeps about `lanes` threads busy with chains as short as the round
+    allows (a lane runs a co-rank search, then its chunk sequentially)."""
     D, outs = build_dag(k, tw, th)
     propagate_windows(D, outs)
     fw, fh = k + tw - 1, k + th - 1
@@ -314,12 +320,14 @@ def schedule(k: int, tw: int, th: int, chunk: int = CHUNK) -> Schedule:
     for r, group in enumerate(order):
         for n in group:
             n.off = alloc(n.need_hi - n.need_lo)
+        total = sum(n.need_hi - n.need_lo for n in group)
+        step = max(chunk, -(-total // lanes))
         for n in group:
             (aoff, na), (boff, nb), r0 = _window_inputs(n)
             nout = n.need_hi - n.need_lo
             assert 0 <= r0 and r0 + nout <= na + nb, (n.nid, r0, nout, na, nb)
-            for c0 in range(0, nout, chunk):
-                c = min(chunk, nout - c0)
+            for c0 in range(0, nout, step):
+                c = min(step, nout - c0)
                 for off in (aoff, boff, n.off + c0):
                     assert 0 <= off < MAX_OFF
                 assert na < MAX_LEN and nb < MAX_LEN and c < MAX_LEN
