@@ -94,6 +94,20 @@ int32_t median_filter_ex(const void* src, void* dst, int64_t H, int64_t W,
                          int64_t pitch_bytes, int32_t dtype, int32_t k,
                          int32_t border, const mf_options* opt, void* stream);
 
+/* As median_filter_ex, over `planes` planes of H x W in one launch (the
+ * channels of an image, a batch of equal-size images): plane p starts at
+ * src/dst + p * plane_stride_bytes. Every plane is filtered separately (no
+ * window crosses planes; the border rule applies per plane). planes = 1
+ * ignores plane_stride_bytes; otherwise it must be a multiple of the element
+ * size and at least (H-1)*pitch_bytes + W*element size (planes do not
+ * overlap), and the src and dst ranges of all planes must not overlap
+ * (MF_ERR_PITCH, MF_ERR_ALIAS). Filtering planes in one launch lets the
+ * persistent kernels balance blocks across planes. */
+int32_t median_filter_planes(const void* src, void* dst, int64_t planes,
+                             int64_t plane_stride_bytes, int64_t H, int64_t W,
+                             int64_t pitch_bytes, int32_t dtype, int32_t k,
+                             int32_t border, const mf_options* opt, void* stream);
+
 /* The configuration median_filter_ex would run for (dtype, k, opt): the
  * variant and root tile actually used. Host-only; no GPU needed. */
 int32_t mf_query_config(int32_t dtype, int32_t k, const mf_options* opt,

@@ -213,28 +213,56 @@ int32_t mf_internal_resolve(int32_t dtype, int32_t k, int32_t* variant, int32_t*
 
 extern "C" {
 
-int32_t median_filter_ex(const void* src, void* dst, int64_t H, int64_t W, int64_t pitch_bytes,
-                         int32_t dtype, int32_t k, int32_t border, const mf_options* opt, void* stream)
+int32_t median_filter_planes(const void* src, void* dst, int64_t planes, int64_t plane_stride_bytes, int64_t H,
+                             int64_t W, int64_t pitch_bytes, int32_t dtype, int32_t k, int32_t border,
+                             const mf_options* opt, void* stream)
 {
     g_last_error.clear();
     int32_t rc = validate(src, dst, H, W, pitch_bytes, dtype, k, border);
     if (rc) return rc;
-    hipStream_t st = (hipStream_t)stream;
     const int s = elem_size(dtype);
-    if (k == 1)
-        return hip_status(hipMemcpy2DAsync(dst, pitch_bytes, src, pitch_bytes, W * s, H,
-                                           hipMemcpyDeviceToDevice, st),
-                          "hipMemcpy2DAsync");
+    const int64_t plane_bytes = (H - 1) * pitch_bytes + W * s;
+    if (planes < 1 || planes > ((int64_t)1 << 30))
+        return fail(MF_ERR_DIMS, "planes=%lld outside [1, 2^30]", (long long)planes);
+    if (planes > 1) {
+        if (plane_stride_bytes < plane_bytes || plane_stride_bytes % s || plane_stride_bytes > ((int64_t)1 << 46))
+            return fail(MF_ERR_PITCH, "plane stride %lld: planes of %lld bytes would overlap or misalign",
+                        (long long)plane_stride_bytes, (long long)plane_bytes);
+        const uintptr_t a0 = (uintptr_t)src, b0 = (uintptr_t)dst;
+        const uintptr_t len = (uintptr_t)((planes - 1) * plane_stride_bytes + plane_bytes);
+        if (a0 < b0 + len && b0 < a0 + len) return fail(MF_ERR_ALIAS, "src and dst plane ranges overlap");
+    } else {
+        plane_stride_bytes = 0;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (k == 1) {
+        for (int64_t p = 0; p < planes; ++p) {
+            rc = hip_status(hipMemcpy2DAsync((char*)dst + p * plane_stride_bytes, pitch_bytes,
+                                             (const char*)src + p * plane_stride_bytes, pitch_bytes, W * s, H,
+                                             hipMemcpyDeviceToDevice, st),
+                            "hipMemcpy2DAsync");
+            if (rc) return rc;
+        }
+        return MF_OK;
+    }
     int32_t variant = 0, tw = 0, th = 0, group = 0;
     const OblEntry* e = nullptr;
     rc = resolve(dtype, k, opt, &variant, &tw, &th, &e, &group);
     if (rc) return rc;
     if (variant == MF_VARIANT_OBLIVIOUS) {
         mf_launch_fn fn = (dtype == MF_U8 || dtype == MF_U16) ? e->p16 : e->u32;
-        return hip_status(fn(src, dst, (int)H, (int)W, pitch_bytes, dtype, st), "oblivious kernel launch");
+        return hip_status(fn(src, dst, (int)planes, plane_stride_bytes, (int)H, (int)W, pitch_bytes, dtype, st),
+                          "oblivious kernel launch");
     }
-    return hip_status(mf_da_launch(src, dst, (int)H, (int)W, pitch_bytes, dtype, k, tw, th, group, st),
+    return hip_status(mf_da_launch(src, dst, (int)planes, plane_stride_bytes, (int)H, (int)W, pitch_bytes, dtype, k,
+                                   tw, th, group, st),
                       "data-aware kernel launch");
+}
+
+int32_t median_filter_ex(const void* src, void* dst, int64_t H, int64_t W, int64_t pitch_bytes,
+                         int32_t dtype, int32_t k, int32_t border, const mf_options* opt, void* stream)
+{
+    return median_filter_planes(src, dst, 1, 0, H, W, pitch_bytes, dtype, k, border, opt, stream);
 }
 
 int32_t median_filter(const void* src, void* dst, int64_t H, int64_t W, int64_t pitch_bytes,
@@ -285,10 +313,8 @@ int32_t median_filter_fwd_argmedian(const float* src, float* dst, int32_t* idx, 
     const size_t bytes = (size_t)(planes * H * W) * 4;
     if (overlap(src, bytes, dst, bytes) || overlap(src, bytes, idx, bytes) || overlap(dst, bytes, idx, bytes))
         return fail(MF_ERR_ALIAS, "src, dst and idx must not overlap");
-    for (int64_t p = 0; p < planes; ++p) {
-        rc = median_filter_ex(src + p * H * W, dst + p * H * W, H, W, W * 4, MF_F32, k, border, nullptr, stream);
-        if (rc) return rc;
-    }
+    rc = median_filter_planes(src, dst, planes, H * W * 4, H, W, W * 4, MF_F32, k, border, nullptr, stream);
+    if (rc) return rc;
     g_last_error.clear();
     return hip_status(mf_ag_argmedian_launch(src, dst, idx, planes, (int)H, (int)W, k, (hipStream_t)stream),
                       "argmedian kernel launch");

@@ -171,9 +171,10 @@ mf_da_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
 template <class E, int T>
 __global__ void __launch_bounds__(kDaThreads)
 mf_da_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, int H, int W,
-             long long pitch, int dtype, MfDaArgs a, int ntx)
+             long long pitch, long long plane_stride, int dtype, MfDaArgs a, int ntx)
 {
-    mf_da_block<E, T>(src, dst, H, W, pitch, dtype, a, blockIdx.x % ntx, blockIdx.x / ntx);
+    const long long po = (long long)blockIdx.y * plane_stride;   // plane = blockIdx.y
+    mf_da_block<E, T>(src + po, dst + po, H, W, pitch, dtype, a, blockIdx.x % ntx, blockIdx.x / ntx);
 }
 
 // Batched form: blocks of every image of a job table (same k, tile, tiles per
@@ -307,8 +308,8 @@ static MfDaArgs da_args(const DaEntry* e, const uint32_t* blob)
     return a;
 }
 
-hipError_t mf_da_launch(const void* src, void* dst, int H, int W, long long pitch, int dtype, int k,
-                        int tw, int th, int group, hipStream_t stream)
+hipError_t mf_da_launch(const void* src, void* dst, int planes, long long plane_stride, int H, int W,
+                        long long pitch, int dtype, int k, int tw, int th, int group, hipStream_t stream)
 {
     const DaEntry* e = da_find(dtype, k, tw, th, group);
     if (!e) return hipErrorInvalidValue;
@@ -318,10 +319,15 @@ hipError_t mf_da_launch(const void* src, void* dst, int H, int W, long long pitc
     MfDaArgs a = da_args(e, blob);
     const int ntx = (W + e->tw * e->tiles - 1) / (e->tw * e->tiles), nty = (H + e->th - 1) / e->th;
     const size_t lds = (size_t)e->arena * e->es * e->tiles;
-    const unsigned char* s8 = (const unsigned char*)src;
-    unsigned char* d8 = (unsigned char*)dst;
-    void* args[] = {&s8, &d8, &H, &W, &pitch, &dtype, &a, (void*)&ntx};
-    return hipLaunchKernel(da_kernel_for(e, false), dim3(ntx * nty), dim3(kDaThreads), args, lds, stream);
+    for (int p0 = 0; p0 < planes; p0 += 65535) {     // grid rows are planes
+        const int np = planes - p0 < 65535 ? planes - p0 : 65535;
+        const unsigned char* s8 = (const unsigned char*)src + p0 * plane_stride;
+        unsigned char* d8 = (unsigned char*)dst + p0 * plane_stride;
+        void* args[] = {&s8, &d8, &H, &W, &pitch, &plane_stride, &dtype, &a, (void*)&ntx};
+        err = hipLaunchKernel(da_kernel_for(e, false), dim3(ntx * nty, np), dim3(kDaThreads), args, lds, stream);
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
 }
 
 hipError_t mf_da_batched(int dtype, int k, int tw, int th, int group, MfBatchedKernel* kern, MfDaArgs* args)

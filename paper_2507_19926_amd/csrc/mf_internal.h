@@ -7,11 +7,12 @@
 
 #include "medfilt.h"
 
-// Launcher of one compiled kernel configuration. src/dst are device
-// pointers, pitch in bytes, dtype an mf_dtype the kernel's value class
-// accepts (u8/u16 for the packed 16-bit class, u32/f32 for the 32-bit one).
-typedef hipError_t (*mf_launch_fn)(const void* src, void* dst, int H, int W,
-                                   long long pitch, int dtype, hipStream_t stream);
+// Launcher of one compiled kernel configuration: `planes` planes of H x W,
+// plane p at src/dst + p * plane_stride bytes. src/dst are device pointers,
+// pitch in bytes, dtype an mf_dtype the kernel's value class accepts (u8/u16
+// for the packed 16-bit class, u32/f32 for the 32-bit one).
+typedef hipError_t (*mf_launch_fn)(const void* src, void* dst, int planes, long long plane_stride, int H,
+                                   int W, long long pitch, int dtype, hipStream_t stream);
 
 // One image of a batched launch. Images of one job table share the kernel
 // (k, root tile, value class); block_begin is the first grid block of the
@@ -36,22 +37,22 @@ struct MfBatchedKernel {
 #define MF_OBL_BATCHED_NAME(NET, RY, NW, VC) mf_obl_batched_##NET##_r##RY##w##NW##_##VC
 
 #define MF_OBL_DECLARE(NET, RY, NW)                                                \
-    hipError_t MF_OBL_NAME(NET, RY, NW, p16)(const void*, void*, int, int,        \
+    hipError_t MF_OBL_NAME(NET, RY, NW, p16)(const void*, void*, int, long long, int, int, \
                                              long long, int, hipStream_t);        \
-    hipError_t MF_OBL_NAME(NET, RY, NW, u32)(const void*, void*, int, int,        \
+    hipError_t MF_OBL_NAME(NET, RY, NW, u32)(const void*, void*, int, long long, int, int, \
                                              long long, int, hipStream_t);        \
     void MF_OBL_BATCHED_NAME(NET, RY, NW, p16)(MfBatchedKernel*);                 \
     void MF_OBL_BATCHED_NAME(NET, RY, NW, u32)(MfBatchedKernel*);
 
 // Column-strip form for k = 3 (mf_strip.hip), per value class.
-hipError_t mf_strip3_launch_p16(const void* src, void* dst, int H, int W, long long pitch, int dtype,
-                                hipStream_t stream);
-hipError_t mf_strip3_launch_u32(const void* src, void* dst, int H, int W, long long pitch, int dtype,
-                                hipStream_t stream);
+hipError_t mf_strip3_launch_p16(const void* src, void* dst, int planes, long long plane_stride, int H, int W,
+                                long long pitch, int dtype, hipStream_t stream);
+hipError_t mf_strip3_launch_u32(const void* src, void* dst, int planes, long long plane_stride, int H, int W,
+                                long long pitch, int dtype, hipStream_t stream);
 
 // Data-aware launcher: one per value class, any k up to mf_max_k().
-hipError_t mf_da_launch(const void* src, void* dst, int H, int W, long long pitch,
-                        int dtype, int k, int tw, int th, int group, hipStream_t stream);
+hipError_t mf_da_launch(const void* src, void* dst, int planes, long long plane_stride, int H, int W,
+                        long long pitch, int dtype, int k, int tw, int th, int group, hipStream_t stream);
 bool mf_da_supports(int dtype, int k, int tw, int th, int group);
 void mf_da_default_tile(int dtype, int k, int* tw, int* th, int* group);
 // Data-aware entries for (dtype, k): fills up to cap (tw, th, group) triples,

@@ -531,8 +531,9 @@ mf_obl_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ 
 //     networks write this block's medians into the output tile.
 template <class NET, class V, int RY, int NW>
 __global__ void __launch_bounds__(64 * NW)
-mf_obl_kernel_persistent(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
-                         int H, int W, long long pitch, int dtype, int nbx, int nblocks, int per, int aligned)
+mf_obl_kernel_persistent(const unsigned char* __restrict__ src0, unsigned char* __restrict__ dst0,
+                         int H, int W, long long pitch, long long plane_stride, int dtype, int nbx,
+                         int nblocks, int total, int per, int aligned)
 {
     using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY, NW>;
     constexpr int BW = G::PACK ? 2 * G::BWH : G::BWH, BH = G::TY * NET::TH;
@@ -541,13 +542,20 @@ mf_obl_kernel_persistent(const unsigned char* __restrict__ src, unsigned char* _
     __shared__ uint4 stage[G::STG_CHUNKS];
     __shared__ uint4 out[BH * BW * (G::PACK ? 2 : 4) / 16];
     static_assert(sizeof(raw) + sizeof(colb) + sizeof(stage) + sizeof(out) <= 160 * 1024, "LDS budget");
+    // block b of the launch: plane b / nblocks, block b % nblocks of it
     const int b0 = blockIdx.x * per;
-    const int b1 = min(b0 + per, nblocks);
+    const int b1 = min(b0 + per, total);
     if (b0 >= b1) return;
+    auto plane_src = [&](int b) { return src0 + (long long)(b / nblocks) * plane_stride; };
+    auto plane_dst = [&](int b) { return dst0 + (long long)(b / nblocks) * plane_stride; };
+    auto bx0 = [&](int b) { return (b % nblocks % nbx) * BW; };
+    auto by0 = [&](int b) { return (b % nblocks / nbx) * BH; };
     int staged = mf_obl_stage_issue<V, NET::K, NET::TW, NET::TH, RY, NW>(
-        src, H, W, pitch, dtype, (b0 % nbx) * BW, (b0 / nbx) * BH, aligned, stage);
+        plane_src(b0), H, W, pitch, dtype, bx0(b0), by0(b0), aligned, stage);
     for (int b = b0; b < b1; ++b) {
-        const int X0 = (b % nbx) * BW, Y0 = (b / nbx) * BH;
+        const unsigned char* src = plane_src(b);
+        unsigned char* dst = plane_dst(b);
+        const int X0 = bx0(b), Y0 = by0(b);
         // this wave's staging copies and stores have completed; after the
         // barrier everyone's have, and the previous networks are done
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -559,12 +567,11 @@ mf_obl_kernel_persistent(const unsigned char* __restrict__ src, unsigned char* _
         else
             mf_obl_load_clamped<V, NET::K, NET::TW, NET::TH, RY, NW>(src, H, W, pitch, dtype, X0, Y0, raw);
         if (b > b0)
-            mf_obl_store_out<NET, V, RY, NW>((const unsigned char*)out, dst, H, W, pitch, dtype,
-                                             ((b - 1) % nbx) * BW, ((b - 1) / nbx) * BH, aligned);
+            mf_obl_store_out<NET, V, RY, NW>((const unsigned char*)out, plane_dst(b - 1), H, W, pitch, dtype,
+                                             bx0(b - 1), by0(b - 1), aligned);
         __syncthreads();                       // raw complete; stage and out free
         staged = b + 1 >= b1 ? 0 : mf_obl_stage_issue<V, NET::K, NET::TW, NET::TH, RY, NW>(
-                                   src, H, W, pitch, dtype, ((b + 1) % nbx) * BW, ((b + 1) / nbx) * BH, aligned,
-                                   stage);
+                                   plane_src(b + 1), H, W, pitch, dtype, bx0(b + 1), by0(b + 1), aligned, stage);
         if constexpr (!NET::INLINE_COLS) {
             mf_obl_colsort<NET, V, RY, NW>(raw, colb);
             __syncthreads();
@@ -573,16 +580,17 @@ mf_obl_kernel_persistent(const unsigned char* __restrict__ src, unsigned char* _
                                               (unsigned char*)out);
     }
     __syncthreads();
-    mf_obl_store_out<NET, V, RY, NW>((const unsigned char*)out, dst, H, W, pitch, dtype, ((b1 - 1) % nbx) * BW,
-                                     ((b1 - 1) / nbx) * BH, aligned);
+    mf_obl_store_out<NET, V, RY, NW>((const unsigned char*)out, plane_dst(b1 - 1), H, W, pitch, dtype, bx0(b1 - 1),
+                                     by0(b1 - 1), aligned);
 }
 
 template <class NET, class V, int RY, int NW>
 __global__ void __launch_bounds__(64 * NW)
 mf_obl_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
-              int H, int W, long long pitch, int dtype, int nbx)
+              int H, int W, long long pitch, long long plane_stride, int dtype, int nbx)
 {
-    mf_obl_block<NET, V, RY, NW>(src, dst, H, W, pitch, dtype, blockIdx.x % nbx, blockIdx.x / nbx);
+    const long long po = (long long)blockIdx.y * plane_stride;   // plane = blockIdx.y
+    mf_obl_block<NET, V, RY, NW>(src + po, dst + po, H, W, pitch, dtype, blockIdx.x % nbx, blockIdx.x / nbx);
 }
 
 // Batched form: the grid covers the blocks of every image of a job table
@@ -615,8 +623,8 @@ static void mf_obl_batched(MfBatchedKernel* k)
 }
 
 template <class NET, class V, int RY, int NW>
-static hipError_t mf_obl_launch(const void* src, void* dst, int H, int W, long long pitch,
-                                int dtype, hipStream_t stream)
+static hipError_t mf_obl_launch(const void* src, void* dst, int planes, long long plane_stride, int H, int W,
+                                long long pitch, int dtype, hipStream_t stream)
 {
     constexpr bool PACK = MfVTraits<V>::PACK;
     const int bw = (PACK ? 2 : 1) * 64 * NET::TW;
@@ -626,8 +634,8 @@ static hipError_t mf_obl_launch(const void* src, void* dst, int H, int W, long l
     if constexpr (NET::PERSISTENT) {
         // resident work-groups of the persistent form, once per process from
         // the occupancy calculator. 0 (never persistent) when the persistent
-        // form would spill to scratch or fit fewer work-groups per CU than the
-        // plain form: its prefetch registers live across the networks.
+        // kernel spills to scratch or fits fewer work-groups per CU than the
+        // plain kernel (its staging and output buffers take LDS).
         static int resident = -1;
         if (resident < 0) {
             int per_cu = 0, per_cu_plain = 0, dev = 0, cus = 0;
@@ -647,41 +655,51 @@ static hipError_t mf_obl_launch(const void* src, void* dst, int H, int W, long l
                 resident = per_cu * cus;
             }
         }
-        if (resident > 0 && nblocks > 2 * resident) {
-            const int per = (nblocks + resident - 1) / resident;
-            const int grid = (nblocks + per - 1) / per;
+        const long long total = (long long)nblocks * planes;
+        if (resident > 0 && total > 2LL * resident && total < (1LL << 31)) {
+            const int per = (int)((total + resident - 1) / resident);
+            const int grid = (int)((total + per - 1) / per);
             using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY, NW>;
             // LDS-direct staging and 16-byte output stores need 16-byte
             // aligned rows; buffer offsets of the footprint rows stay below 2^31
             const int aligned = ((uintptr_t)src % 16 == 0 && (uintptr_t)dst % 16 == 0 && pitch % 16 == 0 &&
-                                 (long long)(G::ROWS + 1) * pitch < (1LL << 31)) ? 1 : 0;
+                                 plane_stride % 16 == 0 && (long long)(G::ROWS + 1) * pitch < (1LL << 31)) ? 1 : 0;
             hipLaunchKernelGGL((mf_obl_kernel_persistent<NET, V, RY, NW>), dim3(grid), dim3(64 * NW), 0, stream,
-                               (const unsigned char*)src, (unsigned char*)dst, H, W, pitch, dtype, nbx, nblocks,
-                               per, aligned);
+                               (const unsigned char*)src, (unsigned char*)dst, H, W, pitch, plane_stride, dtype,
+                               nbx, nblocks, (int)total, per, aligned);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((mf_obl_kernel<NET, V, RY, NW>), dim3(nblocks), dim3(64 * NW), 0, stream,
-                       (const unsigned char*)src, (unsigned char*)dst, H, W, pitch, dtype, nbx);
-    return hipGetLastError();
+    // one work-group per block; grid rows are planes (at most 65535 per launch)
+    for (int p0 = 0; p0 < planes; p0 += 65535) {
+        const int np = planes - p0 < 65535 ? planes - p0 : 65535;
+        hipLaunchKernelGGL((mf_obl_kernel<NET, V, RY, NW>), dim3(nblocks, np), dim3(64 * NW), 0, stream,
+                           (const unsigned char*)src + p0 * plane_stride, (unsigned char*)dst + p0 * plane_stride,
+                           H, W, pitch, plane_stride, dtype, nbx);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
-#define MF_OBL_INSTANTIATE(NET, RY, NW)                                                   \
-    hipError_t mf_obl_launch_##NET##_r##RY##w##NW##_p16(const void* s, void* d, int H, int W, \
-                                                     long long p, int dt, hipStream_t st) \
-    {                                                                                     \
-        return mf_obl_launch<NET, us2, RY, NW>(s, d, H, W, p, dt, st);                    \
-    }                                                                                     \
-    hipError_t mf_obl_launch_##NET##_r##RY##w##NW##_u32(const void* s, void* d, int H, int W, \
-                                                     long long p, int dt, hipStream_t st) \
-    {                                                                                     \
-        return mf_obl_launch<NET, uint32_t, RY, NW>(s, d, H, W, p, dt, st);               \
-    }                                                                                     \
-    void mf_obl_batched_##NET##_r##RY##w##NW##_p16(MfBatchedKernel* k)                   \
-    {                                                                                     \
-        mf_obl_batched<NET, us2, RY, NW>(k);                                              \
-    }                                                                                     \
-    void mf_obl_batched_##NET##_r##RY##w##NW##_u32(MfBatchedKernel* k)                   \
-    {                                                                                     \
-        mf_obl_batched<NET, uint32_t, RY, NW>(k);                                         \
+#define MF_OBL_INSTANTIATE(NET, RY, NW)                                                       \
+    hipError_t mf_obl_launch_##NET##_r##RY##w##NW##_p16(const void* s, void* d, int np, long long ps, \
+                                                        int H, int W, long long p, int dt,        \
+                                                        hipStream_t st)                           \
+    {                                                                                         \
+        return mf_obl_launch<NET, us2, RY, NW>(s, d, np, ps, H, W, p, dt, st);                \
+    }                                                                                         \
+    hipError_t mf_obl_launch_##NET##_r##RY##w##NW##_u32(const void* s, void* d, int np, long long ps, \
+                                                        int H, int W, long long p, int dt,        \
+                                                        hipStream_t st)                           \
+    {                                                                                         \
+        return mf_obl_launch<NET, uint32_t, RY, NW>(s, d, np, ps, H, W, p, dt, st);           \
+    }                                                                                         \
+    void mf_obl_batched_##NET##_r##RY##w##NW##_p16(MfBatchedKernel* k)                       \
+    {                                                                                         \
+        mf_obl_batched<NET, us2, RY, NW>(k);                                                  \
+    }                                                                                         \
+    void mf_obl_batched_##NET##_r##RY##w##NW##_u32(MfBatchedKernel* k)                       \
+    {                                                                                         \
+        mf_obl_batched<NET, uint32_t, RY, NW>(k);                                             \
     }

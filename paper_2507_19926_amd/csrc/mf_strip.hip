@@ -65,8 +65,10 @@ __device__ __forceinline__ void strip_store1(unsigned char* row, int x, uint32_t
 template <int ES>
 __global__ void __launch_bounds__(64 * kStripWaves)
 mf_strip3_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, int H, int W,
-                 long long pitch, int dtype, int nbx, int aligned)
+                 long long pitch, long long plane_stride, int dtype, int nbx, int aligned)
 {
+    src += (long long)blockIdx.y * plane_stride;   // plane = blockIdx.y
+    dst += (long long)blockIdx.y * plane_stride;
     constexpr int P = 16 / ES;               // pixels per lane
     constexpr int R = kStripRows;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -181,29 +183,37 @@ mf_strip3_kernel(const unsigned char* __restrict__ src, unsigned char* __restric
 }
 
 template <int ES>
-hipError_t strip3_launch(const void* src, void* dst, int H, int W, long long pitch, int dtype, hipStream_t st)
+hipError_t strip3_launch(const void* src, void* dst, int planes, long long plane_stride, int H, int W,
+                         long long pitch, int dtype, hipStream_t st)
 {
     constexpr int span = 64 * (16 / ES);
     const int nbx = (W + span - 1) / span;
     const int nby = (H + kStripRows * kStripWaves - 1) / (kStripRows * kStripWaves);
     // 16-byte chunk loads and stores need 16-byte aligned rows
-    const int aligned = ((uintptr_t)src % 16 == 0 && (uintptr_t)dst % 16 == 0 && pitch % 16 == 0) ? 1 : 0;
-    hipLaunchKernelGGL((mf_strip3_kernel<ES>), dim3((unsigned)nbx * nby), dim3(64 * kStripWaves), 0, st,
-                       (const unsigned char*)src, (unsigned char*)dst, H, W, pitch, dtype, nbx, aligned);
-    return hipGetLastError();
+    const int aligned = ((uintptr_t)src % 16 == 0 && (uintptr_t)dst % 16 == 0 && pitch % 16 == 0 &&
+                         plane_stride % 16 == 0) ? 1 : 0;
+    for (int p0 = 0; p0 < planes; p0 += 65535) {     // grid rows are planes
+        const int np = planes - p0 < 65535 ? planes - p0 : 65535;
+        hipLaunchKernelGGL((mf_strip3_kernel<ES>), dim3((unsigned)nbx * nby, np), dim3(64 * kStripWaves), 0, st,
+                           (const unsigned char*)src + p0 * plane_stride, (unsigned char*)dst + p0 * plane_stride,
+                           H, W, pitch, plane_stride, dtype, nbx, aligned);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace
 
-hipError_t mf_strip3_launch_p16(const void* src, void* dst, int H, int W, long long pitch, int dtype,
-                                hipStream_t st)
+hipError_t mf_strip3_launch_p16(const void* src, void* dst, int planes, long long plane_stride, int H, int W,
+                                long long pitch, int dtype, hipStream_t st)
 {
-    return dtype == MF_U8 ? strip3_launch<1>(src, dst, H, W, pitch, dtype, st)
-                          : strip3_launch<2>(src, dst, H, W, pitch, dtype, st);
+    return dtype == MF_U8 ? strip3_launch<1>(src, dst, planes, plane_stride, H, W, pitch, dtype, st)
+                          : strip3_launch<2>(src, dst, planes, plane_stride, H, W, pitch, dtype, st);
 }
 
-hipError_t mf_strip3_launch_u32(const void* src, void* dst, int H, int W, long long pitch, int dtype,
-                                hipStream_t st)
+hipError_t mf_strip3_launch_u32(const void* src, void* dst, int planes, long long plane_stride, int H, int W,
+                                long long pitch, int dtype, hipStream_t st)
 {
-    return strip3_launch<4>(src, dst, H, W, pitch, dtype, st);
+    return strip3_launch<4>(src, dst, planes, plane_stride, H, W, pitch, dtype, st);
 }

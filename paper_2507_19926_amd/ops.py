@@ -29,8 +29,9 @@ def median_filter(x: torch.Tensor, k: int, out: torch.Tensor | None = None,
     """Exact k x k median (replicate border) of every (H, W) plane of x.
 
     x: a device tensor of shape (..., H, W) whose last dimension is contiguous;
-    rows may be pitched (x.stride(-2) >= W). Leading dimensions are filtered
-    plane by plane on the current stream.
+    rows may be pitched (x.stride(-2) >= W). Leading dimensions are planes,
+    each filtered on its own; equally spaced planes go to the library in one
+    call (median_filter_planes), on the current stream.
     """
     if not x.is_cuda:
         raise ValueError("median_filter needs a GPU tensor")
@@ -53,7 +54,16 @@ def median_filter(x: torch.Tensor, k: int, out: torch.Tensor | None = None,
     planes_o = out.reshape(-1, H, W) if out.dim() > 2 else out.unsqueeze(0)
     if planes_x.data_ptr() != x.data_ptr() or planes_o.data_ptr() != out.data_ptr():
         raise ValueError("leading dimensions must be collapsible")
-    for i in range(planes_x.shape[0]):
+    n = planes_x.shape[0]
+    if n == 0:
+        return out
+    # equally spaced planes (the usual case after collapsing) go in one call
+    stride = planes_x.stride(0) * es if n > 1 else 0
+    if n == 1 or stride >= (H - 1) * pitch + W * es:
+        _lib.check(L.median_filter_planes(x.data_ptr(), out.data_ptr(), n, stride, H, W, pitch, code, int(k),
+                                          _lib.MF_BORDER_REPLICATE, ctypes.byref(opt), stream))
+        return out
+    for i in range(n):
         _lib.check(L.median_filter_ex(planes_x[i].data_ptr(), planes_o[i].data_ptr(), H, W, pitch,
                                       code, int(k), _lib.MF_BORDER_REPLICATE, ctypes.byref(opt), stream))
     return out

@@ -80,6 +80,26 @@ def test_query_config():
     assert _lib.lib().mf_max_k() >= 75
 
 
+def test_planes_entry_validation():
+    """median_filter_planes validates on the host: plane count, plane stride
+    (planes may not overlap or misalign) and the src/dst ranges over all
+    planes; a plain image's checks still apply."""
+    L = _lib.lib()
+
+    def call(planes=3, stride=16 * 16, src=FAKE_SRC, dst=FAKE_DST, H=16, W=16, pitch=16, dtype=0, k=3):
+        return L.median_filter_planes(src, dst, planes, stride, H, W, pitch, dtype, k, 0, None, None)
+
+    assert call(planes=0) == -2
+    assert call(planes=-1) == -2
+    assert call(stride=16 * 16 - 1) == -3          # planes would overlap
+    assert call(dtype=1, W=8, stride=16 * 16 + 1) == -3   # stride not a multiple of 2 bytes
+    assert call(dst=FAKE_SRC + 2 * 256 + 100) == -7  # dst inside the src planes
+    assert call(H=0) == -2 and call(k=4) == -5 and call(src=None) == -1
+    # planes = 1 ignores the stride: the call passes validation and fails
+    # later (no GPU) or not at all, but never with a stride error
+    assert call(planes=1, stride=1) != -3
+
+
 def test_strip_form_listed_and_resolved():
     """The column-strip form exists for k = 3 only, is the last oblivious
     entry (never the default), and a request for it resolves to root tile

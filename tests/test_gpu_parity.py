@@ -211,6 +211,40 @@ def test_persistent_staging_placements(k, dtype, placement):
 
 STRIP = dict(variant=_lib.MF_VARIANT_OBLIVIOUS, tile=(1, 1), group=4, form=3, rows=16)
 
+PLANE_CFGS = [dict(k=3), dict(k=3, **STRIP), dict(k=5), dict(k=9), dict(k=17), dict(k=25),
+              dict(k=17, variant=_lib.MF_VARIANT_DATA_AWARE)]
+
+
+@pytest.mark.parametrize("cfg", PLANE_CFGS, ids=lambda c: "_".join("%s%s" % kv for kv in c.items()))
+@pytest.mark.parametrize("dtype", [np.uint8, np.float32])
+def test_planes_one_launch(cfg, dtype):
+    """Several planes in one median_filter_planes call (contiguous stack and
+    planes with gaps between them) equal the oracle plane by plane; big enough
+    for the persistent form to spread blocks over plane boundaries."""
+    cfg = dict(cfg)
+    k = cfg.pop("k")
+    P, H, W = 3, 700, 1300
+    imgs = np.stack([_img(dtype, H, W, seed=40 + p) for p in range(P)])
+    want = [oracle.median_filter(imgs[p], k) for p in range(P)]
+    got = _gpu(imgs, k, **cfg)
+    for p in range(P):
+        assert _eq(got[p], want[p]), (k, p)
+    # planes with a gap of 3 rows plus 32 bytes between them (padded rows)
+    tdt = TORCH_DT[np.dtype(dtype)]
+    es = np.dtype(dtype).itemsize
+    pitch = W + 32 // es
+    stride = (H + 3) * pitch
+    xb = torch.zeros(P * stride * es, dtype=torch.uint8, device="cuda").view(tdt)
+    ob = torch.zeros(P * stride * es, dtype=torch.uint8, device="cuda").view(tdt)
+    x = torch.as_strided(xb, (P, H, W), (stride, pitch, 1))
+    out = torch.as_strided(ob, (P, H, W), (stride, pitch, 1))
+    x.copy_(_dev(imgs))
+    median_filter(x, k, out=out, **cfg)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy()
+    for p in range(P):
+        assert _eq(res[p], want[p]), (k, p, "strided")
+
 
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("shape", [(1, 1), (1, 9), (7, 1), (2, 3), (17, 33), (63, 1023), (64, 1024),
