@@ -10,12 +10,12 @@
 // replaced by this LDS-resident sequence of rounds separated by barriers.
 //
 // Each round is a list of merge-path chunks: a lane finds the chunk's start in
-// its two sorted input windows with a co-rank binary search, reads the next 8
-// elements of each window and merges them with a bitonic network (up to 8
-// outputs per chunk). A work-group holds T root tiles (T arenas) that share
-// the schedule; a lane runs its chunk for the T tiles side by side. Only the
-// ranks some later step can read are produced (forgetting and pruning as
-// output windows).
+// its two sorted input windows with a co-rank binary search and then merges
+// up to 16 outputs sequentially. A work-group holds T root tiles (T arenas)
+// that share the schedule; a lane runs its chunk for the T tiles side by side,
+// so T independent chains of LDS reads are in flight per lane. Only the ranks
+// some later step can read are produced (forgetting and pruning as output
+// windows).
 //
 // 8/16-bit data is held as 16-bit LDS elements, 32-bit data (uint32, float32
 // through an order-preserving key) as 32-bit elements.
@@ -121,46 +121,33 @@ mf_da_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
                     any |= lo[t] < hi[t];
                 }
             }
-            // the chunk's n <= 8 outputs are the n smallest of the next 8
-            // elements of each input from the co-rank on (missing ones read
-            // as the largest key, which never displaces a real output value):
-            // elementwise min of A' and reversed B' is the 8 smallest as a
-            // bitonic sequence, which a 3-stage bitonic merge sorts. All 16
-            // LDS reads are independent; no dependent read chain.
-            static_assert(MF_DA_CHUNK_MAX <= 8, "chunk longer than the merge network");
-            constexpr uint32_t kBig = sizeof(E) == 2 ? 0xFFFFu : 0xFFFFFFFFu;
+            // sequential two-pointer merge of n outputs, the T tiles side by
+            // side (T independent chains of dependent LDS reads)
+            int ii[T], jj[T];
+            E va[T], vb[T];
 #pragma unroll
             for (int t = 0; t < T; ++t) {
                 const E* A = lds + t * arena + ao;
                 const E* B = lds + t * arena + bo;
-                const int i0 = lo[t], j0 = r0 - lo[t];
-                uint32_t a8[8], b8[8];
+                ii[t] = lo[t];
+                jj[t] = r0 - lo[t];
+                va[t] = ii[t] < na ? A[ii[t]] : (E)0;
+                vb[t] = jj[t] < nb ? B[jj[t]] : (E)0;
+            }
+            for (int q = 0; q < n; ++q) {
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    // indices clamped into the arena; out-of-window slots are replaced
-                    const uint32_t va = (uint32_t)A[min(i0 + e, arena - 1 - ao)];
-                    const uint32_t vb = (uint32_t)B[min(j0 + e, arena - 1 - bo)];
-                    a8[e] = i0 + e < na ? va : kBig;
-                    b8[e] = j0 + e < nb ? vb : kBig;
+                for (int t = 0; t < T; ++t) {
+                    const bool takeA = (ii[t] < na) && (jj[t] >= nb || va[t] <= vb[t]);
+                    lds[t * arena + oo + q] = takeA ? va[t] : vb[t];
+                    ii[t] += takeA ? 1 : 0;
+                    jj[t] += takeA ? 0 : 1;
+                    // one read refills the side just consumed; the index is
+                    // clamped into the arena (an exhausted side is never used)
+                    const int src_i = takeA ? ao + ii[t] : bo + jj[t];
+                    const E nv = lds[t * arena + min(src_i, arena - 1)];
+                    va[t] = takeA ? nv : va[t];
+                    vb[t] = takeA ? vb[t] : nv;
                 }
-                uint32_t m[8];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) m[e] = min(a8[e], b8[7 - e]);
-#pragma unroll
-                for (int dist = 4; dist >= 1; dist >>= 1) {
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        if ((e & dist) == 0) {
-                            const uint32_t lo_v = min(m[e], m[e + dist]), hi_v = max(m[e], m[e + dist]);
-                            m[e] = lo_v;
-                            m[e + dist] = hi_v;
-                        }
-                    }
-                }
-                E* O = lds + t * arena + oo;
-#pragma unroll
-                for (int e = 0; e < 8; ++e)
-                    if (e < n) O[e] = (E)m[e];
             }
             d = dn;
             c = cn;

@@ -40,7 +40,6 @@ from dataclasses import dataclass, field
 import numpy as np
 
 CHUNK = 4           # shortest merge-path chunk (outputs)
-CHUNK_MAX = 8       # longest chunk: the kernel merges a chunk with an 8-wide network
 LANES = 512         # threads of a data-aware work-group: a round's outputs are
                     # cut into about this many chunks
 OFF_BITS = 18       # arena offsets and sizes share a 32-bit word
@@ -252,9 +251,9 @@ def _window_inputs(n: Node):
 
 def schedule(k: int, tw: int, th: int, chunk: int = CHUNK, lanes: int = LANES) -> Schedule:
     """Rounds of windowed merges for root tile tw x th. Every round's outputs
-    are cut into chunks of min(CHUNK_MAX, max(chunk, ceil(outputs / lanes)))
-    outputs, so that one round keeps about `lanes` threads busy (a lane runs a
-    co-rank search, then merges its chunk)."""
+    are cut into chunks of max(chunk, ceil(outputs / lanes)) so that one
+    round keeps about `lanes` threads busy with chains as short as the round
+    allows (a lane runs a co-rank search, then its chunk sequentially)."""
     D, outs = build_dag(k, tw, th)
     propagate_windows(D, outs)
     fw, fh = k + tw - 1, k + th - 1
@@ -322,7 +321,7 @@ def schedule(k: int, tw: int, th: int, chunk: int = CHUNK, lanes: int = LANES) -
         for n in group:
             n.off = alloc(n.need_hi - n.need_lo)
         total = sum(n.need_hi - n.need_lo for n in group)
-        step = min(CHUNK_MAX, max(chunk, -(-total // lanes)))
+        step = max(chunk, -(-total // lanes))
         for n in group:
             (aoff, na), (boff, nb), r0 = _window_inputs(n)
             nout = n.need_hi - n.need_lo
