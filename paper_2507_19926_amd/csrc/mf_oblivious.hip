@@ -529,7 +529,10 @@ mf_obl_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ 
 //     16-byte stores, which complete during this block's networks;
 //   * the next block's staging copy is issued, columns are sorted, and the
 //     networks write this block's medians into the output tile.
-template <class NET, class V, int RY, int NW>
+// With TILE = false there is no output tile (less LDS, so as many
+// work-groups per CU as the plain kernel): the networks store medians to HBM
+// as they are produced.
+template <class NET, class V, int RY, int NW, bool TILE>
 __global__ void __launch_bounds__(64 * NW)
 mf_obl_kernel_persistent(const unsigned char* __restrict__ src0, unsigned char* __restrict__ dst0,
                          int H, int W, long long pitch, long long plane_stride, int dtype, int nbx,
@@ -540,7 +543,7 @@ mf_obl_kernel_persistent(const unsigned char* __restrict__ src0, unsigned char* 
     __shared__ V raw[G::ROWS * NET::TW * G::Q];
     __shared__ V colb[NET::INLINE_COLS ? 1 : G::TY * NET::LC * NET::TW * G::Q];
     __shared__ uint4 stage[G::STG_CHUNKS];
-    __shared__ uint4 out[BH * BW * (G::PACK ? 2 : 4) / 16];
+    __shared__ uint4 out[TILE ? BH * BW * (G::PACK ? 2 : 4) / 16 : 1];
     static_assert(sizeof(raw) + sizeof(colb) + sizeof(stage) + sizeof(out) <= 160 * 1024, "LDS budget");
     // block b of the launch: plane b / nblocks, block b % nblocks of it
     const int b0 = blockIdx.x * per;
@@ -566,7 +569,7 @@ mf_obl_kernel_persistent(const unsigned char* __restrict__ src0, unsigned char* 
             mf_obl_stage_commit_clamped<V, NET::K, NET::TW, NET::TH, RY, NW>(stage, W, dtype, X0, raw);
         else
             mf_obl_load_clamped<V, NET::K, NET::TW, NET::TH, RY, NW>(src, H, W, pitch, dtype, X0, Y0, raw);
-        if (b > b0)
+        if (TILE && b > b0)
             mf_obl_store_out<NET, V, RY, NW>((const unsigned char*)out, plane_dst(b - 1), H, W, pitch, dtype,
                                              bx0(b - 1), by0(b - 1), aligned);
         __syncthreads();                       // raw complete; stage and out free
@@ -576,12 +579,13 @@ mf_obl_kernel_persistent(const unsigned char* __restrict__ src0, unsigned char* 
             mf_obl_colsort<NET, V, RY, NW>(raw, colb);
             __syncthreads();
         }
-        mf_obl_networks<NET, V, RY, NW, true>(raw, colb, dst, H, W, pitch, dtype, X0, Y0,
-                                              (unsigned char*)out);
+        mf_obl_networks<NET, V, RY, NW, TILE>(raw, colb, dst, H, W, pitch, dtype, X0, Y0, (unsigned char*)out);
     }
-    __syncthreads();
-    mf_obl_store_out<NET, V, RY, NW>((const unsigned char*)out, plane_dst(b1 - 1), H, W, pitch, dtype, bx0(b1 - 1),
-                                     by0(b1 - 1), aligned);
+    if constexpr (TILE) {
+        __syncthreads();
+        mf_obl_store_out<NET, V, RY, NW>((const unsigned char*)out, plane_dst(b1 - 1), H, W, pitch, dtype,
+                                         bx0(b1 - 1), by0(b1 - 1), aligned);
+    }
 }
 
 template <class NET, class V, int RY, int NW>
@@ -632,27 +636,36 @@ static hipError_t mf_obl_launch(const void* src, void* dst, int planes, long lon
     const int nbx = (W + bw - 1) / bw, nby = (H + bh - 1) / bh;
     const int nblocks = nbx * nby;
     if constexpr (NET::PERSISTENT) {
-        // resident work-groups of the persistent form, once per process from
-        // the occupancy calculator. 0 (never persistent) when the persistent
-        // kernel spills to scratch or fits fewer work-groups per CU than the
-        // plain kernel (its staging and output buffers take LDS).
-        static int resident = -1;
+        // Persistent form, once per process from the occupancy calculator:
+        // with the output tile if that fits as many work-groups per CU as the
+        // plain kernel, else without it if that does; never when the kernel
+        // spills to scratch. resident = 0: plain kernel only.
+        static int resident = -1, tile = 0;
         if (resident < 0) {
-            int per_cu = 0, per_cu_plain = 0, dev = 0, cus = 0;
-            hipFuncAttributes attr;
-            const void* fn = (const void*)mf_obl_kernel_persistent<NET, V, RY, NW>;
-            if (hipFuncGetAttributes(&attr, fn) != hipSuccess || attr.localSizeBytes > 0 ||
-                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mf_obl_kernel_persistent<NET, V, RY, NW>,
-                                                             64 * NW, 0) != hipSuccess ||
-                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_plain, mf_obl_kernel<NET, V, RY, NW>, 64 * NW,
-                                                             0) != hipSuccess ||
-                per_cu < 1 || per_cu < per_cu_plain) {
-                resident = 0;
-            } else {
-                if (hipGetDevice(&dev) != hipSuccess ||
-                    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-                    cus = 256;
-                resident = per_cu * cus;
+            resident = 0;
+            int per_cu_plain = 0, dev = 0, cus = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_plain, mf_obl_kernel<NET, V, RY, NW>, 64 * NW,
+                                                             0) == hipSuccess && per_cu_plain >= 1) {
+                const void* fns[2] = {(const void*)mf_obl_kernel_persistent<NET, V, RY, NW, true>,
+                                      (const void*)mf_obl_kernel_persistent<NET, V, RY, NW, false>};
+                for (int t = 0; t < 2 && resident == 0; ++t) {
+                    hipFuncAttributes attr;
+                    int per_cu = 0;
+                    if (hipFuncGetAttributes(&attr, fns[t]) != hipSuccess || attr.localSizeBytes > 0) continue;
+                    const hipError_t e = t == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                                      &per_cu, mf_obl_kernel_persistent<NET, V, RY, NW, true>,
+                                                      64 * NW, 0)
+                                                : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                                      &per_cu, mf_obl_kernel_persistent<NET, V, RY, NW, false>,
+                                                      64 * NW, 0);
+                    if (e != hipSuccess || per_cu < per_cu_plain) continue;
+                    if (hipGetDevice(&dev) != hipSuccess ||
+                        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+                        cus < 1)
+                        cus = 256;
+                    resident = per_cu * cus;
+                    tile = t == 0;
+                }
             }
         }
         const long long total = (long long)nblocks * planes;
@@ -664,9 +677,14 @@ static hipError_t mf_obl_launch(const void* src, void* dst, int planes, long lon
             // aligned rows; buffer offsets of the footprint rows stay below 2^31
             const int aligned = ((uintptr_t)src % 16 == 0 && (uintptr_t)dst % 16 == 0 && pitch % 16 == 0 &&
                                  plane_stride % 16 == 0 && (long long)(G::ROWS + 1) * pitch < (1LL << 31)) ? 1 : 0;
-            hipLaunchKernelGGL((mf_obl_kernel_persistent<NET, V, RY, NW>), dim3(grid), dim3(64 * NW), 0, stream,
-                               (const unsigned char*)src, (unsigned char*)dst, H, W, pitch, plane_stride, dtype,
-                               nbx, nblocks, (int)total, per, aligned);
+            if (tile)
+                hipLaunchKernelGGL((mf_obl_kernel_persistent<NET, V, RY, NW, true>), dim3(grid), dim3(64 * NW), 0,
+                                   stream, (const unsigned char*)src, (unsigned char*)dst, H, W, pitch, plane_stride,
+                                   dtype, nbx, nblocks, (int)total, per, aligned);
+            else
+                hipLaunchKernelGGL((mf_obl_kernel_persistent<NET, V, RY, NW, false>), dim3(grid), dim3(64 * NW), 0,
+                                   stream, (const unsigned char*)src, (unsigned char*)dst, H, W, pitch, plane_stride,
+                                   dtype, nbx, nblocks, (int)total, per, aligned);
             return hipGetLastError();
         }
     }
