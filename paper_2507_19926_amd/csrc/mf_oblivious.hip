@@ -589,7 +589,7 @@ mf_obl_kernel_persistent(const unsigned char* __restrict__ src0, unsigned char* 
 }
 
 template <class NET, class V, int RY, int NW>
-__global__ void __launch_bounds__(64 * NW)
+__global__ void __launch_bounds__(64 * NW, MfVTraits<V>::PACK ? NET::MIN_WAVES : 1)
 mf_obl_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
               int H, int W, long long pitch, long long plane_stride, int dtype, int nbx)
 {
@@ -601,7 +601,7 @@ mf_obl_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__
 // (images sharing k, root tile and value class); each work-group finds its
 // image by binary search over the jobs' first block indices.
 template <class NET, class V, int RY, int NW>
-__global__ void __launch_bounds__(64 * NW)
+__global__ void __launch_bounds__(64 * NW, MfVTraits<V>::PACK ? NET::MIN_WAVES : 1)
 mf_obl_kernel_batched(const MfJob* __restrict__ jobs, int njobs)
 {
     const int b = blockIdx.x;

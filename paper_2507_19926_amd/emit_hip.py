@@ -93,6 +93,7 @@ def emit_config_tu(k: int, tw: int, th: int, shapes, inline: bool = False) -> st
     instantiation per (tile rows per wave, waves per work-group) shape."""
     P = ng.build_tile_program(k, tw, th, inline_cols=inline)
     cnt = ng.op_counts(P)
+    peak = ng.peak_live(P, ng.demand_order(P))
     name = net_name(k, tw, th, inline)
     lc = k - th + 1
     body = _net_body(P, k, tw, th, indent="        ")
@@ -108,6 +109,9 @@ def emit_config_tu(k: int, tw: int, th: int, shapes, inline: bool = False) -> st
         "    static constexpr int K = %d, TW = %d, TH = %d, LC = %d;" % (k, tw, th, lc),
         "    static constexpr bool INLINE_COLS = %s;" % ("true" if inline else "false"),
         "    static constexpr bool PERSISTENT = %s;" % ("true" if k <= 17 else "false"),
+        # networks whose live values just about fit 256 VGPRs are built for
+        # two waves per SIMD (plain and batched kernels, packed 16-bit data)
+        "    static constexpr int MIN_WAVES = %d;" % (2 if peak <= 270 else 1),
         "    template <class V> static __device__ __forceinline__ void sort_column(V* a) { mf_sort_%d(a); }" % lc,
         "    template <int Q, class V, class Sink>",
         "    static __device__ __forceinline__ void run(const V* __restrict__ col,",
