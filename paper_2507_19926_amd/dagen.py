@@ -322,6 +322,7 @@ def schedule(k: int, tw: int, th: int, chunk: int = CHUNK, lanes: int = LANES) -
             n.off = alloc(n.need_hi - n.need_lo)
         total = sum(n.need_hi - n.need_lo for n in group)
         step = max(chunk, -(-total // lanes))
+        rchunks = []
         for n in group:
             (aoff, na), (boff, nb), r0 = _window_inputs(n)
             nout = n.need_hi - n.need_lo
@@ -331,8 +332,15 @@ def schedule(k: int, tw: int, th: int, chunk: int = CHUNK, lanes: int = LANES) -
                 for off in (aoff, boff, n.off + c0):
                     assert 0 <= off < MAX_OFF
                 assert na < MAX_LEN and nb < MAX_LEN and c < MAX_LEN
-                chunks.append((aoff | (na << OFF_BITS), boff | (nb << OFF_BITS),
-                               (n.off + c0) | (c << OFF_BITS), r0 + c0))
+                # a lane's work: co-rank search steps plus sequential outputs
+                span = min(r0 + c0, na) - max(0, r0 + c0 - nb)
+                cost = max(span, 0).bit_length() + c
+                rchunks.append((cost, (aoff | (na << OFF_BITS), boff | (nb << OFF_BITS),
+                                       (n.off + c0) | (c << OFF_BITS), r0 + c0)))
+        # costliest first: the chunks of one wave (64 consecutive lanes) then
+        # take about the same time, so fewer lanes sit idle in a busy wave
+        rchunks.sort(key=lambda t: -t[0])
+        chunks.extend(ch for _, ch in rchunks)
         rounds.append(len(chunks))
         # free storage whose last reader ran in this round
         for n in merges:
