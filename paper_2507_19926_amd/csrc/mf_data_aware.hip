@@ -123,30 +123,65 @@ mf_da_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
             }
             // sequential two-pointer merge of n outputs, the T tiles side by
             // side (T independent chains of dependent LDS reads)
-            int ii[T], jj[T];
-            E va[T], vb[T];
-#pragma unroll
-            for (int t = 0; t < T; ++t) {
-                const E* A = lds + t * arena + ao;
-                const E* B = lds + t * arena + bo;
-                ii[t] = lo[t];
-                jj[t] = r0 - lo[t];
-                va[t] = ii[t] < na ? A[ii[t]] : (E)0;
-                vb[t] = jj[t] < nb ? B[jj[t]] : (E)0;
-            }
-            for (int q = 0; q < n; ++q) {
+            if constexpr (sizeof(E) == 2) {
+                // 16-bit elements in 32-bit registers: an exhausted side
+                // holds 0x10000, above every element, so one compare picks
+                // the side (A first on ties). pa / pb are the arena indices
+                // of the heads, ea / eb one past the windows.
+                constexpr uint32_t kDone = 0x10000u;
+                int pa[T], pb[T];
+                uint32_t va[T], vb[T];
+                const int ea = ao + na, eb = bo + nb;
 #pragma unroll
                 for (int t = 0; t < T; ++t) {
-                    const bool takeA = (ii[t] < na) && (jj[t] >= nb || va[t] <= vb[t]);
-                    lds[t * arena + oo + q] = takeA ? va[t] : vb[t];
-                    ii[t] += takeA ? 1 : 0;
-                    jj[t] += takeA ? 0 : 1;
-                    // one read refills the side just consumed; the index is
-                    // clamped into the arena (an exhausted side is never used)
-                    const int src_i = takeA ? ao + ii[t] : bo + jj[t];
-                    const E nv = lds[t * arena + min(src_i, arena - 1)];
-                    va[t] = takeA ? nv : va[t];
-                    vb[t] = takeA ? vb[t] : nv;
+                    pa[t] = ao + lo[t];
+                    pb[t] = bo + r0 - lo[t];
+                    va[t] = pa[t] < ea ? (uint32_t)lds[t * arena + pa[t]] : kDone;
+                    vb[t] = pb[t] < eb ? (uint32_t)lds[t * arena + pb[t]] : kDone;
+                }
+                for (int q = 0; q < n; ++q) {
+#pragma unroll
+                    for (int t = 0; t < T; ++t) {
+                        const bool takeA = va[t] <= vb[t];
+                        lds[t * arena + oo + q] = (E)min(va[t], vb[t]);
+                        pa[t] += takeA ? 1 : 0;
+                        pb[t] += takeA ? 0 : 1;
+                        const int p = takeA ? pa[t] : pb[t];
+                        const int e = takeA ? ea : eb;
+                        // index clamped into the arena; past the window the
+                        // value is replaced by kDone
+                        const uint32_t nv = (uint32_t)lds[t * arena + min(p, arena - 1)];
+                        const uint32_t nk = p < e ? nv : kDone;
+                        va[t] = takeA ? nk : va[t];
+                        vb[t] = takeA ? vb[t] : nk;
+                    }
+                }
+            } else {
+                int ii[T], jj[T];
+                E va[T], vb[T];
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    const E* A = lds + t * arena + ao;
+                    const E* B = lds + t * arena + bo;
+                    ii[t] = lo[t];
+                    jj[t] = r0 - lo[t];
+                    va[t] = ii[t] < na ? A[ii[t]] : (E)0;
+                    vb[t] = jj[t] < nb ? B[jj[t]] : (E)0;
+                }
+                for (int q = 0; q < n; ++q) {
+#pragma unroll
+                    for (int t = 0; t < T; ++t) {
+                        const bool takeA = (ii[t] < na) && (jj[t] >= nb || va[t] <= vb[t]);
+                        lds[t * arena + oo + q] = takeA ? va[t] : vb[t];
+                        ii[t] += takeA ? 1 : 0;
+                        jj[t] += takeA ? 0 : 1;
+                        // one read refills the side just consumed; the index is
+                        // clamped into the arena (an exhausted side is never used)
+                        const int src_i = takeA ? ao + ii[t] : bo + jj[t];
+                        const E nv = lds[t * arena + min(src_i, arena - 1)];
+                        va[t] = takeA ? nv : va[t];
+                        vb[t] = takeA ? vb[t] : nv;
+                    }
                 }
             }
             d = dn;
