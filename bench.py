@@ -6,8 +6,8 @@ uint8 planes of 6720 x 4480 (synthetic smooth gradients + 5 % salt-and-pepper,
 standing in for the paper's photographs), each filtered with the k x k median
 (replicate border). The headline is k = 17, the paper's teaser configuration.
 
-Inputs are resident in HBM before timing starts; four distinct frames are
-rotated (720 MB of input + output) so the 256 MB MALL cannot hold the working
+Inputs are resident in HBM before timing starts; eight distinct frames are
+rotated (1.4 GB of input + output) so the 256 MB MALL cannot hold the working
 set. One step is one launch (the frame's three planes through
 median_filter_planes), bracketed by HIP events on the stream it runs on; the
 roofline object uses their average duration.
@@ -37,7 +37,7 @@ VALU_LANES_PER_S = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock = 39.3e1
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--steps", type=int, default=50)
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--k", type=int, default=17, help="headline kernel diameter")
     p.add_argument("--sweep-steps", type=int, default=5, help="timed steps per k of the sweep (0 = no sweep)")
@@ -135,6 +135,43 @@ def _time(fn, steps, warmup, stream):
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / 1e3 / steps
+
+
+def measured_peaks(dev, stream):
+    """Measured ceilings beside the public figures: device-to-device copy
+    bandwidth (bytes read + written) and the packed 16-bit min/max rate of
+    dependent instruction chains (mf_peak_minmax)."""
+    import ctypes
+    import torch
+
+    from paper_2507_19926_amd import _lib
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device=dev).fill_(3)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record(stream)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_bps = 2 * n * reps / (e0.elapsed_time(e1) / 1e3)
+    del a, b
+    blocks, iters = 8192, 128
+    out = torch.empty(blocks * 256, dtype=torch.int32, device=dev)
+    L = _lib.lib()
+    h = ctypes.c_void_p(stream.cuda_stream)
+    _lib.check(L.mf_peak_minmax(out.data_ptr(), blocks, iters, h))
+    e0.record(stream)
+    _lib.check(L.mf_peak_minmax(out.data_ptr(), blocks, iters, h))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ops = blocks * 256 * iters * 512
+    return {"copy_TBps": round(copy_bps / 1e12, 3), "copy_frac_of_8TBps": round(copy_bps / HBM_PEAK_BPS, 3),
+            "pk_minmax_Tops": round(ops / (e0.elapsed_time(e1) / 1e3) / 1e12, 2),
+            "pk_minmax_frac_of_peak": round(ops / (e0.elapsed_time(e1) / 1e3) / (2 * VALU_LANES_PER_S), 3)}
 
 
 def run_extras(args, dev, stream):
@@ -245,7 +282,7 @@ def main():
 
     H, W = wl.RGB30_H, wl.RGB30_W
     base = wl.rgb30_planes()
-    nsets = 4
+    nsets = 8
     ins, outs = [], []
     for s in range(nsets):
         frame = base if s == 0 else np.roll(base, shift=97 * s, axis=2)
@@ -299,6 +336,7 @@ def main():
     extras = {}
     if not args.no_extras and not args.only_headline:
         extras = run_extras(args, dev, stream)
+        extras["measured_peaks"] = measured_peaks(dev, stream)
 
     cpu = None
     if not args.no_cpu:

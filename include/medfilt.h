@@ -108,6 +108,15 @@ int32_t median_filter_planes(const void* src, void* dst, int64_t planes,
                              int64_t pitch_bytes, int32_t dtype, int32_t k,
                              int32_t border, const mf_options* opt, void* stream);
 
+/* Diagnostic (not part of the filter): enqueue `blocks` work-groups of 256
+ * threads, each thread running `iters` iterations of 256 dependent packed
+ * 16-bit min/max instructions in 8 independent chains (512 element-ops per
+ * iteration), and write one word per thread to `out` (a device buffer of
+ * blocks*256 uint32). Timing it gives the measured min/max rate that the
+ * oblivious networks' roofline is compared against. MF_ERR_DIMS for a NULL
+ * buffer or non-positive sizes. */
+int32_t mf_peak_minmax(void* out, int32_t blocks, int32_t iters, void* stream);
+
 /* The configuration median_filter_ex would run for (dtype, k, opt): the
  * variant and root tile actually used. Host-only; no GPU needed. */
 int32_t mf_query_config(int32_t dtype, int32_t k, const mf_options* opt,

@@ -100,6 +100,13 @@ def test_planes_entry_validation():
     assert call(planes=1, stride=1) != -3
 
 
+def test_peak_diagnostic_validation():
+    L = _lib.lib()
+    assert L.mf_peak_minmax(None, 1, 1, None) == -2
+    assert L.mf_peak_minmax(FAKE_DST, 0, 1, None) == -2
+    assert L.mf_peak_minmax(FAKE_DST, 1, 0, None) == -2
+
+
 def test_strip_form_listed_and_resolved():
     """The column-strip form exists for k = 3 only, is the last oblivious
     entry (never the default), and a request for it resolves to root tile

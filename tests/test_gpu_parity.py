@@ -281,3 +281,17 @@ def test_oblivious_large_image_persistent(k, tw, th, nw, form, rows):
     ys = np.concatenate([[0, 2099, 0, 2099], g.integers(0, 2100, 3000)])
     xs = np.concatenate([[0, 0, 2999, 2999], g.integers(0, 3000, 3000)])
     assert np.array_equal(got[ys, xs], oracle.median_points(img, k, ys, xs))
+
+
+def test_peak_diagnostic_runs():
+    """The min/max rate diagnostic runs and is deterministic (its output is a
+    function of the thread index only)."""
+    import ctypes
+    out = torch.zeros(4 * 256, dtype=torch.int32, device="cuda")
+    L = _lib.lib()
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _lib.check(L.mf_peak_minmax(out.data_ptr(), 4, 3, s))
+    a = out.clone()
+    _lib.check(L.mf_peak_minmax(out.data_ptr(), 4, 3, s))
+    torch.cuda.synchronize()
+    assert torch.equal(a, out)
