@@ -336,7 +336,9 @@ def main():
     extras = {}
     if not args.no_extras and not args.only_headline:
         extras = run_extras(args, dev, stream)
-        extras["measured_peaks"] = measured_peaks(dev, stream)
+        extras["measured_peaks"] = mp = measured_peaks(dev, stream)
+        if roof["bound"] == "alu" and roof["unit"] == "Tops/s" and roof["peak"] > 70:
+            roof["frac_of_measured_minmax_rate"] = round(roof["achieved"] / mp["pk_minmax_Tops"], 4)
 
     cpu = None
     if not args.no_cpu:
