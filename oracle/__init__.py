@@ -7,7 +7,8 @@ and called through ctypes on host numpy arrays.
 
 What it computes is the definition of the median filter (Sugy 2025, Section 1):
 every output pixel is the rank-(k*k-1)/2 element of the k x k window around it,
-with replicate borders and IEEE totalOrder for float32. ``argmedian_f32`` and
+with replicate borders and IEEE totalOrder for float32; the ``*_rect``
+functions take a kw x kh window (odd sides) instead. ``argmedian_f32`` and
 ``grad_f32`` add the index of the selected input pixel (lowest plane-flat index
 among window pixels bit-equal to the median) and the gradient scatter in
 ascending output order. Each function is pinned by the CPU oracle tests.
@@ -55,6 +56,11 @@ def _load():
     lib.oracle_median_filter.restype = i32
     lib.oracle_median_points.argtypes = [vp, i64, i64, i64, i32, i32, vp, vp, i64, vp, i32]
     lib.oracle_median_points.restype = i32
+    lib.oracle_median_filter_rect.argtypes = [vp, vp, i64, i64, i64, i32, i32, i32, i64, i64, i32]
+    lib.oracle_median_filter_rect.restype = i32
+    lib.oracle_median_points_rect.argtypes = [vp, i64, i64, i64, i32, i32, i32, vp, vp, i64, vp,
+                                              i32]
+    lib.oracle_median_points_rect.restype = i32
     lib.oracle_argmedian_f32.argtypes = [vp, vp, vp, i64, i64, i32, i64, i64, i32]
     lib.oracle_argmedian_f32.restype = i32
     lib.oracle_grad_f32.argtypes = [vp, vp, vp, i64]
@@ -106,6 +112,42 @@ def median_points(img: np.ndarray, k: int, ys, xs, nthreads: int = 0) -> np.ndar
                                       len(ys), _ptr(out), nthreads)
     if rc:
         raise ValueError("oracle_median_points: bad argument (code %d)" % rc)
+    return out
+
+
+def median_filter_rect(img: np.ndarray, kw: int, kh: int, rows: tuple[int, int] | None = None,
+                       nthreads: int = 0) -> np.ndarray:
+    """Median of the kw x kh window (kw columns, kh rows, both odd) of every
+    pixel, replicate border; ``rows`` as in ``median_filter``."""
+    img = _plane(img)
+    H, W = img.shape
+    a, b = (0, H) if rows is None else rows
+    out = np.zeros_like(img)
+    rc = _load().oracle_median_filter_rect(_ptr(img), _ptr(out), H, W, img.strides[0],
+                                           DTYPE_CODE[img.dtype], int(kw), int(kh), a, b,
+                                           nthreads)
+    if rc:
+        raise ValueError("oracle_median_filter_rect: bad argument (code %d)" % rc)
+    return out[a:b].copy() if rows is not None else out
+
+
+def median_points_rect(img: np.ndarray, kw: int, kh: int, ys, xs,
+                       nthreads: int = 0) -> np.ndarray:
+    """kw x kh median at the listed pixels."""
+    img = _plane(img)
+    H, W = img.shape
+    ys = np.ascontiguousarray(ys, dtype=np.int64)
+    xs = np.ascontiguousarray(xs, dtype=np.int64)
+    if ys.shape != xs.shape or ys.ndim != 1:
+        raise ValueError("ys and xs must be 1-D of equal length")
+    if len(ys) and (ys.min() < 0 or ys.max() >= H or xs.min() < 0 or xs.max() >= W):
+        raise ValueError("point outside the image")
+    out = np.zeros(len(ys), dtype=img.dtype)
+    rc = _load().oracle_median_points_rect(_ptr(img), H, W, img.strides[0],
+                                           DTYPE_CODE[img.dtype], int(kw), int(kh), _ptr(ys),
+                                           _ptr(xs), len(ys), _ptr(out), nthreads)
+    if rc:
+        raise ValueError("oracle_median_points_rect: bad argument (code %d)" % rc)
     return out
 
 

@@ -1,5 +1,6 @@
 /*
- * Plain CPU oracle for the exact k x k median filter.
+ * Plain CPU oracle for the exact k x k median filter (and its kw x kh
+ * rectangular generalisation).
  *
  * TEST INFRASTRUCTURE ONLY. This file is the reference that the GPU path is
  * checked against; it is never part of the product path. It shares no code,
@@ -15,6 +16,8 @@
  *   B(i, n) = min(max(i, 0), n-1)                       replicate border
  *   W(y,x)  = { src[B(y+dy,H)][B(x+dx,W)] : dy,dx in [-r, r] }
  *   out(y,x) = element of rank m (0-based) of W(y,x) under the dtype's order
+ * A kw x kh window (odd kw columns, odd kh rows) takes dx in [-(kw-1)/2,
+ * (kw-1)/2], dy in [-(kh-1)/2, (kh-1)/2], N = kw*kh.
  *
  * The paper states no border rule, no float semantics and no gradient; the
  * readings used here are:
@@ -136,40 +139,42 @@ static int64_t select_rank(int64_t* a, int64_t n, int64_t rank)
 }
 
 static int check_args(const void* src, const void* dst, int64_t H, int64_t W,
-                      int64_t pitch_bytes, int dtype, int k)
+                      int64_t pitch_bytes, int dtype, int kw, int kh)
 {
     static const int size_of[4] = {1, 2, 4, 4};
     if (!src || !dst) return -1;
     if (H < 1 || W < 1) return -2;
     if (dtype < 0 || dtype > 3) return -4;
     if (pitch_bytes < W * size_of[dtype] || pitch_bytes % size_of[dtype]) return -3;
-    if (k < 1 || (k % 2) == 0) return -5;
+    if (kw < 1 || (kw % 2) == 0 || kh < 1 || (kh % 2) == 0) return -5;
     return 0;
 }
 
-/* Median of the window around (y, x): fills `buf` (k*k entries) in row-major
- * window order and selects rank m. */
+/* Median of the kw x kh window (kw columns, kh rows) around (y, x): fills
+ * `buf` (kw*kh entries) in row-major window order and selects rank
+ * (kw*kh - 1) / 2. */
 static int64_t window_median(const unsigned char* src, int64_t H, int64_t W,
-                             int64_t pitch_bytes, int dtype, int k,
+                             int64_t pitch_bytes, int dtype, int kw, int kh,
                              int64_t y, int64_t x, int64_t* buf)
 {
-    const int r = (k - 1) / 2;
+    const int rx = (kw - 1) / 2, ry = (kh - 1) / 2;
     int64_t n = 0;
-    for (int dy = -r; dy <= r; ++dy) {
+    for (int dy = -ry; dy <= ry; ++dy) {
         const int64_t yy = clamp_index(y + dy, H);
-        for (int dx = -r; dx <= r; ++dx)
+        for (int dx = -rx; dx <= rx; ++dx)
             buf[n++] = load_key(src, pitch_bytes, dtype, yy, clamp_index(x + dx, W));
     }
     return select_rank(buf, n, (n - 1) / 2);
 }
 
-/* Median filter of rows [row_begin, row_end) of an H x W plane. src and dst
- * share pitch_bytes. Returns 0, or a negative code on a bad argument. */
-int oracle_median_filter(const void* src, void* dst, int64_t H, int64_t W,
-                         int64_t pitch_bytes, int dtype, int k,
-                         int64_t row_begin, int64_t row_end, int nthreads)
+/* Median filter with a kw x kh window (odd sides; kw along rows, kh along
+ * columns) of rows [row_begin, row_end) of an H x W plane. src and dst share
+ * pitch_bytes. Returns 0, or a negative code on a bad argument. */
+int oracle_median_filter_rect(const void* src, void* dst, int64_t H, int64_t W,
+                              int64_t pitch_bytes, int dtype, int kw, int kh,
+                              int64_t row_begin, int64_t row_end, int nthreads)
 {
-    int rc = check_args(src, dst, H, W, pitch_bytes, dtype, k);
+    int rc = check_args(src, dst, H, W, pitch_bytes, dtype, kw, kh);
     if (rc) return rc;
     if (row_begin < 0) row_begin = 0;
     if (row_end > H) row_end = H;
@@ -178,7 +183,7 @@ int oracle_median_filter(const void* src, void* dst, int64_t H, int64_t W,
 #else
     (void)nthreads;
 #endif
-    const int64_t N = (int64_t)k * k;
+    const int64_t N = (int64_t)kw * kh;
 #pragma omp parallel
     {
         int64_t* buf = (int64_t*)malloc((size_t)N * sizeof(int64_t));
@@ -187,19 +192,28 @@ int oracle_median_filter(const void* src, void* dst, int64_t H, int64_t W,
             for (int64_t x = 0; x < W; ++x)
                 store_key((unsigned char*)dst, pitch_bytes, dtype, y, x,
                           window_median((const unsigned char*)src, H, W, pitch_bytes,
-                                        dtype, k, y, x, buf));
+                                        dtype, kw, kh, y, x, buf));
         free(buf);
     }
     return 0;
 }
 
-/* Median at n individual pixels (ys[i], xs[i]); out is a dense array of n
- * elements of the dtype. */
-int oracle_median_points(const void* src, int64_t H, int64_t W, int64_t pitch_bytes,
-                         int dtype, int k, const int64_t* ys, const int64_t* xs,
-                         int64_t n, void* out, int nthreads)
+/* The k x k filter (Section 1). */
+int oracle_median_filter(const void* src, void* dst, int64_t H, int64_t W,
+                         int64_t pitch_bytes, int dtype, int k,
+                         int64_t row_begin, int64_t row_end, int nthreads)
 {
-    int rc = check_args(src, out, H, W, pitch_bytes, dtype, k);
+    return oracle_median_filter_rect(src, dst, H, W, pitch_bytes, dtype, k, k, row_begin, row_end,
+                                     nthreads);
+}
+
+/* Median of the kw x kh window at n individual pixels (ys[i], xs[i]); out is
+ * a dense array of n elements of the dtype. */
+int oracle_median_points_rect(const void* src, int64_t H, int64_t W, int64_t pitch_bytes,
+                              int dtype, int kw, int kh, const int64_t* ys, const int64_t* xs,
+                              int64_t n, void* out, int nthreads)
+{
+    int rc = check_args(src, out, H, W, pitch_bytes, dtype, kw, kh);
     if (rc) return rc;
     if (!ys || !xs) return -1;
 #ifdef _OPENMP
@@ -207,7 +221,7 @@ int oracle_median_points(const void* src, int64_t H, int64_t W, int64_t pitch_by
 #else
     (void)nthreads;
 #endif
-    const int64_t N = (int64_t)k * k;
+    const int64_t N = (int64_t)kw * kh;
     static const int size_of[4] = {1, 2, 4, 4};
     const int64_t out_pitch = n * size_of[dtype];
 #pragma omp parallel
@@ -219,11 +233,18 @@ int oracle_median_points(const void* src, int64_t H, int64_t W, int64_t pitch_by
             if (y < 0 || y >= H || x < 0 || x >= W) continue;
             store_key((unsigned char*)out, out_pitch, dtype, 0, i,
                       window_median((const unsigned char*)src, H, W, pitch_bytes,
-                                    dtype, k, y, x, buf));
+                                    dtype, kw, kh, y, x, buf));
         }
         free(buf);
     }
     return 0;
+}
+
+int oracle_median_points(const void* src, int64_t H, int64_t W, int64_t pitch_bytes,
+                         int dtype, int k, const int64_t* ys, const int64_t* xs,
+                         int64_t n, void* out, int nthreads)
+{
+    return oracle_median_points_rect(src, H, W, pitch_bytes, dtype, k, k, ys, xs, n, out, nthreads);
 }
 
 /* Median value and argmedian of rows [row_begin, row_end) of a contiguous
@@ -232,7 +253,7 @@ int oracle_median_points(const void* src, int64_t H, int64_t W, int64_t pitch_by
 int oracle_argmedian_f32(const float* src, float* val, int32_t* idx, int64_t H, int64_t W,
                          int k, int64_t row_begin, int64_t row_end, int nthreads)
 {
-    int rc = check_args(src, val, H, W, W * 4, OR_F32, k);
+    int rc = check_args(src, val, H, W, W * 4, OR_F32, k, k);
     if (rc) return rc;
     if (!idx) return -1;
     if (row_begin < 0) row_begin = 0;
@@ -251,7 +272,7 @@ int oracle_argmedian_f32(const float* src, float* val, int32_t* idx, int64_t H, 
         for (int64_t y = row_begin; y < row_end; ++y)
             for (int64_t x = 0; x < W; ++x) {
                 int64_t key = window_median((const unsigned char*)src, H, W, W * 4,
-                                            OR_F32, k, y, x, buf);
+                                            OR_F32, k, k, y, x, buf);
                 uint32_t bits = f32_key_to_bits(key);
                 int64_t found = -1;
                 for (int dy = -r; dy <= r && found < 0; ++dy) {

@@ -320,3 +320,85 @@ def test_gradient_order_is_ascending():
     g = np.array([1e8, 1.0, -1e8], dtype=np.float32)
     idx = np.array([0, 0, 0], dtype=np.int32)
     assert oracle.grad_f32(g, idx)[0] == np.float32((np.float32(1e8) + np.float32(1.0)) - np.float32(1e8))
+
+
+# ------------------------------------------------ rectangular kw x kh windows
+
+def _brute_sort_median_rect(img, kw, kh):
+    """Full sort of every replicate-padded kh-row, kw-column window."""
+    ry, rx = (kh - 1) // 2, (kw - 1) // 2
+    pad = np.pad(img, ((ry, ry), (rx, rx)), mode="edge")
+    win = np.lib.stride_tricks.sliding_window_view(pad, (kh, kw))
+    flat = win.reshape(img.shape[0], img.shape[1], kh * kw)
+    return np.sort(flat, axis=-1)[..., (kh * kw - 1) // 2]
+
+
+RECT_SHAPES = [(3, 1), (1, 3), (5, 3), (3, 5), (7, 3), (3, 9), (9, 5), (1, 11), (15, 1), (11, 7)]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("shape", [(1, 1), (1, 6), (7, 1), (9, 14), (16, 11)])
+def test_rect_brute_force_full_sort(dtype, shape):
+    H, W = shape
+    if dtype == np.float32:
+        img = _finite_nonzero_f32(H, W, seed=H * 31 + W)
+    else:
+        img = wl.uniform_plane(H, W, dtype, seed=H * 31 + W)
+    for kw, kh in RECT_SHAPES:
+        np.testing.assert_array_equal(oracle.median_filter_rect(img, kw, kh),
+                                      _brute_sort_median_rect(img, kw, kh),
+                                      err_msg="%dx%d" % (kw, kh))
+
+
+def test_rect_square_is_the_k_by_k_filter():
+    img = wl.tie_heavy_plane(19, 23, np.uint16, levels=5, seed=12)
+    for k in (1, 3, 7, 13):
+        assert oracle.median_filter_rect(img, k, k).tobytes() == oracle.median_filter(img, k).tobytes()
+
+
+def test_rect_transpose_swaps_the_sides():
+    img = wl.uniform_plane(21, 34, np.uint8, seed=13)
+    for kw, kh in RECT_SHAPES:
+        a = oracle.median_filter_rect(img, kw, kh)
+        b = oracle.median_filter_rect(np.ascontiguousarray(img.T), kh, kw).T
+        np.testing.assert_array_equal(a, b, err_msg="%dx%d" % (kw, kh))
+
+
+def test_rect_one_row_is_a_running_median():
+    """kh = 1: each row on its own, the running median of the 1-D signal
+    (np.median of an odd window is its middle order statistic)."""
+    img = wl.uniform_plane(6, 40, np.uint16, seed=14)
+    for kw in (3, 5, 9, 41, 81):
+        r = (kw - 1) // 2
+        pad = np.pad(img, ((0, 0), (r, r)), mode="edge").astype(np.float64)
+        want = np.median(np.lib.stride_tricks.sliding_window_view(pad, kw, axis=1), axis=-1)
+        np.testing.assert_array_equal(oracle.median_filter_rect(img, kw, 1), want.astype(np.uint16))
+        np.testing.assert_array_equal(oracle.median_filter_rect(img.T.copy(), 1, kw), want.T.astype(np.uint16))
+
+
+@pytest.mark.parametrize("kw,kh", [(3, 7), (9, 3), (5, 21), (31, 9)])
+def test_rect_threshold_decomposition_u8(kw, kh):
+    img = wl.rgb30_planes(H=35, W=41, seed=kw * 100 + kh)[1]
+    ry, rx = (kh - 1) // 2, (kw - 1) // 2
+    H, W = img.shape
+    need = (kw * kh + 1) // 2
+    pad = np.pad(img, ((ry, ry), (rx, rx)), mode="edge").astype(np.int32)
+    want = np.zeros((H, W), dtype=np.int32)
+    for tau in range(1, 256):
+        b = (pad >= tau).astype(np.int32)
+        s = np.zeros((b.shape[0] + 1, b.shape[1] + 1), dtype=np.int32)
+        s[1:, 1:] = b.cumsum(0).cumsum(1)
+        cnt = s[kh:kh + H, kw:kw + W] - s[0:H, kw:kw + W] - s[kh:kh + H, 0:W] + s[0:H, 0:W]
+        want += (cnt >= need)
+    np.testing.assert_array_equal(oracle.median_filter_rect(img, kw, kh), want.astype(np.uint8))
+
+
+def test_rect_rows_points_and_bad_sides():
+    img = wl.uniform_plane(30, 26, np.float32, seed=15)
+    full = oracle.median_filter_rect(img, 9, 3)
+    np.testing.assert_array_equal(oracle.median_filter_rect(img, 9, 3, rows=(4, 17)), full[4:17])
+    ys = np.array([0, 29, 13, 2]); xs = np.array([25, 0, 12, 24])
+    np.testing.assert_array_equal(oracle.median_points_rect(img, 9, 3, ys, xs), full[ys, xs])
+    for kw, kh in ((2, 3), (3, 4), (0, 1), (3, -1)):
+        with pytest.raises(ValueError):
+            oracle.median_filter_rect(img, kw, kh)
