@@ -108,6 +108,25 @@ int32_t median_filter_planes(const void* src, void* dst, int64_t planes,
                              int64_t pitch_bytes, int32_t dtype, int32_t k,
                              int32_t border, const mf_options* opt, void* stream);
 
+/* Median of a rectangular window: every output pixel is the median of the
+ * kw x kh window centred on it (kw columns, kh rows, both odd), the
+ * rectangular neighbourhood of the Section 1 definition; the tile terminology
+ * of Section 3.2 (footprint (kw+t_w-1) x (kh+t_h-1), core
+ * (kw-t_w+1) x (kh-t_h+1)) and the recursion of Section 3 carry over with
+ * separate horizontal and vertical radii. Arguments, planes and errors as in
+ * median_filter_planes. kw == kh is the square filter (median_filter_planes
+ * with default options, any k up to mf_max_k()). A rectangular window runs
+ * the data-aware variant (Section 5) with one generated schedule per shape;
+ * both sides must lie in [1, mf_max_rect_side()] (MF_ERR_K otherwise). */
+int32_t median_filter_rect(const void* src, void* dst, int64_t planes,
+                           int64_t plane_stride_bytes, int64_t H, int64_t W,
+                           int64_t pitch_bytes, int32_t dtype, int32_t kw, int32_t kh,
+                           int32_t border, void* stream);
+
+/* Largest side of a rectangular (kw != kh) window median_filter_rect
+ * accepts. */
+int32_t mf_max_rect_side(void);
+
 /* Diagnostic (not part of the filter): enqueue `blocks` work-groups of 256
  * threads, each thread running `iters` iterations of 256 dependent packed
  * 16-bit min/max instructions in 8 independent chains (512 element-ops per

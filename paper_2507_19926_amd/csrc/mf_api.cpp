@@ -211,7 +211,55 @@ int32_t mf_internal_resolve(int32_t dtype, int32_t k, int32_t* variant, int32_t*
     return MF_OK;
 }
 
+// Plane count and stride of a multi-plane call (src, dst and the single-plane
+// arguments already validated). planes = 1 sets the stride to 0.
+static int32_t check_planes(const void* src, const void* dst, int64_t planes, int64_t* plane_stride_bytes,
+                            int64_t H, int64_t W, int64_t pitch_bytes, int32_t dtype)
+{
+    const int s = elem_size(dtype);
+    const int64_t plane_bytes = (H - 1) * pitch_bytes + W * s;
+    if (planes < 1 || planes > ((int64_t)1 << 30))
+        return fail(MF_ERR_DIMS, "planes=%lld outside [1, 2^30]", (long long)planes);
+    if (planes > 1) {
+        const int64_t ps = *plane_stride_bytes;
+        if (ps < plane_bytes || ps % s || ps > ((int64_t)1 << 46))
+            return fail(MF_ERR_PITCH, "plane stride %lld: planes of %lld bytes would overlap or misalign",
+                        (long long)ps, (long long)plane_bytes);
+        const uintptr_t a0 = (uintptr_t)src, b0 = (uintptr_t)dst;
+        const uintptr_t len = (uintptr_t)((planes - 1) * ps + plane_bytes);
+        if (a0 < b0 + len && b0 < a0 + len) return fail(MF_ERR_ALIAS, "src and dst plane ranges overlap");
+    } else {
+        *plane_stride_bytes = 0;
+    }
+    return MF_OK;
+}
+
 extern "C" {
+
+int32_t median_filter_rect(const void* src, void* dst, int64_t planes, int64_t plane_stride_bytes, int64_t H,
+                           int64_t W, int64_t pitch_bytes, int32_t dtype, int32_t kw, int32_t kh, int32_t border,
+                           void* stream)
+{
+    g_last_error.clear();
+    if (kw == kh)
+        return median_filter_planes(src, dst, planes, plane_stride_bytes, H, W, pitch_bytes, dtype, kw, border,
+                                    nullptr, stream);
+    // k = 1 stands for the window in the shared checks (it passes the k test)
+    int32_t rc = validate(src, dst, H, W, pitch_bytes, dtype, 1, border);
+    if (rc) return rc;
+    const int side = mf_da_rect_max_side();
+    if (kw < 1 || kh < 1 || kw % 2 == 0 || kh % 2 == 0 || kw > side || kh > side)
+        return fail(MF_ERR_K, "window %dx%d: a rectangular window needs odd sides in [1, %d]", kw, kh, side);
+    rc = check_planes(src, dst, planes, &plane_stride_bytes, H, W, pitch_bytes, dtype);
+    if (rc) return rc;
+    if (!mf_da_supports(dtype, kw, 0, 0, 0, kh))
+        return fail(MF_ERR_CONFIG, "no data-aware schedule for the %dx%d window", kw, kh);
+    return hip_status(mf_da_launch(src, dst, (int)planes, plane_stride_bytes, (int)H, (int)W, pitch_bytes, dtype, kw,
+                                   0, 0, 0, (hipStream_t)stream, kh),
+                      "data-aware kernel launch");
+}
+
+int32_t mf_max_rect_side(void) { return mf_da_rect_max_side(); }
 
 int32_t median_filter_planes(const void* src, void* dst, int64_t planes, int64_t plane_stride_bytes, int64_t H,
                              int64_t W, int64_t pitch_bytes, int32_t dtype, int32_t k, int32_t border,
@@ -220,20 +268,9 @@ int32_t median_filter_planes(const void* src, void* dst, int64_t planes, int64_t
     g_last_error.clear();
     int32_t rc = validate(src, dst, H, W, pitch_bytes, dtype, k, border);
     if (rc) return rc;
+    rc = check_planes(src, dst, planes, &plane_stride_bytes, H, W, pitch_bytes, dtype);
+    if (rc) return rc;
     const int s = elem_size(dtype);
-    const int64_t plane_bytes = (H - 1) * pitch_bytes + W * s;
-    if (planes < 1 || planes > ((int64_t)1 << 30))
-        return fail(MF_ERR_DIMS, "planes=%lld outside [1, 2^30]", (long long)planes);
-    if (planes > 1) {
-        if (plane_stride_bytes < plane_bytes || plane_stride_bytes % s || plane_stride_bytes > ((int64_t)1 << 46))
-            return fail(MF_ERR_PITCH, "plane stride %lld: planes of %lld bytes would overlap or misalign",
-                        (long long)plane_stride_bytes, (long long)plane_bytes);
-        const uintptr_t a0 = (uintptr_t)src, b0 = (uintptr_t)dst;
-        const uintptr_t len = (uintptr_t)((planes - 1) * plane_stride_bytes + plane_bytes);
-        if (a0 < b0 + len && b0 < a0 + len) return fail(MF_ERR_ALIAS, "src and dst plane ranges overlap");
-    } else {
-        plane_stride_bytes = 0;
-    }
     hipStream_t st = (hipStream_t)stream;
     if (k == 1) {
         for (int64_t p = 0; p < planes; ++p) {

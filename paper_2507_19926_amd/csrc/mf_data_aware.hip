@@ -9,6 +9,10 @@
 // (Sections 3.3-3.4, 5.1). The paper's global-memory multi-pass structure is
 // replaced by this LDS-resident sequence of rounds separated by barriers.
 //
+// The window may be rectangular (k columns by kh rows, both odd): the
+// schedule encodes the recursion for its footprint, the kernel only needs the
+// two radii to place the footprint.
+//
 // Each round is a list of merge-path chunks: a lane finds the chunk's start in
 // its two sorted input windows with a co-rank binary search and then merges
 // up to 16 outputs sequentially. A work-group holds T root tiles (T arenas)
@@ -26,8 +30,9 @@
 
 namespace {
 
+// one schedule: window k x kh (columns x rows), LDS element size, root tile
 struct DaEntry {
-    int k, es, tw, th, tiles, c_off, nchunks, r_off, nrounds, o_off, arena;
+    int k, kh, es, tw, th, tiles, c_off, nchunks, r_off, nrounds, o_off, arena;
 };
 
 const DaEntry kDaTable[] = {MF_DA_TABLE_ENTRIES};
@@ -62,18 +67,18 @@ mf_da_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
 {
     extern __shared__ __align__(16) unsigned char mf_da_lds[];
     E* lds = reinterpret_cast<E*>(mf_da_lds);
-    const int k = a.k, tw = a.tw, th = a.th, arena = a.arena;
+    const int tw = a.tw, th = a.th, arena = a.arena;
     const uint32_t* __restrict__ blob = a.blob;
-    const int r = (k - 1) / 2;
-    const int fw = k + tw - 1, fh = k + th - 1;
+    const int rx = (a.k - 1) / 2, ry = (a.kh - 1) / 2;
+    const int fw = a.k + tw - 1, fh = a.kh + th - 1;
     const int Y0 = by * th;
 
     // footprints -> LDS, row-major fw x fh per tile (replicate border)
     for (int i = threadIdx.x; i < T * fw * fh; i += kDaThreads) {
         const int t = i / (fw * fh), e = i - t * fw * fh;
         const int y = e / fw, x = e - y * fw;
-        const int gy = min(max(Y0 - r + y, 0), H - 1);
-        const int gx = min(max((bx * T + t) * tw - r + x, 0), W - 1);
+        const int gy = min(max(Y0 - ry + y, 0), H - 1);
+        const int gx = min(max((bx * T + t) * tw - rx + x, 0), W - 1);
         const unsigned char* row = src + (long long)gy * pitch;
         uint32_t v;
         if (dtype == MF_U8) v = row[gx];
@@ -253,12 +258,14 @@ const void* da_kernel_for(const DaEntry* e, bool batched)
 
 namespace {
 
-const DaEntry* da_find(int dtype, int k, int tw, int th, int group)
+// kh = 0: the square k x k window
+const DaEntry* da_find(int dtype, int k, int tw, int th, int group, int kh = 0)
 {
     const int es = (dtype == MF_U8 || dtype == MF_U16) ? 2 : 4;
+    if (kh == 0) kh = k;
     for (int i = 0; i < kDaCount; ++i) {
         const DaEntry& e = kDaTable[i];
-        if (e.k == k && e.es == es && (tw == 0 || e.tw == tw) && (th == 0 || e.th == th) &&
+        if (e.k == k && e.kh == kh && e.es == es && (tw == 0 || e.tw == tw) && (th == 0 || e.th == th) &&
             (group == 0 || e.tiles == group))
             return &e;
     }
@@ -298,10 +305,12 @@ hipError_t da_blob(const uint32_t** out)
 
 }  // namespace
 
-bool mf_da_supports(int dtype, int k, int tw, int th, int group)
+bool mf_da_supports(int dtype, int k, int tw, int th, int group, int kh)
 {
-    return da_find(dtype, k, tw, th, group) != nullptr;
+    return da_find(dtype, k, tw, th, group, kh) != nullptr;
 }
+
+int mf_da_rect_max_side() { return MF_DA_RECT_MAX_SIDE; }
 
 void mf_da_default_tile(int dtype, int k, int* tw, int* th, int* group)
 {
@@ -317,7 +326,7 @@ int mf_da_list(int dtype, int k, int* tw, int* th, int* group, int cap)
     int n = 0;
     for (int i = 0; i < kDaCount; ++i) {
         const DaEntry& e = kDaTable[i];
-        if (e.k != k || e.es != es) continue;
+        if (e.k != k || e.kh != k || e.es != es) continue;
         if (n < cap) {
             tw[n] = e.tw;
             th[n] = e.th;
@@ -333,6 +342,7 @@ static MfDaArgs da_args(const DaEntry* e, const uint32_t* blob)
     MfDaArgs a;
     a.blob = blob;
     a.k = e->k;
+    a.kh = e->kh;
     a.tw = e->tw;
     a.th = e->th;
     a.c_off = e->c_off;
@@ -344,15 +354,16 @@ static MfDaArgs da_args(const DaEntry* e, const uint32_t* blob)
 }
 
 hipError_t mf_da_launch(const void* src, void* dst, int planes, long long plane_stride, int H, int W,
-                        long long pitch, int dtype, int k, int tw, int th, int group, hipStream_t stream)
+                        long long pitch, int dtype, int k, int tw, int th, int group, hipStream_t stream, int kh)
 {
-    const DaEntry* e = da_find(dtype, k, tw, th, group);
+    const DaEntry* e = da_find(dtype, k, tw, th, group, kh);
     if (!e) return hipErrorInvalidValue;
     const uint32_t* blob = nullptr;
     hipError_t err = da_blob(&blob);
     if (err != hipSuccess) return err;
     MfDaArgs a = da_args(e, blob);
     const int ntx = (W + e->tw * e->tiles - 1) / (e->tw * e->tiles), nty = (H + e->th - 1) / e->th;
+    if ((long long)ntx * nty > 0x7fffffffLL) return hipErrorInvalidConfiguration;   // grid.x limit
     const size_t lds = (size_t)e->arena * e->es * e->tiles;
     for (int p0 = 0; p0 < planes; p0 += 65535) {     // grid rows are planes
         const int np = planes - p0 < 65535 ? planes - p0 : 65535;

@@ -50,10 +50,15 @@ hipError_t mf_strip3_launch_p16(const void* src, void* dst, int planes, long lon
 hipError_t mf_strip3_launch_u32(const void* src, void* dst, int planes, long long plane_stride, int H, int W,
                                 long long pitch, int dtype, hipStream_t stream);
 
-// Data-aware launcher: one per value class, any k up to mf_max_k().
+// Data-aware launcher: one per value class, any k up to mf_max_k(). kh = 0 is
+// the square k x k window; otherwise the window is k columns by kh rows (a
+// generated rectangular shape, both sides odd and at most
+// mf_da_rect_max_side()).
 hipError_t mf_da_launch(const void* src, void* dst, int planes, long long plane_stride, int H, int W,
-                        long long pitch, int dtype, int k, int tw, int th, int group, hipStream_t stream);
-bool mf_da_supports(int dtype, int k, int tw, int th, int group);
+                        long long pitch, int dtype, int k, int tw, int th, int group, hipStream_t stream,
+                        int kh = 0);
+bool mf_da_supports(int dtype, int k, int tw, int th, int group, int kh = 0);
+int mf_da_rect_max_side();
 void mf_da_default_tile(int dtype, int k, int* tw, int* th, int* group);
 // Data-aware entries for (dtype, k): fills up to cap (tw, th, group) triples,
 // returns the count.
@@ -62,7 +67,7 @@ int mf_da_list(int dtype, int k, int* tw, int* th, int* group, int cap);
 // schedule offsets are filled into *args (see mf_da_batched_args).
 struct MfDaArgs {
     const uint32_t* blob;
-    int k, tw, th, c_off, r_off, nrounds, o_off, arena;
+    int k, kh, tw, th, c_off, r_off, nrounds, o_off, arena;   // window k columns x kh rows
 };
 hipError_t mf_da_batched(int dtype, int k, int tw, int th, int group, MfBatchedKernel* kern, MfDaArgs* args);
 

@@ -115,16 +115,23 @@ def trim(ref: tuple, unseen: int) -> tuple:
     return (n, lo + d, lo + d + keep)
 
 
-def build_dag(k: int, tw: int, th: int):
+def build_dag(k: int, tw: int, th: int, kh: int | None = None):
     """DAG of the hierarchical recursion for one tw x th root tile.
+
+    The window is k columns by kh rows (kh defaults to k: the square filter);
+    the footprint is (k+tw-1) x (kh+th-1) and the core of a tile is the
+    intersection of its pixels' windows, so every split, added column or row
+    and forgetful trim follows from those two sides.
 
     Returns (dag, outputs) with outputs[py*tw+px] a (node, lo, lo+1) view of
     that pixel's median."""
-    assert k % 2 == 1 and tw <= k and th <= k
-    D = Dag(k + tw - 1)
-    N = k * k
-    core_y = range(th - 1, k)
-    core_x = range(tw - 1, k)
+    kw = k
+    kh = k if kh is None else kh
+    assert kw % 2 == 1 and kh % 2 == 1 and tw <= kw and th <= kh
+    D = Dag(kw + tw - 1)
+    N = kw * kh
+    core_y = range(th - 1, kh)
+    core_x = range(tw - 1, kw)
 
     def col(x, ys):
         D.role = "sort_col"
@@ -139,8 +146,8 @@ def build_dag(k: int, tw: int, th: int):
     D.role = "core_init"
     core = D.reduce(cols)
     core = trim(core, N - len(core_x) * len(core_y))
-    xcols = {x: col(x, core_y) for x in list(range(0, tw - 1)) + list(range(k, k + tw - 1))}
-    xrows = {y: row(y, core_x) for y in list(range(0, th - 1)) + list(range(k, k + th - 1))}
+    xcols = {x: col(x, core_y) for x in list(range(0, tw - 1)) + list(range(kw, kw + tw - 1))}
+    xrows = {y: row(y, core_x) for y in list(range(0, th - 1)) + list(range(kh, kh + th - 1))}
     outputs = {}
 
     def recurse(ox, oy, w, h, core, xcols, xrows, level):
@@ -152,14 +159,14 @@ def build_dag(k: int, tw: int, th: int):
         children = []
         if w >= h:
             hh = w // 2
-            for cox, added in ((ox, range(ox + hh - 1, ox + w - 1)), (ox + hh, range(ox + k, ox + k + hh))):
+            for cox, added in ((ox, range(ox + hh - 1, ox + w - 1)), (ox + hh, range(ox + kw, ox + kw + hh))):
                 D.phase = level + 1
                 D.role = "core_extra"
                 e = D.reduce([xcols[x] for x in added])
                 D.role = "core_merge"
                 c = D.merge(core, e)
-                c = trim(c, N - (k - hh + 1) * (k - h + 1))
-                ncols = {x: xcols[x] for x in list(range(cox, cox + hh - 1)) + list(range(cox + k, cox + k + hh - 1))}
+                c = trim(c, N - (kw - hh + 1) * (kh - h + 1))
+                ncols = {x: xcols[x] for x in list(range(cox, cox + hh - 1)) + list(range(cox + kw, cox + kw + hh - 1))}
                 nrows = {}
                 for y, r in xrows.items():
                     D.role = "sort_corner"
@@ -169,14 +176,14 @@ def build_dag(k: int, tw: int, th: int):
                 children.append((cox, oy, hh, h, c, ncols, nrows))
         else:
             hh = h // 2
-            for coy, added in ((oy, range(oy + hh - 1, oy + h - 1)), (oy + hh, range(oy + k, oy + k + hh))):
+            for coy, added in ((oy, range(oy + hh - 1, oy + h - 1)), (oy + hh, range(oy + kh, oy + kh + hh))):
                 D.phase = level + 1
                 D.role = "core_extra"
                 e = D.reduce([xrows[y] for y in added])
                 D.role = "core_merge"
                 c = D.merge(core, e)
-                c = trim(c, N - (k - w + 1) * (k - hh + 1))
-                nrows = {y: xrows[y] for y in list(range(coy, coy + hh - 1)) + list(range(coy + k, coy + k + hh - 1))}
+                c = trim(c, N - (kw - w + 1) * (kh - hh + 1))
+                nrows = {y: xrows[y] for y in list(range(coy, coy + hh - 1)) + list(range(coy + kh, coy + kh + hh - 1))}
                 ncols = {}
                 for x, cl in xcols.items():
                     D.role = "sort_corner"
@@ -215,7 +222,7 @@ def propagate_windows(D: Dag, outs: list[tuple]) -> None:
 
 @dataclass
 class Schedule:
-    k: int
+    k: int                      # window columns
     tw: int
     th: int
     fw: int
@@ -226,6 +233,15 @@ class Schedule:
     arena: int                  # elements of LDS the schedule needs
     merge_outputs: int          # elements produced by all merges
     stats: dict
+    kh: int = 0                 # window rows (0: k, the square filter)
+
+    @property
+    def kw(self) -> int:
+        return self.k
+
+    @property
+    def rows(self) -> int:
+        return self.kh or self.k
 
 
 def _window_inputs(n: Node):
@@ -249,14 +265,16 @@ def _window_inputs(n: Node):
     return res[0], res[1], r0
 
 
-def schedule(k: int, tw: int, th: int, chunk: int = CHUNK, lanes: int = LANES) -> Schedule:
+def schedule(k: int, tw: int, th: int, chunk: int = CHUNK, lanes: int = LANES,
+             kh: int | None = None) -> Schedule:
     """Rounds of windowed merges for root tile tw x th. Every round's outputs
     are cut into chunks of max(chunk, ceil(outputs / lanes)) so that one
     round keeps about `lanes` threads busy with chains as short as the round
     allows (a lane runs a co-rank search, then its chunk sequentially)."""
-    D, outs = build_dag(k, tw, th)
+    kh = k if kh is None else kh
+    D, outs = build_dag(k, tw, th, kh)
     propagate_windows(D, outs)
-    fw, fh = k + tw - 1, k + th - 1
+    fw, fh = k + tw - 1, kh + th - 1
     merges = [n for n in D.nodes if n.a is not None and n.need_hi > n.need_lo]
     # rounds: per phase, ASAP by dependency depth within the phase
     depth = {}
@@ -372,7 +390,7 @@ def schedule(k: int, tw: int, th: int, chunk: int = CHUNK, lanes: int = LANES) -
           "merges": len(merges)}
     return Schedule(k, tw, th, fw, fh, np.array(chunks, dtype=np.uint32).reshape(-1, 4),
                     np.array(rounds, dtype=np.int32), np.array(outputs, dtype=np.int32), peak,
-                    merge_outputs, st)
+                    merge_outputs, st, kh)
 
 
 # ------------------------------------------------------------- CPU model
@@ -383,12 +401,11 @@ def run_schedule_on_image(S: Schedule, img: np.ndarray, exact_merge_path: bool =
     Each chunk merges its two input windows and keeps ranks [r0, r0+n); with
     exact_merge_path the chunk is executed the way the kernel does it (co-rank
     binary search, then a sequential merge), per tile."""
-    k, tw, th = S.k, S.tw, S.th
+    kw, kh, tw, th = S.kw, S.rows, S.tw, S.th
     H, W = img.shape
-    r = (k - 1) // 2
     nty, ntx = -(-H // th), -(-W // tw)
-    ys = np.clip(np.arange(nty * th + k - 1) - r, 0, H - 1)
-    xs = np.clip(np.arange(ntx * tw + k - 1) - r, 0, W - 1)
+    ys = np.clip(np.arange(nty * th + kh - 1) - (kh - 1) // 2, 0, H - 1)
+    xs = np.clip(np.arange(ntx * tw + kw - 1) - (kw - 1) // 2, 0, W - 1)
     pad = img[ys][:, xs]
     win = np.lib.stride_tricks.sliding_window_view(pad, (S.fh, S.fw))[::th, ::tw]
     T = nty * ntx

@@ -1,18 +1,22 @@
 """Emit the data-aware schedules (dagen) as a binary blob plus a host table.
 
-For every odd k in 3..75 and each LDS element size (2 bytes for 8/16-bit
-data, 4 bytes for 32-bit data) a root tile is chosen: the one with the lowest
-estimated work per pixel (merge outputs, co-rank searches, footprint loads)
-whose LDS arena fits the budget. Schedules depend only on (k, t_w, t_h) and
-are stored once each.
+For every odd k in 3..75 (square windows) and every rectangular window
+k_w x k_h with odd sides up to RECT_MAX_SIDE, and each LDS element size
+(2 bytes for 8/16-bit data, 4 bytes for 32-bit data), root tiles are chosen:
+per LDS budget the one with the lowest estimated work per pixel (merge
+outputs, co-rank searches, footprint loads) whose arena fits. Schedules depend
+only on (k_w, k_h, t_w, t_h) and are stored once each; they are computed in a
+process pool.
 
 Outputs in the generated directory:
 * mf_da_blob.bin   -- all schedules, little-endian uint32 words;
-* mf_da_table.h    -- size of the blob and one entry per (k, element size).
+* mf_da_table.h    -- size of the blob and one entry per (k_w, k_h, element
+  size, tile).
 """
 from __future__ import annotations
 
 import os
+from concurrent.futures import ProcessPoolExecutor
 
 import numpy as np
 
@@ -21,6 +25,22 @@ from . import dagen
 LDS_BYTES = 160 * 1024
 KS = list(range(3, 76, 2))
 TILE_CANDIDATES = [(t, t) for t in (1, 2, 4, 8, 16, 32)] + [(2 * t, t) for t in (1, 2, 4, 8, 16)]
+# rectangular windows: both sides odd, 1..RECT_MAX_SIDE, sides different
+RECT_MAX_SIDE = 31
+RECT_SHAPES = [(kw, kh) for kw in range(1, RECT_MAX_SIDE + 1, 2)
+               for kh in range(1, RECT_MAX_SIDE + 1, 2) if kw != kh]
+
+
+def tile_options(kw: int, kh: int) -> list:
+    """Root tiles tried for a kw x kh window: power-of-two sides, t_w <= kw,
+    t_h <= kh (a non-empty core); square windows use TILE_CANDIDATES,
+    rectangular ones every aspect ratio up to 4:1 either way."""
+    if kw == kh:
+        opts = TILE_CANDIDATES
+    else:
+        p2 = (1, 2, 4, 8, 16, 32)
+        opts = [(tw, th) for tw in p2 for th in p2 if max(tw, th) <= 4 * min(tw, th)]
+    return [(tw, th) for (tw, th) in opts if tw <= kw and th <= kh]
 
 
 def _cost(S: dagen.Schedule) -> float:
@@ -32,25 +52,31 @@ def _cost(S: dagen.Schedule) -> float:
 LDS_BUDGETS = (LDS_BYTES // 3, LDS_BYTES // 2, LDS_BYTES)
 
 
-def candidates(k: int, elem_bytes: int, cache: dict):
-    """(tile_w, tile_h, tiles per work-group) options for k, best first.
+def _schedule_or_none(key):
+    kw, kh, tw, th = key
+    try:
+        return dagen.schedule(kw, tw, th, kh=kh)
+    except (AssertionError, RuntimeError):
+        return None
+
+
+def candidates(k: int, elem_bytes: int, cache: dict, kh: int | None = None,
+               budgets=LDS_BUDGETS):
+    """(tile_w, tile_h, tiles per work-group) options for a k x kh window
+    (kh defaults to k), best first.
 
     One root tile per work-group. For each LDS budget (3, 2 or 1 work-groups
     per CU) the root tile with the lowest estimated work whose arena fits;
     duplicates removed. More work-groups per CU hide more of the merge rounds'
     latency, larger tiles amortise more work: the tuner decides."""
+    kh = k if kh is None else kh
     out = []
-    for budget in LDS_BUDGETS:
+    for budget in budgets:
         best = None
-        for (tw, th) in TILE_CANDIDATES:
-            if tw > k or th > k:
-                continue
-            key = (k, tw, th)
+        for (tw, th) in tile_options(k, kh):
+            key = (k, kh, tw, th)
             if key not in cache:
-                try:
-                    cache[key] = dagen.schedule(k, tw, th)
-                except (AssertionError, RuntimeError):
-                    cache[key] = None
+                cache[key] = _schedule_or_none(key)
             S = cache[key]
             if S is None or S.arena * elem_bytes > budget:
                 continue
@@ -65,22 +91,44 @@ def candidates(k: int, elem_bytes: int, cache: dict):
     return out
 
 
-def choose_tile(k: int, elem_bytes: int, cache: dict):
-    tw, th, _ = candidates(k, elem_bytes, cache)[0]
-    return (k, tw, th)
+def choose_tile(k: int, elem_bytes: int, cache: dict, kh: int | None = None):
+    kh = k if kh is None else kh
+    tw, th, _ = candidates(k, elem_bytes, cache, kh)[0]
+    return (k, kh, tw, th)
 
 
-def generate(out_dir: str) -> dict:
+def windows() -> list:
+    """Every (k_w, k_h) the generated table covers."""
+    return [(k, k) for k in KS] + RECT_SHAPES
+
+
+def generate(out_dir: str, workers: int | None = None) -> dict:
     os.makedirs(out_dir, exist_ok=True)
-    cache: dict = {}
+    keys = [(kw, kh, tw, th) for (kw, kh) in windows() for (tw, th) in tile_options(kw, kh)]
+    # largest first so that the pool's tail is short
+    keys.sort(key=lambda t: -(t[0] + t[2]) * (t[1] + t[3]))
+    workers = workers or min(8, os.cpu_count() or 1)
+    if workers > 1:
+        with ProcessPoolExecutor(max_workers=workers) as ex:
+            cache = dict(zip(keys, ex.map(_schedule_or_none, keys, chunksize=4)))
+    else:
+        cache = {key: _schedule_or_none(key) for key in keys}
     entries = []
     placed = {}
     words: list[np.ndarray] = []
     pos = 0
     for es in (2, 4):
-        for k in KS:
-            for (tw, th, T) in candidates(k, es, cache):
-                key = (k, tw, th)
+        for (kw, kh) in windows():
+            # rectangular windows keep one tile (no tuned choice), shared by
+            # both element sizes: the best one that lets three work-groups of
+            # 32-bit elements share a CU, the budget most square windows up
+            # to k = 31 are tuned to
+            if kw == kh:
+                opts = candidates(kw, es, cache)
+            else:
+                opts = candidates(kw, 4, cache, kh, LDS_BUDGETS[:1])
+            for (tw, th, T) in opts:
+                key = (kw, kh, tw, th)
                 if key not in placed:
                     S = cache[key]
                     ch = S.chunks.reshape(-1).astype(np.uint32)
@@ -99,20 +147,22 @@ def generate(out_dir: str) -> dict:
                     words.append(ou); pos += len(ou)
                     placed[key] = (c_off, len(S.chunks), r_off, len(S.rounds) - 1, o_off, S.arena)
                 c_off, nch, r_off, nr, o_off, arena = placed[key]
-                entries.append((k, es) + key[1:] + (T, c_off, nch, r_off, nr, o_off, arena))
+                entries.append((kw, kh, es, tw, th, T, c_off, nch, r_off, nr, o_off, arena))
     blob = np.concatenate(words).astype("<u4")
     bpath = os.path.join(out_dir, "mf_da_blob.bin")
     data = blob.tobytes()
     if not os.path.exists(bpath) or open(bpath, "rb").read() != data:
         with open(bpath, "wb") as f:
             f.write(data)
-    lines = ["// Generated by emit_da.py: data-aware schedules, one entry per (k, LDS element size).",
+    lines = ["// Generated by emit_da.py: data-aware schedules, one entry per",
+             "// (k_w, k_h, LDS element size, root tile).",
              "#pragma once",
              "#define MF_DA_BLOB_WORDS %d" % len(blob),
              "#define MF_DA_CHUNK %d" % dagen.CHUNK,
+             "#define MF_DA_RECT_MAX_SIDE %d" % RECT_MAX_SIDE,
              "#define MF_DA_TABLE_ENTRIES \\"]
     for e in entries:
-        lines.append("    {%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d}, \\" % e)
+        lines.append("    {%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d}, \\" % e)
     lines.append("")
     text = "\n".join(lines) + "\n"
     hpath = os.path.join(out_dir, "mf_da_table.h")

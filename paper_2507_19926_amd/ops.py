@@ -69,6 +69,39 @@ def median_filter(x: torch.Tensor, k: int, out: torch.Tensor | None = None,
     return out
 
 
+def median_filter_rect(x: torch.Tensor, kw: int, kh: int,
+                       out: torch.Tensor | None = None) -> torch.Tensor:
+    """Exact median of the kw x kh window (kw columns, kh rows, both odd;
+    replicate border) of every (H, W) plane of x, through
+    median_filter_rect. Layout rules as in ``median_filter``; the planes must
+    be equally spaced (one call)."""
+    if not x.is_cuda:
+        raise ValueError("median_filter_rect needs a GPU tensor")
+    if x.dim() < 2:
+        raise ValueError("median_filter_rect needs (..., H, W)")
+    code = dtype_code(x.dtype)
+    if x.stride(-1) != 1:
+        x = x.contiguous()
+    H, W = x.shape[-2], x.shape[-1]
+    if out is None:
+        out = torch.empty(x.shape, dtype=x.dtype, device=x.device)
+    if out.shape != x.shape or out.dtype != x.dtype or out.stride() != x.stride():
+        raise ValueError("out must match x in shape, dtype and strides")
+    es = x.element_size()
+    pitch = x.stride(-2) * es
+    planes_x = x.reshape(-1, H, W) if x.dim() > 2 else x.unsqueeze(0)
+    if planes_x.data_ptr() != x.data_ptr():
+        raise ValueError("leading dimensions must be collapsible")
+    n = planes_x.shape[0]
+    if n == 0:
+        return out
+    stride = planes_x.stride(0) * es if n > 1 else 0
+    _lib.check(_lib.lib().median_filter_rect(x.data_ptr(), out.data_ptr(), n, stride, H, W, pitch, code,
+                                             int(kw), int(kh), _lib.MF_BORDER_REPLICATE,
+                                             _stream_handle(x.device)))
+    return out
+
+
 def median_filter_argmedian(x: torch.Tensor, k: int):
     """(y, idx) for a float32 tensor (..., H, W): the median and, per output
     pixel, the plane-local flat index of the input pixel it was taken from

@@ -100,6 +100,29 @@ def test_planes_entry_validation():
     assert call(planes=1, stride=1) != -3
 
 
+def test_rect_entry_validation():
+    """median_filter_rect: both sides odd in [1, mf_max_rect_side()] for a
+    rectangular window, the plain image and plane checks as in
+    median_filter_planes."""
+    L = _lib.lib()
+    side = L.mf_max_rect_side()
+    assert side >= 31
+
+    def call(kw=5, kh=3, planes=1, stride=0, src=FAKE_SRC, dst=FAKE_DST, H=16, W=16, pitch=16, dtype=0,
+             border=0):
+        return L.median_filter_rect(src, dst, planes, stride, H, W, pitch, dtype, kw, kh, border, None)
+
+    for kw, kh in ((4, 3), (3, 4), (0, 3), (3, -1), (side + 2, 3), (3, side + 2)):
+        assert call(kw=kw, kh=kh) == -5, (kw, kh)
+    assert call(kw=4, kh=4) == -5                    # square: the k x k rules
+    assert call(kw=77, kh=77) == -5
+    assert call(src=None) == -1 and call(H=0) == -2 and call(pitch=15) == -3
+    assert call(dtype=9) == -4 and call(border=2) == -6 and call(dst=FAKE_SRC + 8) == -7
+    assert call(planes=0) == -2 and call(planes=2, stride=255) == -3
+    assert call(planes=3, stride=256, dst=FAKE_SRC + 600) == -7
+    assert L.mf_last_error().decode() != ""
+
+
 def test_peak_diagnostic_validation():
     L = _lib.lib()
     assert L.mf_peak_minmax(None, 1, 1, None) == -2

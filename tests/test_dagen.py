@@ -49,5 +49,32 @@ def test_library_tiles_fit_lds():
             key = emit_da.choose_tile(k, es, cache)
             S = cache[key]
             assert S.arena * es <= emit_da.LDS_BYTES
-            assert S.chunks.shape[1] == 4 and len(S.outputs) == key[1] * key[2]
+            assert S.chunks.shape[1] == 4 and len(S.outputs) == key[2] * key[3]
+    for kw, kh in ((31, 3), (1, 29), (17, 5)):
+        for es in (2, 4):
+            key = emit_da.choose_tile(kw, es, cache, kh)
+            S = cache[key]
+            assert S.arena * es <= emit_da.LDS_BYTES and (S.kw, S.rows) == (kw, kh)
+            assert key[2] <= kw and key[3] <= kh and len(S.outputs) == key[2] * key[3]
+
+
+@pytest.mark.parametrize("kw,kh,tw,th", [(5, 3, 2, 2), (3, 7, 2, 4), (9, 5, 4, 4), (7, 1, 4, 1),
+                                         (1, 9, 1, 8), (15, 5, 8, 4), (11, 21, 8, 16), (31, 7, 16, 4)])
+def test_rect_schedule_matches_oracle(kw, kh, tw, th):
+    """The generated recursion for a rectangular window (separate horizontal
+    and vertical radii) reproduces the oracle's kw x kh median, merged with
+    sorts and with the kernel's merge-path chunks."""
+    img = wl.uniform_plane(23, 29, np.uint8, seed=kw * 64 + kh)
+    S = dg.schedule(kw, tw, th, kh=kh)
+    assert (S.fw, S.fh) == (kw + tw - 1, kh + th - 1)
+    want = oracle.median_filter_rect(img, kw, kh)
+    np.testing.assert_array_equal(dg.run_schedule_on_image(S, img), want)
+    if kw * kh <= 45:
+        np.testing.assert_array_equal(dg.run_schedule_on_image(S, img, exact_merge_path=True), want)
+
+
+def test_rect_windows_listed():
+    ws = emit_da.windows()
+    assert (3, 3) in ws and (75, 75) in ws and (31, 1) in ws and (1, 31) in ws
+    assert all(kw % 2 and kh % 2 for kw, kh in ws) and len(ws) == len(set(ws))
 
