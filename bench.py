@@ -51,13 +51,17 @@ def parse():
     return p.parse_args()
 
 
-def algorithmic_ops_per_pixel(dtype_code: int, k: int):
-    """(variant, tile, element-ops per output pixel) for what the library runs.
+def algorithmic_ops_per_pixel(dtype_code: int, k: int, kh: int | None = None):
+    """(variant, tile, element-ops per output pixel) for what the library runs
+    (k x k window, or k columns by kh rows).
 
     Oblivious: live min/max of the generated network per root tile / pixels,
     plus the column sort network (one sort of k-t_h+1 values per image column
     and tile row, i.e. per t_h pixels)."""
     from paper_2507_19926_amd import _lib, dagen, netgen as ng
+    if kh is not None and kh != k:
+        variant, tw, th = _lib.query_rect_config(dtype_code, k, kh)
+        return variant, (tw, th), dagen.schedule(k, tw, th, kh=kh).stats["per_pixel_outputs"]
     variant, tw, th = _lib.query_config(dtype_code, k)
     if variant == _lib.MF_VARIANT_OBLIVIOUS:
         P = ng.build_tile_program(k, tw, th)
@@ -91,11 +95,11 @@ def measured_traffic(k: int, tile):
     return None
 
 
-def roofline(dtype_code: int, k: int, pixels_per_launch: int, launch_s: float):
+def roofline(dtype_code: int, k: int, pixels_per_launch: int, launch_s: float, kh: int | None = None):
     from paper_2507_19926_amd import _lib
     es = {0: 1, 1: 2, 2: 4, 3: 4}[dtype_code]
     bytes_per_launch = 2 * es * pixels_per_launch
-    variant, tile, ops_px = algorithmic_ops_per_pixel(dtype_code, k)
+    variant, tile, ops_px = algorithmic_ops_per_pixel(dtype_code, k, kh)
     if variant == _lib.MF_VARIANT_DATA_AWARE:
         # each merge output is one LDS read and one LDS write of an element
         # (2 bytes for 8/16-bit data, 4 for 32-bit)
@@ -333,6 +337,25 @@ def main():
             per_k[str(k)] = {"mpix_s": round(px_step * args.sweep_steps / w / 1e6, 1),
                              "frame_ms": round(ls * 1e3, 4), "bound": r["bound"],
                              "frac": round(r["frac"], 4), "variant": r["variant"], "tile": r["tile"]}
+    rect = {}
+    if args.sweep_steps > 0 and not args.only_headline:
+        from paper_2507_19926_amd.ops import median_filter_rect
+        for kw, kh in wl.RGB30_RECT:
+            for i in range(2):
+                median_filter_rect(ins[i], kw, kh, out=outs[i])
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for i in range(args.sweep_steps):
+                median_filter_rect(ins[i % nsets], kw, kh, out=outs[i % nsets])
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ls = e0.elapsed_time(e1) / 1e3 / args.sweep_steps
+            r = roofline(_lib.MF_U8, kw, px_step, ls, kh)
+            rect["%dx%d" % (kw, kh)] = {"mpix_s": round(px_step / ls / 1e6, 1), "frame_ms": round(ls * 1e3, 4),
+                                        "bound": r["bound"], "frac": round(r["frac"], 4),
+                                        "variant": r["variant"], "tile": r["tile"],
+                                        "merge_outputs_per_pixel": r.get("merge_outputs_per_pixel")}
     extras = {}
     if not args.no_extras and not args.only_headline:
         extras = run_extras(args, dev, stream)
@@ -373,7 +396,7 @@ def main():
         "dtype": "u8", "data": "synthetic",
         "config": {"workload": "30MP RGB uint8, 3 planar 6720x4480 planes, k=%d, replicate border" % args.k,
                    "k": args.k, "H": H, "W": W, "planes": 3, "frames_rotated": nsets},
-        "roofline": roof, "cpu_baseline": cpu, "per_k": per_k, **extras,
+        "roofline": roof, "cpu_baseline": cpu, "per_k": per_k, "rect_kw_x_kh": rect, **extras,
     }
     print(json.dumps(line))
 

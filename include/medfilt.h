@@ -127,6 +127,14 @@ int32_t median_filter_rect(const void* src, void* dst, int64_t planes,
  * accepts. */
 int32_t mf_max_rect_side(void);
 
+/* The variant and root tile median_filter_rect runs for (dtype, kw, kh):
+ * kw == kh answers as mf_query_config with default options; otherwise
+ * MF_VARIANT_DATA_AWARE and the generated schedule's tile. Errors as
+ * median_filter_rect's window and dtype checks (MF_ERR_NULL for a NULL
+ * output pointer). */
+int32_t mf_query_rect_config(int32_t dtype, int32_t kw, int32_t kh, int32_t* variant,
+                             int32_t* tile_w, int32_t* tile_h);
+
 /* Diagnostic (not part of the filter): enqueue `blocks` work-groups of 256
  * threads, each thread running `iters` iterations of 256 dependent packed
  * 16-bit min/max instructions in 8 independent chains (512 element-ops per

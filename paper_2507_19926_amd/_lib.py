@@ -62,6 +62,9 @@ def lib():
     L.median_filter_rect.restype = i32
     L.mf_max_rect_side.argtypes = []
     L.mf_max_rect_side.restype = i32
+    L.mf_query_rect_config.argtypes = [i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                       ctypes.POINTER(i32)]
+    L.mf_query_rect_config.restype = i32
     L.mf_peak_minmax.argtypes = [vp, i32, i32, vp]
     L.mf_peak_minmax.restype = i32
     L.mf_query_config.argtypes = [i32, i32, ctypes.POINTER(mf_options), ctypes.POINTER(i32),
@@ -132,4 +135,11 @@ def query_config(dtype_code: int, k: int, variant: int = MF_VARIANT_AUTO, tile=N
     o = options(variant, tile)
     check(lib().mf_query_config(dtype_code, k, ctypes.byref(o), ctypes.byref(v), ctypes.byref(tw),
                                 ctypes.byref(th)))
+    return v.value, tw.value, th.value
+
+
+def query_rect_config(dtype_code: int, kw: int, kh: int):
+    """(variant, tile_w, tile_h) median_filter_rect runs for this window."""
+    v, tw, th = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    check(lib().mf_query_rect_config(dtype_code, kw, kh, ctypes.byref(v), ctypes.byref(tw), ctypes.byref(th)))
     return v.value, tw.value, th.value

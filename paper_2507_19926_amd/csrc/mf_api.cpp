@@ -261,6 +261,25 @@ int32_t median_filter_rect(const void* src, void* dst, int64_t planes, int64_t p
 
 int32_t mf_max_rect_side(void) { return mf_da_rect_max_side(); }
 
+int32_t mf_query_rect_config(int32_t dtype, int32_t kw, int32_t kh, int32_t* variant, int32_t* tile_w,
+                             int32_t* tile_h)
+{
+    g_last_error.clear();
+    if (kw == kh) return mf_query_config(dtype, kw, nullptr, variant, tile_w, tile_h);
+    if (!variant || !tile_w || !tile_h) return fail(MF_ERR_NULL, "output pointer is NULL");
+    if (!elem_size(dtype)) return fail(MF_ERR_DTYPE, "unknown dtype %d", dtype);
+    const int side = mf_da_rect_max_side();
+    if (kw < 1 || kh < 1 || kw % 2 == 0 || kh % 2 == 0 || kw > side || kh > side)
+        return fail(MF_ERR_K, "window %dx%d: a rectangular window needs odd sides in [1, %d]", kw, kh, side);
+    int tw = 0, th = 0, g = 0;
+    mf_da_default_tile(dtype, kw, &tw, &th, &g, kh);
+    if (!tw) return fail(MF_ERR_CONFIG, "no data-aware schedule for the %dx%d window", kw, kh);
+    *variant = MF_VARIANT_DATA_AWARE;
+    *tile_w = tw;
+    *tile_h = th;
+    return MF_OK;
+}
+
 int32_t median_filter_planes(const void* src, void* dst, int64_t planes, int64_t plane_stride_bytes, int64_t H,
                              int64_t W, int64_t pitch_bytes, int32_t dtype, int32_t k, int32_t border,
                              const mf_options* opt, void* stream)

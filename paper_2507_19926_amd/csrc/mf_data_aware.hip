@@ -312,9 +312,9 @@ bool mf_da_supports(int dtype, int k, int tw, int th, int group, int kh)
 
 int mf_da_rect_max_side() { return MF_DA_RECT_MAX_SIDE; }
 
-void mf_da_default_tile(int dtype, int k, int* tw, int* th, int* group)
+void mf_da_default_tile(int dtype, int k, int* tw, int* th, int* group, int kh)
 {
-    const DaEntry* e = da_find(dtype, k, 0, 0, 0);
+    const DaEntry* e = da_find(dtype, k, 0, 0, 0, kh);
     *tw = e ? e->tw : 0;
     *th = e ? e->th : 0;
     *group = e ? e->tiles : 0;

@@ -59,7 +59,7 @@ hipError_t mf_da_launch(const void* src, void* dst, int planes, long long plane_
                         int kh = 0);
 bool mf_da_supports(int dtype, int k, int tw, int th, int group, int kh = 0);
 int mf_da_rect_max_side();
-void mf_da_default_tile(int dtype, int k, int* tw, int* th, int* group);
+void mf_da_default_tile(int dtype, int k, int* tw, int* th, int* group, int kh = 0);
 // Data-aware entries for (dtype, k): fills up to cap (tw, th, group) triples,
 // returns the count.
 int mf_da_list(int dtype, int k, int* tw, int* th, int* group, int cap);

@@ -34,12 +34,13 @@ RECT_SHAPES = [(kw, kh) for kw in range(1, RECT_MAX_SIDE + 1, 2)
 def tile_options(kw: int, kh: int) -> list:
     """Root tiles tried for a kw x kh window: power-of-two sides, t_w <= kw,
     t_h <= kh (a non-empty core); square windows use TILE_CANDIDATES,
-    rectangular ones every aspect ratio up to 4:1 either way."""
+    rectangular ones every such pair up to 32 x 32 (a thin window needs a
+    thin tile: t_w = 1 for k_w = 1)."""
     if kw == kh:
         opts = TILE_CANDIDATES
     else:
         p2 = (1, 2, 4, 8, 16, 32)
-        opts = [(tw, th) for tw in p2 for th in p2 if max(tw, th) <= 4 * min(tw, th)]
+        opts = [(tw, th) for tw in p2 for th in p2]
     return [(tw, th) for (tw, th) in opts if tw <= kw and th <= kh]
 
 

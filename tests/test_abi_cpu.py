@@ -123,6 +123,21 @@ def test_rect_entry_validation():
     assert L.mf_last_error().decode() != ""
 
 
+def test_rect_config_query():
+    from paper_2507_19926_amd import emit_da
+    for dtype in range(4):
+        for kw, kh in ((31, 9), (1, 31), (3, 5)):
+            v, tw, th = _lib.query_rect_config(dtype, kw, kh)
+            assert v == _lib.MF_VARIANT_DATA_AWARE and 1 <= tw <= kw and 1 <= th <= kh
+            assert (tw, th) == emit_da.candidates(kw, 4, {}, kh, emit_da.LDS_BUDGETS[:1])[0][:2]
+    assert _lib.query_rect_config(0, 9, 9) == _lib.query_config(0, 9)
+    for kw, kh in ((2, 3), (33, 1)):
+        with pytest.raises(_lib.MfError):
+            _lib.query_rect_config(0, kw, kh)
+    with pytest.raises(_lib.MfError):
+        _lib.query_rect_config(7, 3, 5)
+
+
 def test_peak_diagnostic_validation():
     L = _lib.lib()
     assert L.mf_peak_minmax(None, 1, 1, None) == -2
