@@ -30,9 +30,10 @@
 
 namespace {
 
-// one schedule: window k x kh (columns x rows), LDS element size, root tile
+// one schedule: window k x kh (columns x rows), LDS element size, root tile,
+// tiles per lane, lane groups per work-group
 struct DaEntry {
-    int k, kh, es, tw, th, tiles, c_off, nchunks, r_off, nrounds, o_off, arena;
+    int k, kh, es, tw, th, tiles, groups, c_off, nchunks, r_off, nrounds, o_off, arena;
 };
 
 const DaEntry kDaTable[] = {MF_DA_TABLE_ENTRIES};
@@ -56,10 +57,13 @@ __device__ __forceinline__ uint32_t mf_da_key_to_f32(uint32_t k)
     return k ^ ((uint32_t)((int32_t)~k >> 31) | 0x80000000u);
 }
 
-// T root tiles (bx*T + t, by) of one image, schedule `a`. LDS holds T arenas of
-// `arena` elements each; a lane executes each of its chunks for all T tiles
-// side by side, so the T co-rank searches and loads are independent and their
-// latencies overlap.
+// G*T root tiles (bx*G*T + t, by) of one image, schedule `a`, G = a.groups.
+// The work-group's lanes form G groups of kDaThreads/G lanes; group g owns
+// tiles g*T .. g*T+T-1 and runs every round's chunks for them (small tiles,
+// whose rounds have few chunks, fill the work-group this way). LDS holds G*T
+// arenas of `arena` elements each; a lane executes each of its chunks for its
+// T tiles side by side, so the T co-rank searches and loads are independent
+// and their latencies overlap.
 template <class E, int T>
 __device__ __forceinline__ void
 mf_da_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, int H, int W,
@@ -72,13 +76,15 @@ mf_da_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
     const int rx = (a.k - 1) / 2, ry = (a.kh - 1) / 2;
     const int fw = a.k + tw - 1, fh = a.kh + th - 1;
     const int Y0 = by * th;
+    const int G = a.groups, L = kDaThreads / G, NT = G * T;
+    const int gi = threadIdx.x / L, lt = threadIdx.x - gi * L;
 
     // footprints -> LDS, row-major fw x fh per tile (replicate border)
-    for (int i = threadIdx.x; i < T * fw * fh; i += kDaThreads) {
+    for (int i = threadIdx.x; i < NT * fw * fh; i += kDaThreads) {
         const int t = i / (fw * fh), e = i - t * fw * fh;
         const int y = e / fw, x = e - y * fw;
         const int gy = min(max(Y0 - ry + y, 0), H - 1);
-        const int gx = min(max((bx * T + t) * tw - rx + x, 0), W - 1);
+        const int gx = min(max((bx * NT + t) * tw - rx + x, 0), W - 1);
         const unsigned char* row = src + (long long)gy * pitch;
         uint32_t v;
         if (dtype == MF_U8) v = row[gx];
@@ -94,12 +100,13 @@ mf_da_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
     const uint4* __restrict__ chunks = reinterpret_cast<const uint4*>(blob + a.c_off);
     const uint32_t* __restrict__ rounds = blob + a.r_off;
     constexpr uint32_t kMask = (1u << 18) - 1;
+    E* const gl = lds + gi * T * arena;     // this lane group's T arenas
     for (int rd = 0; rd < a.nrounds; ++rd) {
         const int c1 = (int)rounds[rd + 1];
-        int c = (int)rounds[rd] + threadIdx.x;
+        int c = (int)rounds[rd] + lt;
         uint4 d = c < c1 ? chunks[c] : make_uint4(0, 0, 0, 0);
         while (c < c1) {
-            const int cn = c + kDaThreads;
+            const int cn = c + L;
             const uint4 dn = cn < c1 ? chunks[cn] : make_uint4(0, 0, 0, 0);   // prefetch
             const int ao = (int)(d.x & kMask), bo = (int)(d.y & kMask), oo = (int)(d.z & kMask);
             const int na = (int)(d.x >> 18), nb = (int)(d.y >> 18), n = (int)(d.z >> 18);
@@ -117,8 +124,8 @@ mf_da_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
 #pragma unroll
                 for (int t = 0; t < T; ++t) {
                     if (lo[t] < hi[t]) {
-                        const E* A = lds + t * arena + ao;
-                        const E* B = lds + t * arena + bo;
+                        const E* A = gl + t * arena + ao;
+                        const E* B = gl + t * arena + bo;
                         const int i = (lo[t] + hi[t]) >> 1;
                         if (A[i] <= B[r0 - i - 1]) lo[t] = i + 1;
                         else hi[t] = i;
@@ -141,21 +148,21 @@ mf_da_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
                 for (int t = 0; t < T; ++t) {
                     pa[t] = ao + lo[t];
                     pb[t] = bo + r0 - lo[t];
-                    va[t] = pa[t] < ea ? (uint32_t)lds[t * arena + pa[t]] : kDone;
-                    vb[t] = pb[t] < eb ? (uint32_t)lds[t * arena + pb[t]] : kDone;
+                    va[t] = pa[t] < ea ? (uint32_t)gl[t * arena + pa[t]] : kDone;
+                    vb[t] = pb[t] < eb ? (uint32_t)gl[t * arena + pb[t]] : kDone;
                 }
                 for (int q = 0; q < n; ++q) {
 #pragma unroll
                     for (int t = 0; t < T; ++t) {
                         const bool takeA = va[t] <= vb[t];
-                        lds[t * arena + oo + q] = (E)min(va[t], vb[t]);
+                        gl[t * arena + oo + q] = (E)min(va[t], vb[t]);
                         pa[t] += takeA ? 1 : 0;
                         pb[t] += takeA ? 0 : 1;
                         const int p = takeA ? pa[t] : pb[t];
                         const int e = takeA ? ea : eb;
                         // index clamped into the arena; past the window the
                         // value is replaced by kDone
-                        const uint32_t nv = (uint32_t)lds[t * arena + min(p, arena - 1)];
+                        const uint32_t nv = (uint32_t)gl[t * arena + min(p, arena - 1)];
                         const uint32_t nk = p < e ? nv : kDone;
                         va[t] = takeA ? nk : va[t];
                         vb[t] = takeA ? vb[t] : nk;
@@ -166,8 +173,8 @@ mf_da_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
                 E va[T], vb[T];
 #pragma unroll
                 for (int t = 0; t < T; ++t) {
-                    const E* A = lds + t * arena + ao;
-                    const E* B = lds + t * arena + bo;
+                    const E* A = gl + t * arena + ao;
+                    const E* B = gl + t * arena + bo;
                     ii[t] = lo[t];
                     jj[t] = r0 - lo[t];
                     va[t] = ii[t] < na ? A[ii[t]] : (E)0;
@@ -177,13 +184,13 @@ mf_da_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
 #pragma unroll
                     for (int t = 0; t < T; ++t) {
                         const bool takeA = (ii[t] < na) && (jj[t] >= nb || va[t] <= vb[t]);
-                        lds[t * arena + oo + q] = takeA ? va[t] : vb[t];
+                        gl[t * arena + oo + q] = takeA ? va[t] : vb[t];
                         ii[t] += takeA ? 1 : 0;
                         jj[t] += takeA ? 0 : 1;
                         // one read refills the side just consumed; the index is
                         // clamped into the arena (an exhausted side is never used)
                         const int src_i = takeA ? ao + ii[t] : bo + jj[t];
-                        const E nv = lds[t * arena + min(src_i, arena - 1)];
+                        const E nv = gl[t * arena + min(src_i, arena - 1)];
                         va[t] = takeA ? nv : va[t];
                         vb[t] = takeA ? vb[t] : nv;
                     }
@@ -196,9 +203,9 @@ mf_da_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
     }
 
     const uint32_t* outs = blob + a.o_off;
-    for (int p = threadIdx.x; p < T * tw * th; p += kDaThreads) {
+    for (int p = threadIdx.x; p < NT * tw * th; p += kDaThreads) {
         const int t = p / (tw * th), e = p - t * tw * th;
-        const int y = Y0 + e / tw, x = (bx * T + t) * tw + e % tw;
+        const int y = Y0 + e / tw, x = (bx * NT + t) * tw + e % tw;
         if (y >= H || x >= W) continue;
         unsigned char* row = dst + (long long)y * pitch;
         const uint32_t v = (uint32_t)lds[t * arena + outs[e]];
@@ -350,6 +357,7 @@ static MfDaArgs da_args(const DaEntry* e, const uint32_t* blob)
     a.nrounds = e->nrounds;
     a.o_off = e->o_off;
     a.arena = e->arena;
+    a.groups = e->groups;
     return a;
 }
 
@@ -362,9 +370,10 @@ hipError_t mf_da_launch(const void* src, void* dst, int planes, long long plane_
     hipError_t err = da_blob(&blob);
     if (err != hipSuccess) return err;
     MfDaArgs a = da_args(e, blob);
-    const int ntx = (W + e->tw * e->tiles - 1) / (e->tw * e->tiles), nty = (H + e->th - 1) / e->th;
+    const int bw = e->tw * e->tiles * e->groups;     // pixels of a work-group along x
+    const int ntx = (W + bw - 1) / bw, nty = (H + e->th - 1) / e->th;
     if ((long long)ntx * nty > 0x7fffffffLL) return hipErrorInvalidConfiguration;   // grid.x limit
-    const size_t lds = (size_t)e->arena * e->es * e->tiles;
+    const size_t lds = (size_t)e->arena * e->es * e->tiles * e->groups;
     for (int p0 = 0; p0 < planes; p0 += 65535) {     // grid rows are planes
         const int np = planes - p0 < 65535 ? planes - p0 : 65535;
         const unsigned char* s8 = (const unsigned char*)src + p0 * plane_stride;
@@ -386,8 +395,8 @@ hipError_t mf_da_batched(int dtype, int k, int tw, int th, int group, MfBatchedK
     *args = da_args(e, blob);
     kern->fn = da_kernel_for(e, true);
     kern->threads = kDaThreads;
-    kern->lds = (size_t)e->arena * e->es * e->tiles;
-    kern->bw = e->tw * e->tiles;
+    kern->lds = (size_t)e->arena * e->es * e->tiles * e->groups;
+    kern->bw = e->tw * e->tiles * e->groups;
     kern->bh = e->th;
     return hipSuccess;
 }

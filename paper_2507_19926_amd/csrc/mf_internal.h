@@ -68,6 +68,7 @@ int mf_da_list(int dtype, int k, int* tw, int* th, int* group, int cap);
 struct MfDaArgs {
     const uint32_t* blob;
     int k, kh, tw, th, c_off, r_off, nrounds, o_off, arena;   // window k columns x kh rows
+    int groups;   // lane groups per work-group, each with its own root tiles
 };
 hipError_t mf_da_batched(int dtype, int k, int tw, int th, int group, MfBatchedKernel* kern, MfDaArgs* args);
 

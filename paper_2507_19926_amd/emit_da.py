@@ -92,6 +92,24 @@ def candidates(k: int, elem_bytes: int, cache: dict, kh: int | None = None,
     return out
 
 
+MAX_GROUPS = 32      # lane groups per work-group: at least 16 lanes each
+
+
+def lane_groups(S: dagen.Schedule, elem_bytes: int = 4) -> int:
+    """Lane groups G for a small root tile: enough groups that a group's
+    kDaThreads/G lanes match the schedule's mean chunks per round (lanes
+    beyond that would idle), a power of two <= MAX_GROUPS, and G arenas
+    within half the LDS (two work-groups per CU)."""
+    rounds = max(1, len(S.rounds) - 1)
+    mean = max(1.0, len(S.chunks) / rounds)
+    g = 1
+    while g < MAX_GROUPS and dagen.LANES / (2 * g) >= mean:
+        g *= 2
+    while g > 1 and g * S.arena * elem_bytes > LDS_BYTES // 2:
+        g //= 2
+    return g
+
+
 def choose_tile(k: int, elem_bytes: int, cache: dict, kh: int | None = None):
     kh = k if kh is None else kh
     tw, th, _ = candidates(k, elem_bytes, cache, kh)[0]
@@ -125,13 +143,18 @@ def generate(out_dir: str, workers: int | None = None) -> dict:
             # 32-bit elements share a CU, the budget most square windows up
             # to k = 31 are tuned to
             if kw == kh:
-                opts = candidates(kw, es, cache)
+                opts = [c + (1,) for c in candidates(kw, es, cache)]
             else:
-                opts = candidates(kw, 4, cache, kh, LDS_BUDGETS[:1])
-            for (tw, th, T) in opts:
-                key = (kw, kh, tw, th)
+                # small tiles run several to a work-group in lane groups;
+                # their schedule is cut for the group's lanes
+                tw, th, T = candidates(kw, 4, cache, kh, LDS_BUDGETS[:1])[0]
+                opts = [(tw, th, T, lane_groups(cache[(kw, kh, tw, th)]))]
+            for (tw, th, T, G) in opts:
+                key = (kw, kh, tw, th, G)
                 if key not in placed:
-                    S = cache[key]
+                    S = cache[key[:4]] if G == 1 else dagen.schedule(kw, tw, th, kh=kh,
+                                                                     lanes=dagen.LANES // G)
+                    assert S.arena * (es if kw == kh else 4) * T * G <= LDS_BYTES
                     ch = S.chunks.reshape(-1).astype(np.uint32)
                     rd = S.rounds.astype(np.uint32)
                     ou = S.outputs.astype(np.uint32)
@@ -148,7 +171,7 @@ def generate(out_dir: str, workers: int | None = None) -> dict:
                     words.append(ou); pos += len(ou)
                     placed[key] = (c_off, len(S.chunks), r_off, len(S.rounds) - 1, o_off, S.arena)
                 c_off, nch, r_off, nr, o_off, arena = placed[key]
-                entries.append((kw, kh, es, tw, th, T, c_off, nch, r_off, nr, o_off, arena))
+                entries.append((kw, kh, es, tw, th, T, G, c_off, nch, r_off, nr, o_off, arena))
     blob = np.concatenate(words).astype("<u4")
     bpath = os.path.join(out_dir, "mf_da_blob.bin")
     data = blob.tobytes()
@@ -156,14 +179,14 @@ def generate(out_dir: str, workers: int | None = None) -> dict:
         with open(bpath, "wb") as f:
             f.write(data)
     lines = ["// Generated by emit_da.py: data-aware schedules, one entry per",
-             "// (k_w, k_h, LDS element size, root tile).",
+             "// (k_w, k_h, LDS element size, root tile, tiles per lane, lane groups).",
              "#pragma once",
              "#define MF_DA_BLOB_WORDS %d" % len(blob),
              "#define MF_DA_CHUNK %d" % dagen.CHUNK,
              "#define MF_DA_RECT_MAX_SIDE %d" % RECT_MAX_SIDE,
              "#define MF_DA_TABLE_ENTRIES \\"]
     for e in entries:
-        lines.append("    {%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d}, \\" % e)
+        lines.append("    {%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d}, \\" % e)
     lines.append("")
     text = "\n".join(lines) + "\n"
     hpath = os.path.join(out_dir, "mf_da_table.h")

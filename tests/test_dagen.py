@@ -73,6 +73,23 @@ def test_rect_schedule_matches_oracle(kw, kh, tw, th):
         np.testing.assert_array_equal(dg.run_schedule_on_image(S, img, exact_merge_path=True), want)
 
 
+@pytest.mark.parametrize("kw,kh", [(31, 1), (1, 31), (15, 5), (5, 15), (9, 31), (31, 29)])
+def test_rect_lane_groups(kw, kh):
+    """Small rectangular tiles run G to a work-group: G is a power of two
+    that divides the lanes, G arenas of 32-bit elements fit half the LDS, and
+    the schedule cut for G lane groups still computes the oracle's median."""
+    cache = {}
+    tw, th, _ = emit_da.candidates(kw, 4, cache, kh, emit_da.LDS_BUDGETS[:1])[0]
+    G = emit_da.lane_groups(cache[(kw, kh, tw, th)])
+    assert 1 <= G <= emit_da.MAX_GROUPS and dg.LANES % G == 0 and G & (G - 1) == 0
+    S = dg.schedule(kw, tw, th, kh=kh, lanes=dg.LANES // G)
+    assert G * S.arena * 4 <= emit_da.LDS_BYTES // 2
+    if tw * th <= 16:
+        assert G >= 8            # tiny tiles must not leave the work-group idle
+    img = wl.uniform_plane(19, 37, np.uint16, seed=kw + kh)
+    np.testing.assert_array_equal(dg.run_schedule_on_image(S, img), oracle.median_filter_rect(img, kw, kh))
+
+
 def test_rect_windows_listed():
     ws = emit_da.windows()
     assert (3, 3) in ws and (75, 75) in ws and (31, 1) in ws and (1, 31) in ws

@@ -61,6 +61,16 @@ def test_every_rect_window(kw):
         assert _eq(_rect(img, kw, kh), oracle.median_filter_rect(img, kw, kh)), (kw, kh, dtype)
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("kw,kh", [(31, 1), (1, 31), (15, 5), (5, 15), (3, 1), (9, 31)])
+def test_rect_lane_groups_across_workgroups(kw, kh, dtype):
+    """Small tiles run many to a work-group (lane groups): images several
+    work-groups wide and tall, with a partial last work-group and tile."""
+    H, W = 75 + kh, 1500 + 3 * kw
+    img = _img(dtype, H, W, seed=kw * 7 + kh)
+    assert _eq(_rect(img, kw, kh), oracle.median_filter_rect(img, kw, kh)), (kw, kh)
+
+
 @pytest.mark.parametrize("dtype", [np.uint8, np.float32])
 @pytest.mark.parametrize("shape", [(1, 1), (1, 300), (300, 1), (2, 3), (5, 700), (129, 65)])
 def test_rect_small_and_degenerate_images(dtype, shape):
