@@ -40,6 +40,9 @@ def parse():
     p.add_argument("--steps", type=int, default=50)
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--k", type=int, default=17, help="headline kernel diameter")
+    p.add_argument("--window", default=None,
+                   help="KWxKH: time this rectangular window (kw columns, kh rows) in place of k "
+                        "(for profiling one data-aware schedule)")
     p.add_argument("--sweep-steps", type=int, default=5, help="timed steps per k of the sweep (0 = no sweep)")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle work for the CPU baseline")
@@ -268,9 +271,12 @@ def main():
     import torch
 
     from paper_2507_19926_amd import _lib, workloads as wl
-    from paper_2507_19926_amd.ops import median_filter
+    from paper_2507_19926_amd.ops import median_filter, median_filter_rect
 
     _lib.lib()  # fail loudly if the HIP library is missing
+    kw = kh = args.k
+    if args.window:
+        kw, kh = (int(v) for v in args.window.lower().split("x"))
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
 
@@ -295,10 +301,15 @@ def main():
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream(dev)
 
-    def run(k, steps, warmup):
-        for i in range(warmup):
-            s = i % nsets
+    def filt(s, k, rows=None):
+        if rows is None or rows == k:
             median_filter(ins[s], k, out=outs[s])
+        else:
+            median_filter_rect(ins[s], k, rows, out=outs[s])
+
+    def run(k, steps, warmup, rows=None):
+        for i in range(warmup):
+            filt(i % nsets, k, rows)
         torch.cuda.synchronize()
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(steps)]
@@ -308,7 +319,7 @@ def main():
             s = i % nsets
             e0, e1 = evs[i]
             e0.record(stream)
-            median_filter(ins[s], k, out=outs[s])     # the 3 planes in one launch
+            filt(s, k, rows)     # the 3 planes in one launch
             e1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -317,13 +328,15 @@ def main():
 
     px_step = 3 * H * W
     # headline
-    wall, launch_s = run(args.k, args.steps, args.warmup)
+    wall, launch_s = run(kw, args.steps, args.warmup, kh)
     value = px_step * args.steps / wall / 1e6
-    roof = roofline(_lib.MF_U8, args.k, px_step, launch_s)
-    roof["traffic"] = measured_traffic(args.k, roof["tile"]) if roof["variant"] == _lib.MF_VARIANT_OBLIVIOUS else None
+    roof = roofline(_lib.MF_U8, kw, px_step, launch_s, kh)
+    square = kw == kh
+    roof["traffic"] = (measured_traffic(kw, roof["tile"])
+                       if square and roof["variant"] == _lib.MF_VARIANT_OBLIVIOUS else None)
     roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     roof["algorithmic_bytes_per_launch"] = 2 * px_step
-    roof["launch"] = "one launch per step: the frame's 3 planes (median_filter_planes)"
+    roof["launch"] = "one launch per step: the frame's 3 planes (%s)" % ("median_filter_planes" if square else "median_filter_rect")
     per_k = {}
     if args.sweep_steps > 0 and not args.only_headline:
         for k in wl.RGB30_KS:
@@ -368,9 +381,9 @@ def main():
         import oracle  # CPU baseline only
         nthreads = len(os.sched_getaffinity(0))
         probe = 64
-        oracle.median_filter(base[0], args.k, rows=(0, 16), nthreads=nthreads)   # warm-up (threads, caches)
+        oracle.median_filter_rect(base[0], kw, kh, rows=(0, 16), nthreads=nthreads)   # warm-up (threads, caches)
         t = time.perf_counter()
-        oracle.median_filter(base[0], args.k, rows=(0, probe), nthreads=nthreads)
+        oracle.median_filter_rect(base[0], kw, kh, rows=(0, probe), nthreads=nthreads)
         dt = time.perf_counter() - t
         # rows of the frame (plane after plane, whole frames repeated if one
         # frame is shorter than that) that take about cpu_seconds
@@ -380,22 +393,25 @@ def main():
         while done < rows:
             c = (done // H) % 3
             n = min(H - done % H, rows - done)
-            oracle.median_filter(base[c], args.k, rows=(done % H, done % H + n), nthreads=nthreads)
+            oracle.median_filter_rect(base[c], kw, kh, rows=(done % H, done % H + n), nthreads=nthreads)
             done += n
         dt = time.perf_counter() - t
         cpu = {"value": round(done * W / dt / 1e6, 3), "unit": "Mpixel/s", "cores": nthreads,
                "kind": "oracle",
                "sample": "%d rows of 6720 px (%.2f passes over the 3-plane frame, %d px) at k=%d, %.1f s"
                          % (done, done / (3 * H), done * W, args.k, dt)}
+        if not square:
+            cpu["sample"] = cpu["sample"].replace("k=%d" % args.k, "window %dx%d" % (kw, kh))
 
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mpixel/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 4),
         "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": round(value / PAPER_L40S_MSAMPLE_S_K17, 3) if args.k == 17 else None,
+        "vs_baseline": round(value / PAPER_L40S_MSAMPLE_S_K17, 3) if square and kw == 17 else None,
         "dtype": "u8", "data": "synthetic",
-        "config": {"workload": "30MP RGB uint8, 3 planar 6720x4480 planes, k=%d, replicate border" % args.k,
-                   "k": args.k, "H": H, "W": W, "planes": 3, "frames_rotated": nsets},
+        "config": {"workload": "30MP RGB uint8, 3 planar 6720x4480 planes, %s, replicate border"
+                               % ("k=%d" % kw if square else "window %dx%d (kw x kh)" % (kw, kh)),
+                   "k": kw, "kh": kh, "H": H, "W": W, "planes": 3, "frames_rotated": nsets},
         "roofline": roof, "cpu_baseline": cpu, "per_k": per_k, "rect_kw_x_kh": rect, **extras,
     }
     print(json.dumps(line))
