@@ -64,15 +64,16 @@ def algorithmic_ops_per_pixel(dtype_code: int, k: int, kh: int | None = None):
     from paper_2507_19926_amd import _lib, dagen, netgen as ng
     if kh is not None and kh != k:
         variant, tw, th = _lib.query_rect_config(dtype_code, k, kh)
-        return variant, (tw, th), dagen.schedule(k, tw, th, kh=kh).stats["per_pixel_outputs"]
-    variant, tw, th = _lib.query_config(dtype_code, k)
+    else:
+        kh = k
+        variant, tw, th = _lib.query_config(dtype_code, k)
     if variant == _lib.MF_VARIANT_OBLIVIOUS:
-        P = ng.build_tile_program(k, tw, th)
+        P = ng.build_tile_program(k, tw, th, kh=kh)
         net = ng.op_counts(P)["minmax"] / (tw * th)
-        srt = ng.op_counts(ng.build_sort_program(k - th + 1))["minmax"] / th
+        srt = ng.op_counts(ng.build_sort_program(kh - th + 1))["minmax"] / th
         return variant, (tw, th), net + srt
     # data-aware: merge outputs per pixel of the schedule
-    return variant, (tw, th), dagen.schedule(k, tw, th).stats["per_pixel_outputs"]
+    return variant, (tw, th), dagen.schedule(k, tw, th, kh=kh).stats["per_pixel_outputs"]
 
 
 def measured_traffic(k: int, tile):
@@ -368,7 +369,7 @@ def main():
             rect["%dx%d" % (kw, kh)] = {"mpix_s": round(px_step / ls / 1e6, 1), "frame_ms": round(ls * 1e3, 4),
                                         "bound": r["bound"], "frac": round(r["frac"], 4),
                                         "variant": r["variant"], "tile": r["tile"],
-                                        "merge_outputs_per_pixel": r.get("merge_outputs_per_pixel")}
+                                        "ops_per_pixel": r.get("merge_outputs_per_pixel", r.get("ops_per_pixel"))}
     extras = {}
     if not args.no_extras and not args.only_headline:
         extras = run_extras(args, dev, stream)

@@ -115,13 +115,19 @@ int32_t median_filter_planes(const void* src, void* dst, int64_t planes,
  * (kw-t_w+1) x (kh-t_h+1)) and the recursion of Section 3 carry over with
  * separate horizontal and vertical radii. Arguments, planes and errors as in
  * median_filter_planes. kw == kh is the square filter (median_filter_planes
- * with default options, any k up to mf_max_k()). A rectangular window runs
- * the data-aware variant (Section 5) with one generated schedule per shape;
- * both sides must lie in [1, mf_max_rect_side()] (MF_ERR_K otherwise). */
+ * with opt's variant and default tiles, any k up to mf_max_k()). A
+ * rectangular window runs an oblivious network (Section 4) where one is
+ * compiled for (kw, kh) and the data-aware variant (Section 5, one generated
+ * schedule per shape) otherwise; both sides must lie in
+ * [1, mf_max_rect_side()] (MF_ERR_K otherwise). opt may be NULL; for a
+ * rectangular window only opt->variant is honoured (MF_VARIANT_AUTO,
+ * MF_VARIANT_OBLIVIOUS: MF_ERR_CONFIG when no network is compiled for the
+ * shape, MF_VARIANT_DATA_AWARE); any non-zero tile, group, form or rows is
+ * MF_ERR_CONFIG. Results are identical for every variant. */
 int32_t median_filter_rect(const void* src, void* dst, int64_t planes,
                            int64_t plane_stride_bytes, int64_t H, int64_t W,
                            int64_t pitch_bytes, int32_t dtype, int32_t kw, int32_t kh,
-                           int32_t border, void* stream);
+                           int32_t border, const mf_options* opt, void* stream);
 
 /* Largest side of a rectangular (kw != kh) window median_filter_rect
  * accepts. */
@@ -129,7 +135,9 @@ int32_t mf_max_rect_side(void);
 
 /* The variant and root tile median_filter_rect runs for (dtype, kw, kh):
  * kw == kh answers as mf_query_config with default options; otherwise
- * MF_VARIANT_DATA_AWARE and the generated schedule's tile. Errors as
+ * MF_VARIANT_OBLIVIOUS and the network's root tile when one is compiled for
+ * the shape, else MF_VARIANT_DATA_AWARE and the generated schedule's tile
+ * (the MF_VARIANT_AUTO choice). Errors as
  * median_filter_rect's window and dtype checks (MF_ERR_NULL for a NULL
  * output pointer). */
 int32_t mf_query_rect_config(int32_t dtype, int32_t kw, int32_t kh, int32_t* variant,

@@ -58,7 +58,8 @@ def lib():
     L.median_filter_ex.restype = i32
     L.median_filter_planes.argtypes = [vp, vp, i64, i64, i64, i64, i64, i32, i32, i32, ctypes.POINTER(mf_options), vp]
     L.median_filter_planes.restype = i32
-    L.median_filter_rect.argtypes = [vp, vp, i64, i64, i64, i64, i64, i32, i32, i32, i32, vp]
+    L.median_filter_rect.argtypes = [vp, vp, i64, i64, i64, i64, i64, i32, i32, i32, i32,
+                                     ctypes.POINTER(mf_options), vp]
     L.median_filter_rect.restype = i32
     L.mf_max_rect_side.argtypes = []
     L.mf_max_rect_side.restype = i32

@@ -45,6 +45,16 @@ OBL_CONFIGS = [
     (21, 4, 4, 1, 4),
 ]
 
+# Oblivious networks for rectangular windows: (k_w, k_h, t_w, t_h, tile rows
+# per wave, waves per work-group); other k_w x k_h windows run data-aware.
+RECT_OBL_CONFIGS = [
+    (3, 1, 2, 1, 8, 4), (1, 3, 1, 2, 4, 4),
+    (5, 3, 4, 2, 2, 4), (3, 5, 2, 4, 1, 4), (7, 3, 4, 2, 2, 4), (3, 7, 2, 4, 1, 4),
+    (9, 3, 4, 2, 2, 4), (3, 9, 2, 4, 1, 4),
+    (7, 5, 4, 4, 1, 4), (5, 7, 4, 4, 1, 4), (9, 5, 4, 4, 1, 4), (5, 9, 4, 4, 1, 4),
+    (9, 7, 4, 4, 1, 4), (7, 9, 4, 4, 1, 4), (15, 5, 4, 4, 1, 4), (5, 15, 4, 4, 1, 4),
+]
+
 HIP_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=%s" % ARCH, "-fPIC",
     # no packed-fp32 instructions anywhere in the library
@@ -107,7 +117,7 @@ def build(jobs: int | None = None, verbose: bool = False, incremental: bool = Fa
     incremental=True, objects whose sources and headers are unchanged since
     they were compiled are reused."""
     os.makedirs(GEN, exist_ok=True)
-    obl_srcs = emit_hip.generate(GEN, OBL_CONFIGS)
+    obl_srcs = emit_hip.generate(GEN, OBL_CONFIGS, RECT_OBL_CONFIGS)
     _write_auto_table()
     emit_da.generate(GEN)
     blob_cpp = os.path.join(GEN, "mf_da_blob.cpp")

@@ -14,6 +14,9 @@
 #define MF_OBL_ENTRY(NET, K, TW, TH, RY, NW, INL) MF_OBL_DECLARE(NET, RY, NW)
 #include "mf_obl_table.inc"
 #undef MF_OBL_ENTRY
+#define MF_OBL_RECT_ENTRY(NET, KW, KH, TW, TH, RY, NW, INL) MF_OBL_DECLARE(NET, RY, NW)
+#include "mf_obl_rect_table.inc"
+#undef MF_OBL_RECT_ENTRY
 
 namespace {
 
@@ -36,6 +39,27 @@ const OblEntry kOblTable[] = {
     {3, 1, 1, 16, 4, 3, mf_strip3_launch_p16, mf_strip3_launch_u32, nullptr, nullptr},
 };
 constexpr int kOblCount = sizeof(kOblTable) / sizeof(kOblTable[0]);
+
+// Oblivious networks for rectangular windows (k_w columns by k_h rows).
+struct OblRectEntry {
+    int kw, kh, tw, th;
+    mf_launch_fn p16, u32;
+};
+
+const OblRectEntry kOblRectTable[] = {
+#define MF_OBL_RECT_ENTRY(NET, KW, KH, TW, TH, RY, NW, INL) \
+    {KW, KH, TW, TH, MF_OBL_NAME(NET, RY, NW, p16), MF_OBL_NAME(NET, RY, NW, u32)},
+#include "mf_obl_rect_table.inc"
+#undef MF_OBL_RECT_ENTRY
+    {0, 0, 0, 0, nullptr, nullptr},   // keeps the array non-empty
+};
+
+const OblRectEntry* find_obl_rect(int kw, int kh)
+{
+    for (const OblRectEntry& e : kOblRectTable)
+        if (e.p16 && e.kw == kw && e.kh == kh) return &e;
+    return nullptr;
+}
 
 constexpr int kMaxK = 75;
 
@@ -238,12 +262,20 @@ extern "C" {
 
 int32_t median_filter_rect(const void* src, void* dst, int64_t planes, int64_t plane_stride_bytes, int64_t H,
                            int64_t W, int64_t pitch_bytes, int32_t dtype, int32_t kw, int32_t kh, int32_t border,
-                           void* stream)
+                           const mf_options* opt, void* stream)
 {
     g_last_error.clear();
-    if (kw == kh)
-        return median_filter_planes(src, dst, planes, plane_stride_bytes, H, W, pitch_bytes, dtype, kw, border,
-                                    nullptr, stream);
+    const int32_t variant = opt ? opt->variant : MF_VARIANT_AUTO;
+    if (kw == kh) {
+        mf_options o = {};
+        o.variant = variant;
+        return median_filter_planes(src, dst, planes, plane_stride_bytes, H, W, pitch_bytes, dtype, kw, border, &o,
+                                    stream);
+    }
+    if (opt && (opt->tile_w || opt->tile_h || opt->group || opt->form || opt->rows))
+        return fail(MF_ERR_CONFIG, "a rectangular window takes only the variant option");
+    if (variant != MF_VARIANT_AUTO && variant != MF_VARIANT_OBLIVIOUS && variant != MF_VARIANT_DATA_AWARE)
+        return fail(MF_ERR_CONFIG, "unknown variant %d", variant);
     // k = 1 stands for the window in the shared checks (it passes the k test)
     int32_t rc = validate(src, dst, H, W, pitch_bytes, dtype, 1, border);
     if (rc) return rc;
@@ -252,6 +284,15 @@ int32_t median_filter_rect(const void* src, void* dst, int64_t planes, int64_t p
         return fail(MF_ERR_K, "window %dx%d: a rectangular window needs odd sides in [1, %d]", kw, kh, side);
     rc = check_planes(src, dst, planes, &plane_stride_bytes, H, W, pitch_bytes, dtype);
     if (rc) return rc;
+    const OblRectEntry* oe = variant == MF_VARIANT_DATA_AWARE ? nullptr : find_obl_rect(kw, kh);
+    if (oe) {
+        mf_launch_fn fn = (dtype == MF_U8 || dtype == MF_U16) ? oe->p16 : oe->u32;
+        return hip_status(fn(src, dst, (int)planes, plane_stride_bytes, (int)H, (int)W, pitch_bytes, dtype,
+                             (hipStream_t)stream),
+                          "oblivious kernel launch");
+    }
+    if (variant == MF_VARIANT_OBLIVIOUS)
+        return fail(MF_ERR_CONFIG, "no oblivious network compiled for the %dx%d window", kw, kh);
     if (!mf_da_supports(dtype, kw, 0, 0, 0, kh))
         return fail(MF_ERR_CONFIG, "no data-aware schedule for the %dx%d window", kw, kh);
     return hip_status(mf_da_launch(src, dst, (int)planes, plane_stride_bytes, (int)H, (int)W, pitch_bytes, dtype, kw,
@@ -271,6 +312,12 @@ int32_t mf_query_rect_config(int32_t dtype, int32_t kw, int32_t kh, int32_t* var
     const int side = mf_da_rect_max_side();
     if (kw < 1 || kh < 1 || kw % 2 == 0 || kh % 2 == 0 || kw > side || kh > side)
         return fail(MF_ERR_K, "window %dx%d: a rectangular window needs odd sides in [1, %d]", kw, kh, side);
+    if (const OblRectEntry* oe = find_obl_rect(kw, kh)) {
+        *variant = MF_VARIANT_OBLIVIOUS;
+        *tile_w = oe->tw;
+        *tile_h = oe->th;
+        return MF_OK;
+    }
     int tw = 0, th = 0, g = 0;
     mf_da_default_tile(dtype, kw, &tw, &th, &g, kh);
     if (!tw) return fail(MF_ERR_CONFIG, "no data-aware schedule for the %dx%d window", kw, kh);

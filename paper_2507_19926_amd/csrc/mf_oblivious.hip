@@ -66,16 +66,18 @@ __device__ __forceinline__ int mf_tid()
     return t;
 }
 
-// Geometry of a block: the union of its tiles' footprints.
-template <class V, int K, int TW, int TH, int RY, int NW>
+// Geometry of a block: the union of its tiles' footprints. The window is K
+// columns by KH rows (KH = K for the square filter).
+template <class V, int K, int KH, int TW, int TH, int RY, int NW>
 struct MfObGeom {
     static constexpr bool PACK = MfVTraits<V>::PACK;
-    static constexpr int R = (K - 1) / 2;
+    static constexpr int RX = (K - 1) / 2;         // horizontal radius
+    static constexpr int RV = (KH - 1) / 2;        // vertical radius
     static constexpr int NT = 64 * NW;             // threads of a work-group
     static constexpr int TY = NW * RY;
     static constexpr int BWH = 64 * TW;            // block width of one packed half
     static constexpr int COLS = BWH + K - 1;       // footprint-union columns
-    static constexpr int ROWS = TY * TH + K - 1;   // footprint-union rows
+    static constexpr int ROWS = TY * TH + KH - 1;  // footprint-union rows
     static constexpr int Q = (COLS + TW - 1) / TW;
     // a segment of seg_bytes starting `lead` (< 4) bytes into an aligned
     // dword needs ceil((lead + seg_bytes) / 4) <= (seg_bytes + 6) / 4 dwords;
@@ -95,9 +97,9 @@ struct MfObGeom {
 
 // Global loads of one block's footprint union (plain and batched forms),
 // issued all at once into registers, then scattered into LDS.
-template <class V, int K, int TW, int TH, int RY, int NW>
+template <class V, int K, int KH, int TW, int TH, int RY, int NW>
 struct MfObPrefetch {
-    using G = MfObGeom<V, K, TW, TH, RY, NW>;
+    using G = MfObGeom<V, K, KH, TW, TH, RY, NW>;
     uint32_t va[G::U], vb[G::PACK ? G::U : 1];
     bool fast;
 };
@@ -105,14 +107,14 @@ struct MfObPrefetch {
 // Blocks whose columns stay inside the image with an 8-element margin take
 // the fast path: aligned dword loads of whole row segments. Blocks touching
 // the left or right edge clamp element by element at commit time.
-template <class V, int K, int TW, int TH, int RY, int NW>
+template <class V, int K, int KH, int TW, int TH, int RY, int NW>
 __device__ __forceinline__ void
 mf_obl_issue(const unsigned char* __restrict__ src, int H, int W, long long pitch, int dtype, int X0, int Y0,
-             MfObPrefetch<V, K, TW, TH, RY, NW>& pf)
+             MfObPrefetch<V, K, KH, TW, TH, RY, NW>& pf)
 {
-    using G = MfObGeom<V, K, TW, TH, RY, NW>;
+    using G = MfObGeom<V, K, KH, TW, TH, RY, NW>;
     const int es = G::PACK ? (dtype == MF_U8 ? 1 : 2) : 4;
-    const int gx0 = X0 - G::R;
+    const int gx0 = X0 - G::RX;
     const int span = G::PACK ? (G::BWH + G::COLS) : G::COLS;
     pf.fast = gx0 >= 4 && gx0 + span + 8 <= W;
     if (!pf.fast) return;
@@ -125,7 +127,7 @@ mf_obl_issue(const unsigned char* __restrict__ src, int H, int W, long long pitc
         if constexpr (G::PACK) pf.vb[u] = 0;
         if (it < G::ROWS * nd) {
             const int rho = it / nd, d = it - rho * nd;
-            const int gy = mf_clampi(Y0 - G::R + rho, 0, H - 1);
+            const int gy = mf_clampi(Y0 - G::RV + rho, 0, H - 1);
             const uintptr_t a = (uintptr_t)(src + (long long)gy * pitch + (long long)gx0 * es);
             const uint32_t* p = (const uint32_t*)((a & ~(uintptr_t)3) + 4 * (uintptr_t)d);
             pf.va[u] = p[0];
@@ -137,11 +139,11 @@ mf_obl_issue(const unsigned char* __restrict__ src, int H, int W, long long pitc
 // Scatter the elements of one source dword into the raw buffer's row. b0 is
 // the footprint column of the dword's byte 0 (may be negative); vb is the
 // dword at the same position of the right half (packed types only).
-template <class V, int K, int TW, int TH, int RY, int NW>
+template <class V, int K, int KH, int TW, int TH, int RY, int NW>
 __device__ __forceinline__ void mf_obl_put_dword(V* __restrict__ rrow, int b0, uint32_t va, uint32_t vb, int es,
                                                  int dtype)
 {
-    using G = MfObGeom<V, K, TW, TH, RY, NW>;
+    using G = MfObGeom<V, K, KH, TW, TH, RY, NW>;
     constexpr int Q = G::Q, COLS = G::COLS;
     if constexpr (G::PACK) {
         if (es == 1) {
@@ -179,12 +181,12 @@ __device__ __forceinline__ void mf_obl_put_dword(V* __restrict__ rrow, int b0, u
 
 // Footprint union with clamped coordinates, element by element (blocks at
 // the left or right image edge).
-template <class V, int K, int TW, int TH, int RY, int NW>
+template <class V, int K, int KH, int TW, int TH, int RY, int NW>
 __device__ __forceinline__ void
 mf_obl_load_clamped(const unsigned char* __restrict__ src, int H, int W, long long pitch, int dtype, int X0, int Y0,
                     V* __restrict__ raw)
 {
-    using G = MfObGeom<V, K, TW, TH, RY, NW>;
+    using G = MfObGeom<V, K, KH, TW, TH, RY, NW>;
     constexpr int Q = G::Q, COLS = G::COLS;
     constexpr int UC = (G::ROWS * COLS + G::NT - 1) / G::NT;
     const int tid = mf_tid();
@@ -194,12 +196,12 @@ mf_obl_load_clamped(const unsigned char* __restrict__ src, int H, int W, long lo
         const int w = tid + u * G::NT;
         if (w >= G::ROWS * COLS) break;
         const int rho = w / COLS, c = w - rho * COLS;
-        const int gy = mf_clampi(Y0 - G::R + rho, 0, H - 1);
+        const int gy = mf_clampi(Y0 - G::RV + rho, 0, H - 1);
         const unsigned char* row = src + (long long)gy * pitch;
-        const int gxa = mf_clampi(X0 - G::R + c, 0, W - 1);
+        const int gxa = mf_clampi(X0 - G::RX + c, 0, W - 1);
         V v;
         if constexpr (G::PACK) {
-            const int gxb = mf_clampi(X0 + G::BWH - G::R + c, 0, W - 1);
+            const int gxb = mf_clampi(X0 + G::BWH - G::RX + c, 0, W - 1);
             if (dtype == MF_U8) {
                 v.x = row[gxa];
                 v.y = row[gxb];
@@ -218,15 +220,15 @@ mf_obl_load_clamped(const unsigned char* __restrict__ src, int H, int W, long lo
 
 // Footprint union -> LDS raw buffer (swizzled layout), from the prefetched
 // registers or, for edge blocks, by clamped element loads.
-template <class V, int K, int TW, int TH, int RY, int NW>
+template <class V, int K, int KH, int TW, int TH, int RY, int NW>
 __device__ __forceinline__ void
 mf_obl_commit(const unsigned char* __restrict__ src, int H, int W, long long pitch, int dtype, int X0, int Y0,
-              const MfObPrefetch<V, K, TW, TH, RY, NW>& pf, V* __restrict__ raw)
+              const MfObPrefetch<V, K, KH, TW, TH, RY, NW>& pf, V* __restrict__ raw)
 {
-    using G = MfObGeom<V, K, TW, TH, RY, NW>;
+    using G = MfObGeom<V, K, KH, TW, TH, RY, NW>;
     constexpr int Q = G::Q, COLS = G::COLS;
     const int es = G::PACK ? (dtype == MF_U8 ? 1 : 2) : 4;
-    const int gx0 = X0 - G::R;
+    const int gx0 = X0 - G::RX;
     if (pf.fast) {
         const int nd = (COLS * es + 6) / 4;
         const int tid = mf_tid();
@@ -235,16 +237,16 @@ mf_obl_commit(const unsigned char* __restrict__ src, int H, int W, long long pit
             const int it = tid + u * G::NT;
             if (it < G::ROWS * nd) {
                 const int rho = it / nd, d = it - rho * nd;
-                const int gy = mf_clampi(Y0 - G::R + rho, 0, H - 1);
+                const int gy = mf_clampi(Y0 - G::RV + rho, 0, H - 1);
                 const uintptr_t a = (uintptr_t)(src + (long long)gy * pitch + (long long)gx0 * es);
                 const int lead = (int)(a & 3);            // bytes before the segment start
-                mf_obl_put_dword<V, K, TW, TH, RY, NW>(raw + rho * TW * Q, 4 * d - lead, pf.va[u],
+                mf_obl_put_dword<V, K, KH, TW, TH, RY, NW>(raw + rho * TW * Q, 4 * d - lead, pf.va[u],
                                                        G::PACK ? pf.vb[u] : 0u, es, dtype);
             }
         }
         return;
     }
-    mf_obl_load_clamped<V, K, TW, TH, RY, NW>(src, H, W, pitch, dtype, X0, Y0, raw);
+    mf_obl_load_clamped<V, K, KH, TW, TH, RY, NW>(src, H, W, pitch, dtype, X0, Y0, raw);
 }
 
 // Persistent form, stage 1a: start copying the footprint union of block
@@ -260,19 +262,19 @@ mf_obl_commit(const unsigned char* __restrict__ src, int H, int W, long long pit
 // reaches the last row); those blocks load element by element instead.
 // Chunks may run past the end of a row into the next one (never past the
 // last row's data): such bytes are never used.
-template <class V, int K, int TW, int TH, int RY, int NW>
+template <class V, int K, int KH, int TW, int TH, int RY, int NW>
 __device__ __forceinline__ int
 mf_obl_stage_issue(const unsigned char* __restrict__ src, int H, int W, long long pitch, int dtype, int X0, int Y0,
                    int aligned, uint4* stage)
 {
-    using G = MfObGeom<V, K, TW, TH, RY, NW>;
+    using G = MfObGeom<V, K, KH, TW, TH, RY, NW>;
     const int es = G::PACK ? (dtype == MF_U8 ? 1 : 2) : 4;
-    const int gx0 = X0 - G::R;
+    const int gx0 = X0 - G::RX;
     const int cb = (max(gx0, 0) * es) & ~15;          // first chunk, bytes from the row start
     const int nch = (18 + G::SPAN * es + 15) >> 4;
     const long long ce = cb + 16 * nch, row_bytes = (long long)W * es;
-    const int gyb = mf_clampi(Y0 - G::R, 0, H - 1);
-    const int gyl = mf_clampi(Y0 - G::R + G::ROWS - 1, 0, H - 1);
+    const int gyb = mf_clampi(Y0 - G::RV, 0, H - 1);
+    const int gyl = mf_clampi(Y0 - G::RV + G::ROWS - 1, 0, H - 1);
     if (!aligned || !(ce <= row_bytes || (ce <= row_bytes + pitch && gyl < H - 1))) return 0;
     // the descriptor covers the footprint's rows, up to the last chunk's end
     // (the host checks that ROWS * pitch fits in 31 bits); anything past it
@@ -287,7 +289,7 @@ mf_obl_stage_issue(const unsigned char* __restrict__ src, int H, int W, long lon
         const int i = first + lane;
         if (i < total) {
             const int rho = i / nch, ch = i - rho * nch;
-            const int gy = mf_clampi(Y0 - G::R + rho, 0, H - 1);
+            const int gy = mf_clampi(Y0 - G::RV + rho, 0, H - 1);
             const uint32_t off = (uint32_t)((long long)(gy - gyb) * pitch) + (uint32_t)(cb + 16 * ch);
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(stage + first),
                                                      16, off, 0, 0, 0);
@@ -300,14 +302,14 @@ mf_obl_stage_issue(const unsigned char* __restrict__ src, int H, int W, long lon
 // with clamped columns. The element of global column gx sits at staging byte
 // gx*es - cb of its row; for every gx the block uses,
 // max(gx0, 0) <= gx <= gx0 + SPAN - 1, so it lies in [0, 16*nch).
-template <class V, int K, int TW, int TH, int RY, int NW>
+template <class V, int K, int KH, int TW, int TH, int RY, int NW>
 __device__ __forceinline__ void mf_obl_stage_commit_clamped(const uint4* stage, int W, int dtype, int X0,
                                                             V* __restrict__ raw)
 {
-    using G = MfObGeom<V, K, TW, TH, RY, NW>;
+    using G = MfObGeom<V, K, KH, TW, TH, RY, NW>;
     constexpr int Q = G::Q, COLS = G::COLS;
     const int es = G::PACK ? (dtype == MF_U8 ? 1 : 2) : 4;
-    const int gx0 = X0 - G::R;
+    const int gx0 = X0 - G::RX;
     const int cb = (max(gx0, 0) * es) & ~15;
     const int nch = (18 + G::SPAN * es + 15) >> 4;
     const unsigned char* st = (const unsigned char*)stage;
@@ -341,13 +343,13 @@ __device__ __forceinline__ void mf_obl_stage_commit_clamped(const uint4* stage, 
 // starts at footprint column 4d - lead, at staging byte (gx0*es mod 16) rounded
 // down to 4, plus 4d (+ BWH*es for the right half); the last byte read is below
 // 12 + 4*nd + BWH*es <= 18 + SPAN*es, inside the row's nch chunks.
-template <class V, int K, int TW, int TH, int RY, int NW>
+template <class V, int K, int KH, int TW, int TH, int RY, int NW>
 __device__ __forceinline__ void mf_obl_stage_commit(const uint4* stage, int dtype, int X0, V* __restrict__ raw)
 {
-    using G = MfObGeom<V, K, TW, TH, RY, NW>;
+    using G = MfObGeom<V, K, KH, TW, TH, RY, NW>;
     constexpr int Q = G::Q, COLS = G::COLS;
     const int es = G::PACK ? (dtype == MF_U8 ? 1 : 2) : 4;
-    const int gx0 = X0 - G::R;
+    const int gx0 = X0 - G::RX;
     const int nch = (18 + G::SPAN * es + 15) >> 4;
     const int a4 = ((gx0 * es) & 15) >> 2, lead = (gx0 * es) & 3;
     const int nd = (COLS * es + 6) / 4;
@@ -359,7 +361,7 @@ __device__ __forceinline__ void mf_obl_stage_commit(const uint4* stage, int dtyp
         const uint32_t* srow = st + rho * nch * 4 + a4;
         const uint32_t va = srow[d];
         const uint32_t vb = G::PACK ? srow[d + G::BWH * es / 4] : 0u;
-        mf_obl_put_dword<V, K, TW, TH, RY, NW>(raw + rho * TW * Q, 4 * d - lead, va, vb, es, dtype);
+        mf_obl_put_dword<V, K, KH, TW, TH, RY, NW>(raw + rho * TW * Q, 4 * d - lead, va, vb, es, dtype);
     }
 }
 
@@ -368,7 +370,7 @@ __device__ __forceinline__ void mf_obl_stage_commit(const uint4* stage, int dtyp
 template <class NET, class V, int RY, int NW>
 __device__ __forceinline__ void mf_obl_colsort(const V* __restrict__ raw, V* __restrict__ colb)
 {
-    using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY, NW>;
+    using G = MfObGeom<V, NET::K, NET::KH, NET::TW, NET::TH, RY, NW>;
     constexpr int TW = NET::TW, TH = NET::TH, LC = NET::LC, Q = G::Q, COLS = G::COLS;
     const int tid = mf_tid();
     // two column segments per thread in flight hide the LDS latency
@@ -395,7 +397,7 @@ __device__ __forceinline__ void
 mf_obl_networks(const V* __restrict__ raw, const V* __restrict__ colb, unsigned char* __restrict__ dst, int H,
                 int W, long long pitch, int dtype, int X0, int Y0, unsigned char* __restrict__ out = nullptr)
 {
-    using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY, NW>;
+    using G = MfObGeom<V, NET::K, NET::KH, NET::TW, NET::TH, RY, NW>;
     constexpr bool PACK = G::PACK;
     constexpr int TW = NET::TW, TH = NET::TH, LC = NET::LC, Q = G::Q, BWH = G::BWH;
     const int tid = mf_tid();
@@ -457,7 +459,7 @@ __device__ __forceinline__ void mf_obl_store_out(const unsigned char* __restrict
                                                  int H, int W, long long pitch, int dtype, int X0, int Y0,
                                                  int aligned)
 {
-    using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY, NW>;
+    using G = MfObGeom<V, NET::K, NET::KH, NET::TW, NET::TH, RY, NW>;
     constexpr int TW = NET::TW, BH = G::TY * NET::TH;
     constexpr int BW = G::PACK ? 2 * G::BWH : G::BWH;
     const int es = G::PACK ? (dtype == MF_U8 ? 1 : 2) : 4;
@@ -503,12 +505,12 @@ __device__ __forceinline__ void
 mf_obl_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
              int H, int W, long long pitch, int dtype, int bx, int by)
 {
-    using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY, NW>;
+    using G = MfObGeom<V, NET::K, NET::KH, NET::TW, NET::TH, RY, NW>;
     __shared__ V raw[G::ROWS * NET::TW * G::Q];
     __shared__ V colb[NET::INLINE_COLS ? 1 : G::TY * NET::LC * NET::TW * G::Q];
     const int X0 = bx * (G::PACK ? 2 * G::BWH : G::BWH);
     const int Y0 = by * (G::TY * NET::TH);
-    MfObPrefetch<V, NET::K, NET::TW, NET::TH, RY, NW> pf;
+    MfObPrefetch<V, NET::K, NET::KH, NET::TW, NET::TH, RY, NW> pf;
     mf_obl_issue(src, H, W, pitch, dtype, X0, Y0, pf);
     mf_obl_commit(src, H, W, pitch, dtype, X0, Y0, pf, raw);
     __syncthreads();
@@ -538,7 +540,7 @@ mf_obl_kernel_persistent(const unsigned char* __restrict__ src0, unsigned char* 
                          int H, int W, long long pitch, long long plane_stride, int dtype, int nbx,
                          int nblocks, int total, int per, int aligned)
 {
-    using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY, NW>;
+    using G = MfObGeom<V, NET::K, NET::KH, NET::TW, NET::TH, RY, NW>;
     constexpr int BW = G::PACK ? 2 * G::BWH : G::BWH, BH = G::TY * NET::TH;
     __shared__ V raw[G::ROWS * NET::TW * G::Q];
     __shared__ V colb[NET::INLINE_COLS ? 1 : G::TY * NET::LC * NET::TW * G::Q];
@@ -553,7 +555,7 @@ mf_obl_kernel_persistent(const unsigned char* __restrict__ src0, unsigned char* 
     auto plane_dst = [&](int b) { return dst0 + (long long)(b / nblocks) * plane_stride; };
     auto bx0 = [&](int b) { return (b % nblocks % nbx) * BW; };
     auto by0 = [&](int b) { return (b % nblocks / nbx) * BH; };
-    int staged = mf_obl_stage_issue<V, NET::K, NET::TW, NET::TH, RY, NW>(
+    int staged = mf_obl_stage_issue<V, NET::K, NET::KH, NET::TW, NET::TH, RY, NW>(
         plane_src(b0), H, W, pitch, dtype, bx0(b0), by0(b0), aligned, stage);
     for (int b = b0; b < b1; ++b) {
         const unsigned char* src = plane_src(b);
@@ -564,16 +566,16 @@ mf_obl_kernel_persistent(const unsigned char* __restrict__ src0, unsigned char* 
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         if (staged == 1)
-            mf_obl_stage_commit<V, NET::K, NET::TW, NET::TH, RY, NW>(stage, dtype, X0, raw);
+            mf_obl_stage_commit<V, NET::K, NET::KH, NET::TW, NET::TH, RY, NW>(stage, dtype, X0, raw);
         else if (staged == 2)
-            mf_obl_stage_commit_clamped<V, NET::K, NET::TW, NET::TH, RY, NW>(stage, W, dtype, X0, raw);
+            mf_obl_stage_commit_clamped<V, NET::K, NET::KH, NET::TW, NET::TH, RY, NW>(stage, W, dtype, X0, raw);
         else
-            mf_obl_load_clamped<V, NET::K, NET::TW, NET::TH, RY, NW>(src, H, W, pitch, dtype, X0, Y0, raw);
+            mf_obl_load_clamped<V, NET::K, NET::KH, NET::TW, NET::TH, RY, NW>(src, H, W, pitch, dtype, X0, Y0, raw);
         if (TILE && b > b0)
             mf_obl_store_out<NET, V, RY, NW>((const unsigned char*)out, plane_dst(b - 1), H, W, pitch, dtype,
                                              bx0(b - 1), by0(b - 1), aligned);
         __syncthreads();                       // raw complete; stage and out free
-        staged = b + 1 >= b1 ? 0 : mf_obl_stage_issue<V, NET::K, NET::TW, NET::TH, RY, NW>(
+        staged = b + 1 >= b1 ? 0 : mf_obl_stage_issue<V, NET::K, NET::KH, NET::TW, NET::TH, RY, NW>(
                                    plane_src(b + 1), H, W, pitch, dtype, bx0(b + 1), by0(b + 1), aligned, stage);
         if constexpr (!NET::INLINE_COLS) {
             mf_obl_colsort<NET, V, RY, NW>(raw, colb);
@@ -672,7 +674,7 @@ static hipError_t mf_obl_launch(const void* src, void* dst, int planes, long lon
         if (resident > 0 && total > 2LL * resident && total < (1LL << 31)) {
             const int per = (int)((total + resident - 1) / resident);
             const int grid = (int)((total + per - 1) / per);
-            using G = MfObGeom<V, NET::K, NET::TW, NET::TH, RY, NW>;
+            using G = MfObGeom<V, NET::K, NET::KH, NET::TW, NET::TH, RY, NW>;
             // LDS-direct staging and 16-byte output stores need 16-byte
             // aligned rows; buffer offsets of the footprint rows stay below 2^31
             const int aligned = ((uintptr_t)src % 16 == 0 && (uintptr_t)dst % 16 == 0 && pitch % 16 == 0 &&

@@ -22,10 +22,11 @@ import os
 from . import netgen as ng
 
 
-def _net_body(P: ng.Prog, k: int, tw: int, th: int, indent: str = "    ") -> list[str]:
+def _net_body(P: ng.Prog, k: int, tw: int, th: int, indent: str = "    ", kh: int | None = None) -> list[str]:
     """Emit the live ops. Every load stays inside the root footprint
-    (x < k+tw-1, y < k+th-1) and the sorted column length (i < k-th+1): the
-    kernel's LDS buffers are sized for exactly that."""
+    (x < k+tw-1, y < kh+th-1) and the sorted column length (i < kh-th+1): the
+    kernel's LDS buffers are sized for exactly that (kh = k: square)."""
+    kh = k if kh is None else kh
     lines = []
     order = ng.demand_order(P)
     out_index = {}
@@ -37,11 +38,11 @@ def _net_body(P: ng.Prog, k: int, tw: int, th: int, indent: str = "    ") -> lis
             kind, a, b = op[1]
             if kind == "col":
                 x, i = a, b
-                assert 0 <= x < k + tw - 1 and 0 <= i < k - th + 1, op
+                assert 0 <= x < k + tw - 1 and 0 <= i < kh - th + 1, op
                 lines.append("%sconst V v%d = col[(%d) * Q + %d];" % (indent, v, i * tw + x % tw, x // tw))
             else:
                 x, y = a, b
-                assert 0 <= x < k + tw - 1 and 0 <= y < k + th - 1, op
+                assert 0 <= x < k + tw - 1 and 0 <= y < kh + th - 1, op
                 lines.append("%sconst V v%d = raw[(%d) * Q + %d];" % (indent, v, y * tw + x % tw, x // tw))
         else:
             lines.append("%sconst V v%d = %s(v%d, v%d);"
@@ -84,21 +85,25 @@ def emit_sort(n: int) -> str:
     return "\n".join(lines)
 
 
-def net_name(k: int, tw: int, th: int, inline: bool) -> str:
-    return "MfNet_k%d_%dx%d%s" % (k, tw, th, "i" if inline else "")
+def net_name(k: int, tw: int, th: int, inline: bool, kh: int | None = None) -> str:
+    win = "%d" % k if kh is None or kh == k else "%dx%d" % (k, kh)
+    return "MfNet_k%s_%dx%d%s" % (win, tw, th, "i" if inline else "")
 
 
-def emit_config_tu(k: int, tw: int, th: int, shapes, inline: bool = False) -> str:
+def emit_config_tu(k: int, tw: int, th: int, shapes, inline: bool = False, kh: int | None = None) -> str:
     """One translation unit: the network for (k, tw, th) and one kernel
-    instantiation per (tile rows per wave, waves per work-group) shape."""
-    P = ng.build_tile_program(k, tw, th, inline_cols=inline)
+    instantiation per (tile rows per wave, waves per work-group) shape. The
+    window is k columns by kh rows (kh = k: the square filter)."""
+    kh = k if kh is None else kh
+    P = ng.build_tile_program(k, tw, th, inline_cols=inline, kh=kh)
     cnt = ng.op_counts(P)
     peak = ng.peak_live(P, ng.demand_order(P))
-    name = net_name(k, tw, th, inline)
-    lc = k - th + 1
-    body = _net_body(P, k, tw, th, indent="        ")
+    name = net_name(k, tw, th, inline, kh)
+    lc = kh - th + 1
+    body = _net_body(P, k, tw, th, indent="        ", kh=kh)
+    win = "k=%d" % k if kh == k else "window %dx%d (columns x rows)" % (k, kh)
     src = [
-        "// Generated: hierarchical selection network, k=%d, root tile %dx%d." % (k, tw, th),
+        "// Generated: hierarchical selection network, %s, root tile %dx%d." % (win, tw, th),
         "// live min/max ops per root tile: %d (%.2f per pixel), LDS loads: %d"
         % (cnt["minmax"], cnt["minmax"] / (tw * th), cnt["loads"]),
         '#include "mf_oblivious.hip"',
@@ -106,9 +111,9 @@ def emit_config_tu(k: int, tw: int, th: int, shapes, inline: bool = False) -> st
         emit_sort(lc) if lc > 1 else "template <class V> __device__ __forceinline__ void mf_sort_1(V*) {}",
         "",
         "struct %s {" % name,
-        "    static constexpr int K = %d, TW = %d, TH = %d, LC = %d;" % (k, tw, th, lc),
+        "    static constexpr int K = %d, KH = %d, TW = %d, TH = %d, LC = %d;" % (k, kh, tw, th, lc),
         "    static constexpr bool INLINE_COLS = %s;" % ("true" if inline else "false"),
-        "    static constexpr bool PERSISTENT = %s;" % ("true" if k <= 17 else "false"),
+        "    static constexpr bool PERSISTENT = %s;" % ("true" if max(k, kh) <= 17 else "false"),
         # networks whose live values just about fit 256 VGPRs are built for
         # two waves per SIMD (plain and batched kernels, packed 16-bit data)
         "    static constexpr int MIN_WAVES = %d;" % (2 if peak <= 270 else 1),
@@ -126,8 +131,11 @@ def emit_config_tu(k: int, tw: int, th: int, shapes, inline: bool = False) -> st
     return "\n".join(src)
 
 
-def generate(out_dir: str, configs) -> list[str]:
-    """Write one .hip per config plus the launcher table; return the .hip paths."""
+def generate(out_dir: str, configs, rect_configs=()) -> list[str]:
+    """Write one .hip per config plus the launcher tables (square windows:
+    mf_obl_table.inc; rectangular windows, configs (k_w, k_h, t_w, t_h, rows
+    per wave, waves[, inline]): mf_obl_rect_table.inc); return the .hip
+    paths."""
     os.makedirs(out_dir, exist_ok=True)
     paths = []
     table = []
@@ -145,12 +153,32 @@ def generate(out_dir: str, configs) -> list[str]:
             with open(path, "w") as f:
                 f.write(text)
         paths.append(path)
-    tpath = os.path.join(out_dir, "mf_obl_table.inc")
-    text = "// Generated list of compiled oblivious configurations:\n" \
-        "// (network, k, t_w, t_h, tile rows per wave, waves per work-group, inline column sort)\n" \
-        + "\n".join(table) + "\n"
-    old = open(tpath).read() if os.path.exists(tpath) else None
-    if old != text:
-        with open(tpath, "w") as f:
-            f.write(text)
+    rtable = []
+    rtiles = {}
+    for cfg in rect_configs:
+        (kw, kh, tw, th, ry, nw), inline = cfg[:6], (len(cfg) > 6 and cfg[6])
+        assert kw != kh
+        rtiles.setdefault((kw, kh, tw, th, inline), []).append((ry, nw))
+        rtable.append("MF_OBL_RECT_ENTRY(%s, %d, %d, %d, %d, %d, %d, %d)"
+                      % (net_name(kw, tw, th, inline, kh), kw, kh, tw, th, ry, nw, 1 if inline else 0))
+    for (kw, kh, tw, th, inline), shapes in rtiles.items():
+        path = os.path.join(out_dir, "mf_obl_k%dx%d_%dx%d%s.hip" % (kw, kh, tw, th, "i" if inline else ""))
+        text = emit_config_tu(kw, tw, th, shapes, inline, kh)
+        old = open(path).read() if os.path.exists(path) else None
+        if old != text:
+            with open(path, "w") as f:
+                f.write(text)
+        paths.append(path)
+    for name, head, rows in (
+            ("mf_obl_table.inc",
+             "// (network, k, t_w, t_h, tile rows per wave, waves per work-group, inline column sort)", table),
+            ("mf_obl_rect_table.inc",
+             "// (network, k_w, k_h, t_w, t_h, tile rows per wave, waves per work-group, inline column sort)",
+             rtable)):
+        tpath = os.path.join(out_dir, name)
+        text = "// Generated list of compiled oblivious configurations:\n" + head + "\n" + "\n".join(rows) + "\n"
+        old = open(tpath).read() if os.path.exists(tpath) else None
+        if old != text:
+            with open(tpath, "w") as f:
+                f.write(text)
     return paths

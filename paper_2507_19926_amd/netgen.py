@@ -208,24 +208,29 @@ class _State:
     xrows: dict = field(default_factory=dict)   # y -> sorted list over core cols
 
 
-def build_tile_program(k: int, tw: int, th: int, inline_cols: bool = False) -> Prog:
+def build_tile_program(k: int, tw: int, th: int, inline_cols: bool = False,
+                       kh: int | None = None) -> Prog:
     """Straight-line selection network for one tw x th root tile.
 
+    The window is k columns by kh rows (kh defaults to k, the square filter):
+    footprint (k+tw-1) x (kh+th-1), sorted columns over the kh-th+1 core rows.
     outputs[py*tw + px] is the median of the window of pixel (px, py).
     With inline_cols the tile sorts its own footprint columns from raw loads
     (pruned to the ranks it uses) instead of loading pre-sorted shared
     columns: no shared column buffer, more work per tile (small k).
     """
-    assert k % 2 == 1 and k >= 1
+    kw = k
+    kh = k if kh is None else kh
+    assert kw % 2 == 1 and kw >= 1 and kh % 2 == 1 and kh >= 1
     assert tw >= 1 and th >= 1 and (tw & (tw - 1)) == 0 and (th & (th - 1)) == 0
-    assert tw <= k and th <= k
+    assert tw <= kw and th <= kh
     P = Prog()
-    N = k * k
-    Lc = k - th + 1
+    N = kw * kh
+    Lc = kh - th + 1
 
     def col(x):
         if inline_cols:
-            return sort(P, [P.load(("raw", x, y)) for y in range(th - 1, k)])
+            return sort(P, [P.load(("raw", x, y)) for y in range(th - 1, kh)])
         return [P.load(("col", x, i)) for i in range(Lc)]
 
     def raw(x, y):
@@ -233,13 +238,13 @@ def build_tile_program(k: int, tw: int, th: int, inline_cols: bool = False) -> P
 
     # Initialisation (Section 3.3): sorted columns (loads of pre-sorted data),
     # sorted extra rows, core = multi-way merge of the sorted core columns.
-    core_x = range(tw - 1, k)
+    core_x = range(tw - 1, kw)
     core = multiway(P, [col(x) for x in core_x])
     core = trim(core, N - len(core_x) * Lc)
     st = _State(0, 0, tw, th, core)
-    for x in list(range(0, tw - 1)) + list(range(k, k + tw - 1)):
+    for x in list(range(0, tw - 1)) + list(range(kw, kw + tw - 1)):
         st.xcols[x] = col(x)
-    for y in list(range(0, th - 1)) + list(range(k, k + th - 1)):
+    for y in list(range(0, th - 1)) + list(range(kh, kh + th - 1)):
         st.xrows[y] = sort(P, [raw(x, y) for x in core_x])
 
     out = {}
@@ -252,14 +257,14 @@ def build_tile_program(k: int, tw: int, th: int, inline_cols: bool = False) -> P
         if s.tw >= s.th:
             h = s.tw // 2
             for child_ox, added in ((s.ox, range(s.ox + h - 1, s.ox + s.tw - 1)),
-                                    (s.ox + h, range(s.ox + k, s.ox + k + h))):
-                ncx = (k - h + 1)
-                ncy = (k - s.th + 1)
+                                    (s.ox + h, range(s.ox + kw, s.ox + kw + h))):
+                ncx = (kw - h + 1)
+                ncy = (kh - s.th + 1)
                 c = merge(P, s.core, multiway(P, [s.xcols[x] for x in added]))
                 c = trim(c, N - ncx * ncy)
                 ch = _State(child_ox, s.oy, h, s.th, c)
                 for x in list(range(child_ox, child_ox + h - 1)) + \
-                        list(range(child_ox + k, child_ox + k + h - 1)):
+                        list(range(child_ox + kw, child_ox + kw + h - 1)):
                     ch.xcols[x] = s.xcols[x]
                 for y, row in s.xrows.items():
                     ch.xrows[y] = merge(P, row, sort(P, [raw(x, y) for x in added]))
@@ -267,14 +272,14 @@ def build_tile_program(k: int, tw: int, th: int, inline_cols: bool = False) -> P
         else:
             h = s.th // 2
             for child_oy, added in ((s.oy, range(s.oy + h - 1, s.oy + s.th - 1)),
-                                    (s.oy + h, range(s.oy + k, s.oy + k + h))):
-                ncx = (k - s.tw + 1)
-                ncy = (k - h + 1)
+                                    (s.oy + h, range(s.oy + kh, s.oy + kh + h))):
+                ncx = (kw - s.tw + 1)
+                ncy = (kh - h + 1)
                 c = merge(P, s.core, multiway(P, [s.xrows[y] for y in added]))
                 c = trim(c, N - ncx * ncy)
                 ch = _State(s.ox, child_oy, s.tw, h, c)
                 for y in list(range(child_oy, child_oy + h - 1)) + \
-                        list(range(child_oy + k, child_oy + k + h - 1)):
+                        list(range(child_oy + kh, child_oy + kh + h - 1)):
                     ch.xrows[y] = s.xrows[y]
                 for x, cl in s.xcols.items():
                     ch.xcols[x] = merge(P, cl, sort(P, [raw(x, y) for y in added]))
@@ -342,22 +347,25 @@ def max_live(P: Prog) -> int:
 
 # ------------------------------------------------------------ CPU model
 
-def evaluate_on_image(P: Prog, img: np.ndarray, k: int, tw: int, th: int) -> np.ndarray:
-    """Run a tile program over every root tile of `img` (replicate border).
+def evaluate_on_image(P: Prog, img: np.ndarray, k: int, tw: int, th: int,
+                      kh: int | None = None) -> np.ndarray:
+    """Run a tile program over every root tile of `img` (replicate border),
+    window k columns by kh rows (kh defaults to k).
 
     A debugging model of the GPU kernel: sorted columns come from numpy sorts
     of the footprint columns, every op is applied to all tiles at once.
     """
+    kw = k
+    kh = k if kh is None else kh
     H, W = img.shape
-    r = (k - 1) // 2
     nty, ntx = -(-H // th), -(-W // tw)
-    ys = np.clip(np.arange(nty * th + k - 1) - r, 0, H - 1)
-    xs = np.clip(np.arange(ntx * tw + k - 1) - r, 0, W - 1)
+    ys = np.clip(np.arange(nty * th + kh - 1) - (kh - 1) // 2, 0, H - 1)
+    xs = np.clip(np.arange(ntx * tw + kw - 1) - (kw - 1) // 2, 0, W - 1)
     pad = img[ys][:, xs]
-    fh, fw = k + th - 1, k + tw - 1
+    fh, fw = kh + th - 1, kw + tw - 1
     # footprint of every tile: (nty, ntx, fh, fw)
     win = np.lib.stride_tricks.sliding_window_view(pad, (fh, fw))[::th, ::tw]
-    core_sorted = np.sort(win[:, :, th - 1:k, :], axis=2)  # (nty, ntx, Lc, fw)
+    core_sorted = np.sort(win[:, :, th - 1:kh, :], axis=2)  # (nty, ntx, Lc, fw)
     vals = [None] * len(P.ops)
     for v in live_ops(P):
         op = P.ops[v]

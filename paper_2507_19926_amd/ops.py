@@ -69,8 +69,8 @@ def median_filter(x: torch.Tensor, k: int, out: torch.Tensor | None = None,
     return out
 
 
-def median_filter_rect(x: torch.Tensor, kw: int, kh: int,
-                       out: torch.Tensor | None = None) -> torch.Tensor:
+def median_filter_rect(x: torch.Tensor, kw: int, kh: int, out: torch.Tensor | None = None,
+                       variant: int = _lib.MF_VARIANT_AUTO) -> torch.Tensor:
     """Exact median of the kw x kh window (kw columns, kh rows, both odd;
     replicate border) of every (H, W) plane of x, through
     median_filter_rect. Layout rules as in ``median_filter``; the planes must
@@ -96,8 +96,9 @@ def median_filter_rect(x: torch.Tensor, kw: int, kh: int,
     if n == 0:
         return out
     stride = planes_x.stride(0) * es if n > 1 else 0
+    opt = _lib.options(variant)
     _lib.check(_lib.lib().median_filter_rect(x.data_ptr(), out.data_ptr(), n, stride, H, W, pitch, code,
-                                             int(kw), int(kh), _lib.MF_BORDER_REPLICATE,
+                                             int(kw), int(kh), _lib.MF_BORDER_REPLICATE, ctypes.byref(opt),
                                              _stream_handle(x.device)))
     return out
 

@@ -109,8 +109,9 @@ def test_rect_entry_validation():
     assert side >= 31
 
     def call(kw=5, kh=3, planes=1, stride=0, src=FAKE_SRC, dst=FAKE_DST, H=16, W=16, pitch=16, dtype=0,
-             border=0):
-        return L.median_filter_rect(src, dst, planes, stride, H, W, pitch, dtype, kw, kh, border, None)
+             border=0, opt=None):
+        o = ctypes.byref(opt) if opt is not None else None
+        return L.median_filter_rect(src, dst, planes, stride, H, W, pitch, dtype, kw, kh, border, o, None)
 
     for kw, kh in ((4, 3), (3, 4), (0, 3), (3, -1), (side + 2, 3), (3, side + 2)):
         assert call(kw=kw, kh=kh) == -5, (kw, kh)
@@ -121,15 +122,23 @@ def test_rect_entry_validation():
     assert call(planes=0) == -2 and call(planes=2, stride=255) == -3
     assert call(planes=3, stride=256, dst=FAKE_SRC + 600) == -7
     assert L.mf_last_error().decode() != ""
+    # options: only the variant applies to a rectangular window
+    assert call(opt=_lib.options(variant=9)) == -10
+    assert call(opt=_lib.options(tile=(2, 2))) == -10
+    assert call(opt=_lib.options(group=4)) == -10
+    assert call(kw=31, kh=9, opt=_lib.options(variant=_lib.MF_VARIANT_OBLIVIOUS)) == -10   # no network
 
 
 def test_rect_config_query():
-    from paper_2507_19926_amd import emit_da
+    from paper_2507_19926_amd import build as mfbuild, emit_da
     for dtype in range(4):
-        for kw, kh in ((31, 9), (1, 31), (3, 5)):
+        for kw, kh in ((31, 9), (1, 31), (11, 3)):
             v, tw, th = _lib.query_rect_config(dtype, kw, kh)
             assert v == _lib.MF_VARIANT_DATA_AWARE and 1 <= tw <= kw and 1 <= th <= kh
             assert (tw, th) == emit_da.candidates(kw, 4, {}, kh, emit_da.LDS_BUDGETS[:1])[0][:2]
+        # shapes with a compiled network run it
+        for cfg in mfbuild.RECT_OBL_CONFIGS:
+            assert _lib.query_rect_config(dtype, cfg[0], cfg[1]) == (_lib.MF_VARIANT_OBLIVIOUS, cfg[2], cfg[3])
     assert _lib.query_rect_config(0, 9, 9) == _lib.query_config(0, 9)
     for kw, kh in ((2, 3), (33, 1)):
         with pytest.raises(_lib.MfError):

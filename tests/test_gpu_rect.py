@@ -5,7 +5,7 @@ import pytest
 import torch
 
 import oracle
-from paper_2507_19926_amd import _lib, workloads as wl
+from paper_2507_19926_amd import _lib, build as mfbuild, workloads as wl
 from paper_2507_19926_amd.ops import median_filter, median_filter_rect
 
 pytestmark = pytest.mark.gpu
@@ -25,8 +25,8 @@ def _img(dtype, H, W, seed):
     return wl.uniform_plane(H, W, dtype, seed)
 
 
-def _rect(a, kw, kh):
-    out = median_filter_rect(_dev(a), kw, kh)
+def _rect(a, kw, kh, variant=_lib.MF_VARIANT_AUTO):
+    out = median_filter_rect(_dev(a), kw, kh, variant=variant)
     torch.cuda.synchronize()
     return out.cpu().numpy()
 
@@ -52,13 +52,50 @@ def test_rect_matches_oracle(kw, kh, dtype):
 @pytest.mark.parametrize("kw", list(range(1, 32, 2)))
 def test_every_rect_window(kw):
     """Each generated rectangular schedule once (the two element sizes share
-    it), dtype rotating over the shapes."""
+    it), data-aware variant forced, dtype rotating over the shapes."""
     for i, kh in enumerate(range(1, 32, 2)):
         if kh == kw:
             continue
         dtype = DTYPES[(kw + i) % 4]
         img = _img(dtype, 37, 53, seed=kw * 1000 + kh)
-        assert _eq(_rect(img, kw, kh), oracle.median_filter_rect(img, kw, kh)), (kw, kh, dtype)
+        got = _rect(img, kw, kh, variant=_lib.MF_VARIANT_DATA_AWARE)
+        assert _eq(got, oracle.median_filter_rect(img, kw, kh)), (kw, kh, dtype)
+
+
+RECT_OBL = [tuple(c[:2]) for c in mfbuild.RECT_OBL_CONFIGS]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("kw,kh", RECT_OBL)
+def test_rect_oblivious_networks(kw, kh, dtype):
+    """Every compiled rectangular network: several work-groups in each
+    direction with ragged edges, against the oracle and the data-aware
+    variant."""
+    H, W = 61 + 5 * kh, 1100 + 3 * kw
+    img = _img(dtype, H, W, seed=kw * 31 + kh)
+    got = _rect(img, kw, kh, variant=_lib.MF_VARIANT_OBLIVIOUS)
+    want = oracle.median_filter_rect(img, kw, kh)
+    if not _eq(got, want):
+        bad = np.argwhere(got.view(np.uint8).reshape(H, -1) != want.view(np.uint8).reshape(H, -1))
+        pytest.fail("%dx%d %s: %d mismatching bytes, first at %s"
+                    % (kw, kh, np.dtype(dtype).name, len(bad), bad[:5].tolist()))
+    assert _eq(got, _rect(img, kw, kh, variant=_lib.MF_VARIANT_DATA_AWARE))
+
+
+@pytest.mark.parametrize("kw,kh", [(5, 3), (3, 9), (15, 5), (5, 15)])
+def test_rect_oblivious_large_image(kw, kh):
+    """Enough blocks for the persistent form (rows in ranges across planes),
+    uint8 and float32, three planes, sampled rows and points."""
+    for dtype in (np.uint8, np.float32):
+        planes = np.stack([_img(dtype, 2000, 3000, seed=s + kw) for s in range(3)])
+        got = _rect(planes, kw, kh, variant=_lib.MF_VARIANT_OBLIVIOUS)
+        for c in range(3):
+            H, W = planes[c].shape
+            for a, b in ((0, 16), (H // 2 - 8, H // 2 + 8), (H - 16, H)):
+                assert _eq(got[c][a:b], oracle.median_filter_rect(planes[c], kw, kh, rows=(a, b))), (c, a)
+            g = wl.rng(kw * 5 + kh + c)
+            ys, xs = g.integers(0, H, 1500), g.integers(0, W, 1500)
+            assert _eq(got[c][ys, xs], oracle.median_points_rect(planes[c], kw, kh, ys, xs)), c
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -133,3 +170,48 @@ def test_rect_rejects_bad_windows():
     for kw, kh in ((2, 3), (3, 0), (side + 2, 1)):
         with pytest.raises(_lib.MfError):
             median_filter_rect(x, kw, kh)
+    with pytest.raises(_lib.MfError):
+        median_filter_rect(x, 31, 9, variant=_lib.MF_VARIANT_OBLIVIOUS)
+
+
+TORCH_DT = {np.dtype(np.uint8): torch.uint8, np.dtype(np.uint16): torch.uint16,
+            np.dtype(np.uint32): torch.uint32, np.dtype(np.float32): torch.float32}
+
+
+def _placed(img, placement):
+    """(x, out) device views of img: a plain tensor, or views into bigger
+    buffers starting 16 or 4 bytes in, or with a pitch that is not a
+    multiple of 16 bytes."""
+    H, W = img.shape
+    es = img.dtype.itemsize
+    tdt = TORCH_DT[img.dtype]
+    if placement == "aligned":
+        x = _dev(img)
+        return x, torch.empty_like(x)
+    lead = {"offset16": 16, "offset4": 4, "pitch_odd": 0}[placement] // es
+    pitch = W + 16 // es + (1 if placement == "pitch_odd" else 0)
+    n = H * pitch + lead + W
+    xb = torch.zeros(n * es, dtype=torch.uint8, device="cuda").view(tdt)
+    x = xb[lead:lead + H * pitch].view(H, pitch)[:, :W]
+    x.copy_(_dev(img))
+    ob = torch.zeros(n * es, dtype=torch.uint8, device="cuda").view(tdt)
+    return x, ob[lead:lead + H * pitch].view(H, pitch)[:, :W]
+
+
+@pytest.mark.parametrize("placement", ["aligned", "offset16", "offset4", "pitch_odd"])
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("kw,kh", [(5, 3), (3, 9), (15, 5)])
+def test_rect_oblivious_placements(kw, kh, dtype, placement):
+    """Rectangular networks on a plane large enough for the persistent form,
+    with rows 16-byte aligned (LDS-direct staging) or not (element loads)."""
+    img = _img(dtype, 4000, 3000, seed=kw * 3 + kh)
+    x, out = _placed(img, placement)
+    median_filter_rect(x, kw, kh, out=out, variant=_lib.MF_VARIANT_OBLIVIOUS)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    H, W = img.shape
+    for a, b in ((0, 12), (H // 2 - 6, H // 2 + 6), (H - 12, H)):
+        assert _eq(got[a:b], oracle.median_filter_rect(img, kw, kh, rows=(a, b))), (a, b)
+    g = wl.rng(kw + kh)
+    ys, xs = g.integers(0, H, 2000), g.integers(0, W, 2000)
+    assert _eq(got[ys, xs], oracle.median_points_rect(img, kw, kh, ys, xs))

@@ -131,3 +131,25 @@ def test_inline_column_program_matches_oracle(k, tw, th):
     assert all(op[1][0] == "raw" for op in P.ops if op[0] == ng.LD)
     img = wl.uniform_plane(23, 37, np.uint8, seed=k)
     np.testing.assert_array_equal(ng.evaluate_on_image(P, img, k, tw, th), oracle.median_filter(img, k))
+
+
+@pytest.mark.parametrize("kw,kh,tw,th", [(5, 3, 4, 2), (3, 5, 2, 4), (9, 3, 4, 2), (3, 9, 2, 4), (7, 5, 4, 4),
+                                         (5, 9, 4, 4), (15, 5, 4, 4), (5, 15, 4, 4), (3, 1, 2, 1), (1, 3, 1, 2)])
+def test_rect_tile_program_matches_oracle(kw, kh, tw, th):
+    """The rectangular network (k_w columns, k_h rows: separate radii, the
+    sorted columns over k_h-t_h+1 core rows) against the oracle's kw x kh
+    median, on random and tie-heavy images."""
+    P = ng.build_tile_program(kw, tw, th, kh=kh)
+    for dtype, shape, seed in ((np.uint8, (23, 37), 1), (np.uint16, (19, 16), 2), (np.uint32, (9, 30), 3)):
+        img = wl.uniform_plane(*shape, dtype, seed=seed + kw * 7 + kh)
+        np.testing.assert_array_equal(ng.evaluate_on_image(P, img, kw, tw, th, kh),
+                                      oracle.median_filter_rect(img, kw, kh))
+    ties = wl.tie_heavy_plane(21, 26, np.uint8, levels=3, seed=kw + kh)
+    np.testing.assert_array_equal(ng.evaluate_on_image(P, ties, kw, tw, th, kh),
+                                  oracle.median_filter_rect(ties, kw, kh))
+    # every load stays inside the rectangular footprint
+    for op in P.ops:
+        if op[0] == ng.LD:
+            kind, a, b = op[1]
+            assert 0 <= a < kw + tw - 1
+            assert 0 <= b < (kh - th + 1 if kind == "col" else kh + th - 1)
