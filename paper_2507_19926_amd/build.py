@@ -53,6 +53,15 @@ RECT_OBL_CONFIGS = [
     (9, 3, 4, 2, 2, 4), (3, 9, 2, 4, 1, 4),
     (7, 5, 4, 4, 1, 4), (5, 7, 4, 4, 1, 4), (9, 5, 4, 4, 1, 4), (5, 9, 4, 4, 1, 4),
     (9, 7, 4, 4, 1, 4), (7, 9, 4, 4, 1, 4), (15, 5, 4, 4, 1, 4), (5, 15, 4, 4, 1, 4),
+    # larger shapes: the root tile with the fewest min/max per pixel among
+    # those whose network's live values stay near the register file (wide
+    # windows take wide tiles, tall windows tall ones)
+    (5, 1, 4, 1, 4, 4), (1, 5, 1, 4, 1, 4), (9, 1, 8, 1, 1, 4), (1, 9, 1, 8, 1, 4),
+    (11, 3, 8, 1, 1, 4), (3, 11, 1, 8, 1, 4), (31, 3, 8, 1, 1, 4), (3, 31, 1, 8, 1, 4),
+    (11, 5, 8, 1, 1, 4), (5, 11, 4, 4, 1, 4), (13, 5, 8, 1, 1, 4), (5, 13, 4, 4, 1, 4),
+    (17, 5, 8, 1, 1, 4), (5, 17, 4, 4, 1, 4), (11, 7, 8, 2, 1, 4), (7, 11, 4, 4, 1, 4),
+    (21, 7, 8, 1, 1, 4), (7, 21, 4, 4, 1, 4), (13, 9, 8, 2, 1, 4), (9, 13, 4, 4, 1, 4),
+    (17, 9, 8, 2, 1, 4), (9, 17, 4, 4, 1, 4),
 ]
 
 HIP_FLAGS = [
