@@ -62,6 +62,8 @@ RECT_OBL_CONFIGS = [
     (17, 5, 8, 1, 1, 4), (5, 17, 4, 4, 1, 4), (11, 7, 8, 2, 1, 4), (7, 11, 4, 4, 1, 4),
     (21, 7, 8, 1, 1, 4), (7, 21, 4, 4, 1, 4), (13, 9, 8, 2, 1, 4), (9, 13, 4, 4, 1, 4),
     (17, 9, 8, 2, 1, 4), (9, 17, 4, 4, 1, 4),
+    (31, 5, 8, 1, 1, 4), (5, 31, 1, 8, 1, 4), (31, 7, 8, 1, 1, 4), (7, 31, 2, 8, 1, 4),
+    (21, 9, 8, 2, 1, 4), (9, 21, 4, 4, 1, 4), (31, 9, 8, 2, 1, 4), (9, 31, 2, 8, 1, 4),
 ]
 
 HIP_FLAGS = [

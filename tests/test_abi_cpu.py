@@ -126,13 +126,13 @@ def test_rect_entry_validation():
     assert call(opt=_lib.options(variant=9)) == -10
     assert call(opt=_lib.options(tile=(2, 2))) == -10
     assert call(opt=_lib.options(group=4)) == -10
-    assert call(kw=31, kh=9, opt=_lib.options(variant=_lib.MF_VARIANT_OBLIVIOUS)) == -10   # no network
+    assert call(kw=25, kh=11, opt=_lib.options(variant=_lib.MF_VARIANT_OBLIVIOUS)) == -10   # no network
 
 
 def test_rect_config_query():
     from paper_2507_19926_amd import build as mfbuild, emit_da
     for dtype in range(4):
-        for kw, kh in ((31, 9), (1, 31), (23, 3)):
+        for kw, kh in ((29, 9), (1, 31), (23, 3)):
             v, tw, th = _lib.query_rect_config(dtype, kw, kh)
             assert v == _lib.MF_VARIANT_DATA_AWARE and 1 <= tw <= kw and 1 <= th <= kh
             assert (tw, th) == emit_da.candidates(kw, 4, {}, kh, emit_da.LDS_BUDGETS[:1])[0][:2]
