@@ -64,7 +64,9 @@ RECT_OBL_CONFIGS = [
     (17, 9, 8, 2, 1, 4), (9, 17, 4, 4, 1, 4),
     (31, 5, 8, 1, 1, 4), (5, 31, 1, 8, 1, 4), (31, 7, 8, 1, 1, 4), (7, 31, 2, 8, 1, 4),
     (21, 9, 8, 2, 1, 4), (9, 21, 4, 4, 1, 4), (31, 9, 8, 2, 1, 4), (9, 31, 2, 8, 1, 4),
-]
+    # one-dimensional windows (running medians along rows or columns)
+    (7, 1, 4, 1, 4, 4), (1, 7, 1, 4, 1, 4),
+] + [c for n in range(11, 32, 2) for c in ((n, 1, 8, 1, 1, 4), (1, n, 1, 8, 1, 4))]
 
 HIP_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=%s" % ARCH, "-fPIC",

@@ -22,7 +22,8 @@ RGB30_H, RGB30_W = 4480, 6720
 #: odd kernel diameters of the uint8 sweep
 RGB30_KS = (3, 5, 7, 9, 11, 15, 17, 25, 35, 51, 75)
 #: rectangular windows (kw columns, kh rows) timed on the same frame
-RGB30_RECT = ((5, 3), (9, 5), (15, 5), (5, 15), (17, 9), (31, 3), (31, 9), (9, 31), (31, 1), (1, 31), (31, 29))
+RGB30_RECT = ((5, 3), (9, 5), (15, 5), (5, 15), (17, 9), (31, 3), (31, 9), (9, 31), (31, 1), (1, 31),
+              (21, 13), (31, 29))
 #: dtype sweep at 4096 x 4096
 SWEEP_SIDE = 4096
 SWEEP_KS = (3, 7, 17, 35, 75)

@@ -132,7 +132,8 @@ def test_rect_entry_validation():
 def test_rect_config_query():
     from paper_2507_19926_amd import build as mfbuild, emit_da
     for dtype in range(4):
-        for kw, kh in ((29, 9), (1, 31), (23, 3)):
+        compiled = {tuple(c[:2]) for c in mfbuild.RECT_OBL_CONFIGS}
+        for kw, kh in [w for w in ((29, 9), (3, 13), (23, 3), (27, 31)) if w not in compiled]:
             v, tw, th = _lib.query_rect_config(dtype, kw, kh)
             assert v == _lib.MF_VARIANT_DATA_AWARE and 1 <= tw <= kw and 1 <= th <= kh
             assert (tw, th) == emit_da.candidates(kw, 4, {}, kh, emit_da.LDS_BUDGETS[:1])[0][:2]
