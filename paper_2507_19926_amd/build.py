@@ -64,6 +64,15 @@ RECT_OBL_CONFIGS = [
     (17, 9, 8, 2, 1, 4), (9, 17, 4, 4, 1, 4),
     (31, 5, 8, 1, 1, 4), (5, 31, 1, 8, 1, 4), (31, 7, 8, 1, 1, 4), (7, 31, 2, 8, 1, 4),
     (21, 9, 8, 2, 1, 4), (9, 21, 4, 4, 1, 4), (31, 9, 8, 2, 1, 4), (9, 31, 2, 8, 1, 4),
+    # the remaining shapes with sides 3..17, same rule (4x4 where a wider or
+    # taller tile's persistent kernel would not fit the LDS)
+    (3, 13, 1, 8, 1, 4), (3, 15, 1, 8, 1, 4), (3, 17, 1, 8, 1, 4), (7, 13, 4, 4, 1, 4),
+    (7, 15, 4, 4, 1, 4), (7, 17, 4, 4, 1, 4), (9, 11, 4, 4, 1, 4), (9, 15, 4, 4, 1, 4),
+    (11, 9, 8, 2, 1, 4), (11, 13, 4, 4, 1, 4), (11, 15, 4, 4, 1, 4), (11, 17, 4, 4, 1, 4),
+    (13, 3, 8, 1, 1, 4), (13, 7, 8, 2, 1, 4), (13, 11, 4, 4, 1, 4), (13, 15, 4, 4, 1, 4),
+    (13, 17, 4, 4, 1, 4), (15, 3, 8, 1, 1, 4), (15, 7, 8, 2, 1, 4), (15, 9, 8, 2, 1, 4),
+    (15, 11, 4, 4, 1, 4), (15, 13, 4, 4, 1, 4), (15, 17, 4, 4, 1, 4), (17, 3, 8, 1, 1, 4),
+    (17, 7, 8, 2, 1, 4), (17, 11, 4, 4, 1, 4), (17, 13, 4, 4, 1, 4), (17, 15, 4, 4, 1, 4),
     # one-dimensional windows (running medians along rows or columns)
     (7, 1, 4, 1, 4, 4), (1, 7, 1, 4, 1, 4),
 ] + [c for n in range(11, 32, 2) for c in ((n, 1, 8, 1, 1, 4), (1, n, 1, 8, 1, 4))]
