@@ -13,7 +13,7 @@ a seeded synthetic plane of the class's dtype, and writes a JSON table:
 uint32/float32. The build reads ``tuned.json`` next to this file and compiles
 the choices into the library's AUTO table.
 
-Usage (on a GPU): python -m paper_2507_19926_amd.autotune [--out PATH]
+Usage (on a GPU): python -m paper_2507_19926_amd.autotune [--out PATH] [--ks K ...]
 """
 from __future__ import annotations
 
@@ -80,8 +80,17 @@ def main():
     ap.add_argument("--out", default=TUNED)
     ap.add_argument("--shape", type=int, nargs=2, default=(4480, 6720),
                     help="plane rows and columns to time on (default: one 30 MP plane)")
+    ap.add_argument("--ks", type=int, nargs="+", default=None,
+                    help="re-time only these k and merge them into the existing table")
     args = ap.parse_args()
-    t = tune(shape=tuple(args.shape))
+    t = tune(shape=tuple(args.shape), ks=args.ks)
+    if args.ks and os.path.exists(args.out):
+        with open(args.out) as f:
+            old = json.load(f)
+        for cls in CLASSES:
+            old.setdefault(cls, {}).update(t[cls])
+        old.setdefault("timings_ms", {}).update(t["timings_ms"])
+        t = old
     with open(args.out, "w") as f:
         json.dump(t, f, indent=1, sort_keys=True)
     print("wrote", args.out)
