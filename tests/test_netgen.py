@@ -153,3 +153,14 @@ def test_rect_tile_program_matches_oracle(kw, kh, tw, th):
             kind, a, b = op[1]
             assert 0 <= a < kw + tw - 1
             assert 0 <= b < (kh - th + 1 if kind == "col" else kh + th - 1)
+
+
+def test_every_compiled_rect_network_matches_oracle():
+    """Each rectangular network the library compiles (build.RECT_OBL_CONFIGS),
+    run by the CPU model on one ragged image, against the oracle."""
+    from paper_2507_19926_amd import build as mfbuild
+    for kw, kh, tw, th in (tuple(c[:4]) for c in mfbuild.RECT_OBL_CONFIGS):
+        P = ng.build_tile_program(kw, tw, th, kh=kh)
+        img = wl.uniform_plane(3 * th + 5, 3 * tw + 7, np.uint16, seed=kw * 97 + kh)
+        np.testing.assert_array_equal(ng.evaluate_on_image(P, img, kw, tw, th, kh),
+                                      oracle.median_filter_rect(img, kw, kh), err_msg="%dx%d" % (kw, kh))
