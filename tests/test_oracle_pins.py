@@ -350,6 +350,13 @@ def test_rect_brute_force_full_sort(dtype, shape):
                                       err_msg="%dx%d" % (kw, kh))
 
 
+def test_rect_hand_worked():
+    g = _read_golden("hand_rect_3x1_1x3.txt")
+    img = np.array(g["input"], dtype=np.uint8)
+    np.testing.assert_array_equal(oracle.median_filter_rect(img, 3, 1), np.array(g["horizontal"], dtype=np.uint8))
+    np.testing.assert_array_equal(oracle.median_filter_rect(img, 1, 3), np.array(g["vertical"], dtype=np.uint8))
+
+
 def test_rect_square_is_the_k_by_k_filter():
     img = wl.tie_heavy_plane(19, 23, np.uint16, levels=5, seed=12)
     for k in (1, 3, 7, 13):
