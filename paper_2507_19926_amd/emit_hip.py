@@ -85,6 +85,31 @@ def emit_sort(n: int) -> str:
     return "\n".join(lines)
 
 
+LDS_BYTES = 160 * 1024
+
+
+def persistent_lds_bytes(kw: int, kh: int, tw: int, th: int, ry: int, nw: int) -> int:
+    """LDS of the persistent oblivious kernel (footprint union, sorted column
+    segments, staging chunks, output tile) for the larger of its two value
+    types, following the block geometry of csrc/mf_oblivious.hip (MfObGeom);
+    the kernel's own static_assert checks the same budget at compile time."""
+    worst = 0
+    for pack in (True, False):
+        bwh = 64 * tw
+        cols = bwh + kw - 1
+        ty = nw * ry
+        rows = ty * th + kh - 1
+        q = -(-cols // tw)
+        raw = rows * tw * q * 4
+        colb = ty * (kh - th + 1) * tw * q * 4
+        span = bwh + cols if pack else cols
+        nch = (18 + span * (2 if pack else 4) + 15) // 16
+        stage = -(-rows * nch // 64) * 64 * 16
+        out = ty * th * (2 * bwh if pack else bwh) * (2 if pack else 4)
+        worst = max(worst, raw + colb + stage + out)
+    return worst
+
+
 def net_name(k: int, tw: int, th: int, inline: bool, kh: int | None = None) -> str:
     win = "%d" % k if kh is None or kh == k else "%dx%d" % (k, kh)
     return "MfNet_k%s_%dx%d%s" % (win, tw, th, "i" if inline else "")
@@ -93,8 +118,15 @@ def net_name(k: int, tw: int, th: int, inline: bool, kh: int | None = None) -> s
 def emit_config_tu(k: int, tw: int, th: int, shapes, inline: bool = False, kh: int | None = None) -> str:
     """One translation unit: the network for (k, tw, th) and one kernel
     instantiation per (tile rows per wave, waves per work-group) shape. The
-    window is k columns by kh rows (kh = k: the square filter)."""
+    window is k columns by kh rows (kh = k: the square filter). Square
+    networks get the persistent form up to k = 17; rectangular ones whenever
+    its LDS fits."""
     kh = k if kh is None else kh
+    if kh == k:
+        persistent = k <= 17
+    else:
+        persistent = not inline and all(persistent_lds_bytes(k, kh, tw, th, ry, nw) <= LDS_BYTES
+                                        for (ry, nw) in shapes)
     P = ng.build_tile_program(k, tw, th, inline_cols=inline, kh=kh)
     cnt = ng.op_counts(P)
     peak = ng.peak_live(P, ng.demand_order(P))
@@ -113,7 +145,7 @@ def emit_config_tu(k: int, tw: int, th: int, shapes, inline: bool = False, kh: i
         "struct %s {" % name,
         "    static constexpr int K = %d, KH = %d, TW = %d, TH = %d, LC = %d;" % (k, kh, tw, th, lc),
         "    static constexpr bool INLINE_COLS = %s;" % ("true" if inline else "false"),
-        "    static constexpr bool PERSISTENT = %s;" % ("true" if max(k, kh) <= 17 else "false"),
+        "    static constexpr bool PERSISTENT = %s;" % ("true" if persistent else "false"),
         # networks whose live values just about fit 256 VGPRs are built for
         # two waves per SIMD (plain and batched kernels, packed 16-bit data)
         "    static constexpr int MIN_WAVES = %d;" % (2 if peak <= 270 else 1),
