@@ -60,10 +60,10 @@ RECT_OBL_CONFIGS = [
     (11, 3, 8, 1, 1, 4), (3, 11, 1, 8, 1, 4), (31, 3, 8, 1, 1, 4), (3, 31, 1, 8, 1, 4),
     (11, 5, 8, 1, 1, 4), (5, 11, 4, 4, 1, 4), (13, 5, 8, 1, 1, 4), (5, 13, 4, 4, 1, 4),
     (17, 5, 8, 1, 1, 4), (5, 17, 4, 4, 1, 4), (11, 7, 8, 2, 1, 4), (7, 11, 4, 4, 1, 4),
-    (21, 7, 8, 1, 1, 4), (7, 21, 4, 4, 1, 4), (13, 9, 8, 2, 1, 4), (9, 13, 4, 4, 1, 4),
+    (21, 7, 8, 1, 1, 4), (7, 21, 2, 8, 1, 4), (13, 9, 8, 2, 1, 4), (9, 13, 4, 4, 1, 4),
     (17, 9, 8, 2, 1, 4), (9, 17, 4, 4, 1, 4),
     (31, 5, 8, 1, 1, 4), (5, 31, 1, 8, 1, 4), (31, 7, 8, 1, 1, 4), (7, 31, 2, 8, 1, 4),
-    (21, 9, 8, 2, 1, 4), (9, 21, 4, 4, 1, 4), (31, 9, 8, 2, 1, 4), (9, 31, 2, 8, 1, 4),
+    (21, 9, 8, 2, 1, 4), (9, 21, 2, 8, 1, 4), (31, 9, 8, 2, 1, 4), (9, 31, 2, 8, 1, 4),
     # the remaining shapes with sides 3..17, same rule (4x4 where a wider or
     # taller tile's persistent kernel would not fit the LDS)
     (3, 13, 1, 8, 1, 4), (3, 15, 1, 8, 1, 4), (3, 17, 1, 8, 1, 4), (7, 13, 4, 4, 1, 4),
