@@ -43,7 +43,8 @@ def parse():
     p.add_argument("--window", default=None,
                    help="KWxKH: time this rectangular window (kw columns, kh rows) in place of k "
                         "(for profiling one data-aware schedule)")
-    p.add_argument("--sweep-steps", type=int, default=5, help="timed steps per k of the sweep (0 = no sweep)")
+    p.add_argument("--sweep-steps", type=int, default=50,
+                   help="timed launches per k of the sweeps, median reported (0 = no sweep)")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle work for the CPU baseline")
     p.add_argument("--only-headline", action="store_true", help="time only the headline k (for profilers)")
@@ -55,25 +56,34 @@ def parse():
 
 
 def algorithmic_ops_per_pixel(dtype_code: int, k: int, kh: int | None = None):
-    """(variant, tile, element-ops per output pixel) for what the library runs
-    (k x k window, or k columns by kh rows).
+    """(variant, tile, element-ops per output pixel, packed) for what the
+    library runs (k x k window, or k columns by kh rows). `packed` tells
+    whether two element-ops share one 32-bit lane-op (packed 16-bit min/max).
 
     Oblivious: live min/max of the generated network per root tile / pixels,
     plus the column sort network (one sort of k-t_h+1 values per image column
-    and tile row, i.e. per t_h pixels)."""
+    and tile row, i.e. per t_h pixels). Column-strip form (k = 3): 3 ops to
+    sort the three values of a column (v_min3, v_med3, v_max3), one sorted
+    column per pixel, plus 4 ops for the pruned merge of three sorted columns
+    (max of minima, median of medians, min of maxima, median of the three);
+    these are 32-bit lane-ops, one element each."""
     from paper_2507_19926_amd import _lib, dagen, netgen as ng
     if kh is not None and kh != k:
         variant, tw, th = _lib.query_rect_config(dtype_code, k, kh)
+        form = 0
     else:
         kh = k
-        variant, tw, th = _lib.query_config(dtype_code, k)
+        variant, tw, th, _, form, _ = _lib.query_options(dtype_code, k)
+    packed = dtype_code in (_lib.MF_U8, _lib.MF_U16)
     if variant == _lib.MF_VARIANT_OBLIVIOUS:
+        if form == 3:
+            return variant, (tw, th), 3.0 + 4.0, False
         P = ng.build_tile_program(k, tw, th, kh=kh)
         net = ng.op_counts(P)["minmax"] / (tw * th)
         srt = ng.op_counts(ng.build_sort_program(kh - th + 1))["minmax"] / th
-        return variant, (tw, th), net + srt
+        return variant, (tw, th), net + srt, packed
     # data-aware: merge outputs per pixel of the schedule
-    return variant, (tw, th), dagen.schedule(k, tw, th, kh=kh).stats["per_pixel_outputs"]
+    return variant, (tw, th), dagen.schedule(k, tw, th, kh=kh).stats["per_pixel_outputs"], packed
 
 
 def measured_traffic(k: int, tile):
@@ -103,7 +113,7 @@ def roofline(dtype_code: int, k: int, pixels_per_launch: int, launch_s: float, k
     from paper_2507_19926_amd import _lib
     es = {0: 1, 1: 2, 2: 4, 3: 4}[dtype_code]
     bytes_per_launch = 2 * es * pixels_per_launch
-    variant, tile, ops_px = algorithmic_ops_per_pixel(dtype_code, k, kh)
+    variant, tile, ops_px, packed = algorithmic_ops_per_pixel(dtype_code, k, kh)
     if variant == _lib.MF_VARIANT_DATA_AWARE:
         # each merge output is one LDS read and one LDS write of an element
         # (2 bytes for 8/16-bit data, 4 for 32-bit)
@@ -116,7 +126,6 @@ def roofline(dtype_code: int, k: int, pixels_per_launch: int, launch_s: float, k
             return {"bound": "lds", "achieved": achieved / 1e9, "peak": LDS_PEAK_BPS / 1e9, "unit": "GB/s",
                     "frac": achieved / LDS_PEAK_BPS, "traffic": None,
                     "merge_outputs_per_pixel": round(ops_px, 2), "variant": variant, "tile": list(tile)}
-    packed = dtype_code in (0, 1)
     valu_peak = VALU_LANES_PER_S * (2 if packed else 1)    # element-ops/s
     t_hbm = bytes_per_launch / HBM_PEAK_BPS
     t_alu = (ops_px * pixels_per_launch / valu_peak) if ops_px else 0.0
@@ -132,17 +141,20 @@ def roofline(dtype_code: int, k: int, pixels_per_launch: int, launch_s: float, k
 
 
 def _time(fn, steps, warmup, stream):
+    """Median over `steps` launches of the HIP-event time of one call of fn
+    (events recorded on `stream`, the stream fn launches on), in seconds."""
+    import numpy as np
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(steps):
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for e0, e1 in evs:
+        e0.record(stream)
         fn()
-    e1.record(stream)
+        e1.record(stream)
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / 1e3 / steps
+    return float(np.median([e0.elapsed_time(e1) for e0, e1 in evs])) / 1e3
 
 
 def measured_peaks(dev, stream):
@@ -192,13 +204,17 @@ def run_extras(args, dev, stream):
     from paper_2507_19926_amd.ops import (BatchedPlan, median_filter, median_filter_argmedian,
                                           median_filter_backward)
     out = {}
-    # dtype sweep: two distinct planes per dtype, alternated
+    # dtype sweep: at least 8 distinct input/output pairs per dtype, more than
+    # 512 MB in all (the 256 MB MALL cannot hold them), rotated per launch;
+    # median over the sweep steps
     sweep = {}
     side = wl.SWEEP_SIDE
     for name, dt, code in (("u16", np.uint16, _lib.MF_U16), ("u32", np.uint32, _lib.MF_U32),
                            ("f32", np.float32, _lib.MF_F32)):
         base = wl.sweep_plane(dt)
-        xs = [torch.from_numpy(base).to(dev), torch.from_numpy(np.roll(base, 131, axis=1)).to(dev)]
+        pair_bytes = 2 * base.nbytes
+        nsets = max(8, -(-(512 << 20) // pair_bytes) + 1)
+        xs = [torch.from_numpy(np.ascontiguousarray(np.roll(base, 131 * s, axis=1))).to(dev) for s in range(nsets)]
         ys = [torch.empty_like(x) for x in xs]
         res = {}
         for k in wl.SWEEP_KS:
@@ -206,12 +222,14 @@ def run_extras(args, dev, stream):
 
             def one():
                 i = state["i"] = state["i"] + 1
-                median_filter(xs[i % 2], k, out=ys[i % 2])
-            t = _time(one, 3 if k >= 35 else 6, 1, stream)
+                median_filter(xs[i % nsets], k, out=ys[i % nsets])
+            t = _time(one, args.sweep_steps, 2, stream)
             r = roofline(code, k, side * side, t)
-            res[str(k)] = {"mpix_s": round(side * side / t / 1e6, 1), "kernel_ms": round(t * 1e3, 4),
+            res[str(k)] = {"mpix_s": round(side * side / t / 1e6, 1), "kernel_ms_median": round(t * 1e3, 4),
                            "bound": r["bound"], "frac": round(r["frac"], 4), "variant": r["variant"],
                            "tile": r["tile"]}
+        res["buffer_sets"] = nsets
+        res["working_set_MB"] = round(nsets * pair_bytes / 1e6, 1)
         sweep[name] = res
         del xs, ys
     out["dtype_sweep_4096"] = sweep
@@ -230,8 +248,8 @@ def run_extras(args, dev, stream):
     def per_image():
         for x, k, o in zip(xs, ks, outs):
             median_filter(x, k, out=o)
-    t_plain = _time(per_image, 5, 2, stream)
-    t_plan = _time(plan.launch, 5, 2, stream)
+    t_plain = _time(per_image, 20, 2, stream)
+    t_plan = _time(plan.launch, 20, 2, stream)
     npx = sum(int(x.numel()) for x in xs)
     nb, blocks = plan.info()
     out["batched"] = {"images": len(xs), "pixels": npx, "plan_ms": round(t_plan * 1e3, 3),
@@ -250,9 +268,9 @@ def run_extras(args, dev, stream):
 
         def fwd():
             holder["idx"] = median_filter_argmedian(x, k)[1]
-        t_f = _time(fwd, 3, 1, stream)
+        t_f = _time(fwd, 20, 1, stream)
         idx = holder["idx"]
-        t_b = _time(lambda: median_filter_backward(g, idx, k), 5, 1, stream)
+        t_b = _time(lambda: median_filter_backward(g, idx, k), 20, 1, stream)
         n = x.numel()
         ag[str(k)] = {"fwd_ms": round(t_f * 1e3, 3), "bwd_ms": round(t_b * 1e3, 3),
                       "fwd_mpix_s": round(n / t_f / 1e6, 1), "bwd_mpix_s": round(n / t_b / 1e6, 1),
@@ -325,11 +343,11 @@ def main():
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         launch_ms = [e0.elapsed_time(e1) for (e0, e1) in evs]
-        return wall, float(np.mean(launch_ms)) / 1e3
+        return wall, float(np.mean(launch_ms)) / 1e3, float(np.median(launch_ms)) / 1e3
 
     px_step = 3 * H * W
     # headline
-    wall, launch_s = run(kw, args.steps, args.warmup, kh)
+    wall, launch_s, launch_med_s = run(kw, args.steps, args.warmup, kh)
     value = px_step * args.steps / wall / 1e6
     roof = roofline(_lib.MF_U8, kw, px_step, launch_s, kh)
     square = kw == kh
@@ -338,6 +356,8 @@ def main():
     roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     roof["algorithmic_bytes_per_launch"] = 2 * px_step
     roof["launch"] = "one launch per step: the frame's 3 planes (%s)" % ("median_filter_planes" if square else "median_filter_rect")
+    roof["launch_ms_mean"] = round(launch_s * 1e3, 4)
+    roof["launch_ms_median"] = round(launch_med_s * 1e3, 4)
     per_k = {}
     if args.sweep_steps > 0 and not args.only_headline:
         for k in wl.RGB30_KS:
@@ -346,30 +366,22 @@ def main():
             except _lib.MfError:
                 per_k[str(k)] = "unsupported"
                 continue
-            w, ls = run(k, args.sweep_steps, 2)
+            w, _, ls = run(k, args.sweep_steps, 2)
             r = roofline(_lib.MF_U8, k, px_step, ls)
-            per_k[str(k)] = {"mpix_s": round(px_step * args.sweep_steps / w / 1e6, 1),
-                             "frame_ms": round(ls * 1e3, 4), "bound": r["bound"],
-                             "frac": round(r["frac"], 4), "variant": r["variant"], "tile": r["tile"]}
+            per_k[str(k)] = {"mpix_s": round(px_step / ls / 1e6, 1),
+                             "frame_ms_median": round(ls * 1e3, 4), "bound": r["bound"],
+                             "frac": round(r["frac"], 4), "variant": r["variant"], "tile": r["tile"],
+                             "ops_per_pixel": r.get("merge_outputs_per_pixel", r.get("ops_per_pixel"))}
     rect = {}
     if args.sweep_steps > 0 and not args.only_headline:
-        from paper_2507_19926_amd.ops import median_filter_rect
-        for kw, kh in wl.RGB30_RECT:
-            for i in range(2):
-                median_filter_rect(ins[i], kw, kh, out=outs[i])
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for i in range(args.sweep_steps):
-                median_filter_rect(ins[i % nsets], kw, kh, out=outs[i % nsets])
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ls = e0.elapsed_time(e1) / 1e3 / args.sweep_steps
-            r = roofline(_lib.MF_U8, kw, px_step, ls, kh)
-            rect["%dx%d" % (kw, kh)] = {"mpix_s": round(px_step / ls / 1e6, 1), "frame_ms": round(ls * 1e3, 4),
-                                        "bound": r["bound"], "frac": round(r["frac"], 4),
-                                        "variant": r["variant"], "tile": r["tile"],
-                                        "ops_per_pixel": r.get("merge_outputs_per_pixel", r.get("ops_per_pixel"))}
+        for rkw, rkh in wl.RGB30_RECT:
+            _, _, ls = run(rkw, args.sweep_steps, 2, rkh)
+            r = roofline(_lib.MF_U8, rkw, px_step, ls, rkh)
+            rect["%dx%d" % (rkw, rkh)] = {"mpix_s": round(px_step / ls / 1e6, 1),
+                                          "frame_ms_median": round(ls * 1e3, 4),
+                                          "bound": r["bound"], "frac": round(r["frac"], 4),
+                                          "variant": r["variant"], "tile": r["tile"],
+                                          "ops_per_pixel": r.get("merge_outputs_per_pixel", r.get("ops_per_pixel"))}
     extras = {}
     if not args.no_extras and not args.only_headline:
         extras = run_extras(args, dev, stream)
@@ -399,10 +411,9 @@ def main():
         dt = time.perf_counter() - t
         cpu = {"value": round(done * W / dt / 1e6, 3), "unit": "Mpixel/s", "cores": nthreads,
                "kind": "oracle",
-               "sample": "%d rows of 6720 px (%.2f passes over the 3-plane frame, %d px) at k=%d, %.1f s"
-                         % (done, done / (3 * H), done * W, args.k, dt)}
-        if not square:
-            cpu["sample"] = cpu["sample"].replace("k=%d" % args.k, "window %dx%d" % (kw, kh))
+               "sample": "%d rows of 6720 px (%.2f passes over the 3-plane frame, %d px) at %s, %.1f s"
+                         % (done, done / (3 * H), done * W,
+                            "k=%d" % kw if square else "window %dx%d" % (kw, kh), dt)}
 
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mpixel/s", "n_gpus": 1,

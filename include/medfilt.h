@@ -157,6 +157,15 @@ int32_t mf_peak_minmax(void* out, int32_t blocks, int32_t iters, void* stream);
 int32_t mf_query_config(int32_t dtype, int32_t k, const mf_options* opt,
                         int32_t* variant, int32_t* tile_w, int32_t* tile_h);
 
+/* As mf_query_config, with every field of the configuration that runs:
+ * variant, root tile, group (oblivious: waves per work-group; data-aware:
+ * root tiles per work-group), form (oblivious column-sort form, 3 = the
+ * k = 3 column-strip form) and rows (oblivious tile rows per wave); fields
+ * that do not apply are 0. k = 1 (a copy) gives variant 0 and a 1x1 tile.
+ * Host only. MF_ERR_NULL for a NULL `resolved`, other errors as
+ * mf_query_config. */
+int32_t mf_query_options(int32_t dtype, int32_t k, const mf_options* opt, mf_options* resolved);
+
 /* ---- Batched form -------------------------------------------------------
  * Many images of uneven sizes, kernel diameters and dtypes filtered by ONE
  * hipGraph launch. A plan groups its images by kernel (variant, k, root tile,

@@ -71,6 +71,8 @@ def lib():
     L.mf_query_config.argtypes = [i32, i32, ctypes.POINTER(mf_options), ctypes.POINTER(i32),
                                   ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.mf_query_config.restype = i32
+    L.mf_query_options.argtypes = [i32, i32, ctypes.POINTER(mf_options), ctypes.POINTER(mf_options)]
+    L.mf_query_options.restype = i32
     L.median_filter_fwd_argmedian.argtypes = [vp, vp, vp, i64, i64, i64, i32, i32, vp]
     L.median_filter_fwd_argmedian.restype = i32
     L.median_filter_bwd_gather.argtypes = [vp, vp, vp, i64, i64, i64, i32, i32, vp]
@@ -137,6 +139,14 @@ def query_config(dtype_code: int, k: int, variant: int = MF_VARIANT_AUTO, tile=N
     check(lib().mf_query_config(dtype_code, k, ctypes.byref(o), ctypes.byref(v), ctypes.byref(tw),
                                 ctypes.byref(th)))
     return v.value, tw.value, th.value
+
+
+def query_options(dtype_code: int, k: int, variant: int = MF_VARIANT_AUTO, tile=None):
+    """Resolved (variant, tile_w, tile_h, group, form, rows) the library runs."""
+    o = options(variant, tile)
+    r = mf_options()
+    check(lib().mf_query_options(dtype_code, k, ctypes.byref(o), ctypes.byref(r)))
+    return r.variant, r.tile_w, r.tile_h, r.group, r.form, r.rows
 
 
 def query_rect_config(dtype_code: int, kw: int, kh: int):

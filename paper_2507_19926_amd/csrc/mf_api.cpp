@@ -390,6 +390,35 @@ int32_t mf_query_config(int32_t dtype, int32_t k, const mf_options* opt, int32_t
     return resolve(dtype, k, opt, variant, tile_w, tile_h, &e);
 }
 
+int32_t mf_query_options(int32_t dtype, int32_t k, const mf_options* opt, mf_options* resolved)
+{
+    g_last_error.clear();
+    if (!resolved) return fail(MF_ERR_NULL, "output pointer is NULL");
+    if (!elem_size(dtype)) return fail(MF_ERR_DTYPE, "unknown dtype %d", dtype);
+    if (k < 1 || k % 2 == 0 || k > kMaxK) return fail(MF_ERR_K, "k=%d must be odd in [1, %d]", k, kMaxK);
+    mf_options r = {};
+    if (k == 1) {
+        r.tile_w = r.tile_h = 1;
+        *resolved = r;
+        return MF_OK;
+    }
+    const OblEntry* e = nullptr;
+    int32_t group = 0;
+    const int32_t rc = resolve(dtype, k, opt, &r.variant, &r.tile_w, &r.tile_h, &e, &group);
+    if (rc) return rc;
+    if (e) {
+        r.group = e->nw;
+        r.form = e->form;
+        r.rows = e->ry;
+    } else {
+        int tw = 0, th = 0, g = 0;
+        if (!group) mf_da_default_tile(dtype, k, &tw, &th, &g);
+        r.group = group ? group : g;
+    }
+    *resolved = r;
+    return MF_OK;
+}
+
 static bool overlap(const void* a, size_t na, const void* b, size_t nb)
 {
     const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;

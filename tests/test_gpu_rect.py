@@ -200,7 +200,7 @@ def _placed(img, placement):
 
 @pytest.mark.parametrize("placement", ["aligned", "offset16", "offset4", "pitch_odd"])
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("kw,kh", [(5, 3), (3, 9), (15, 5), (31, 9), (1, 31)])
+@pytest.mark.parametrize("kw,kh", [(5, 3), (3, 9), (15, 5), (31, 9), (1, 31), (7, 21), (9, 21), (7, 31)])
 def test_rect_oblivious_placements(kw, kh, dtype, placement):
     """Rectangular networks on a plane large enough for the persistent form,
     with rows 16-byte aligned (LDS-direct staging) or not (element loads)."""

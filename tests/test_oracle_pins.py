@@ -315,11 +315,23 @@ def test_gradient_matches_finite_differences():
 
 
 def test_gradient_order_is_ascending():
-    # Three contributions to one pixel whose float32 sum depends on the order:
-    # (1e8 + 1) - 1e8 = 0 but 1e8 + (1 - 1e8) = 1 would need reassociation.
-    g = np.array([1e8, 1.0, -1e8], dtype=np.float32)
-    idx = np.array([0, 0, 0], dtype=np.int32)
-    assert oracle.grad_f32(g, idx)[0] == np.float32((np.float32(1e8) + np.float32(1.0)) - np.float32(1e8))
+    """Three contributions to one pixel whose binary32 sum depends on the
+    order they are added in. In ascending output order [1e8, -1e8, 1] sums to
+    (1e8 - 1e8) + 1 = 1, while descending order gives (1 - 1e8) + 1e8 = 0
+    because 1 - 1e8 rounds to -1e8; any other association of the three terms
+    gives 0 as well. The same terms in reversed positions must give 0."""
+    idx = np.zeros(3, dtype=np.int32)
+    g = np.array([1e8, -1e8, 1.0], dtype=np.float32)
+    assert np.float32(1.0) - np.float32(1e8) == np.float32(-1e8)    # the rounding the pin relies on
+    got = oracle.grad_f32(g, idx)
+    assert got[0] == np.float32(1.0) and got[1] == 0 and got[2] == 0
+    got = oracle.grad_f32(g[::-1].copy(), idx)
+    assert got[0] == np.float32(0.0)
+    # the same through a plane: pixels 0, 1, 2 all select pixel 1
+    g2 = np.array([[1e8, -1e8, 1.0]], dtype=np.float32)
+    idx2 = np.ones((1, 3), dtype=np.int32)
+    got2 = oracle.grad_f32(g2, idx2)
+    assert got2.tolist() == [[0.0, 1.0, 0.0]]
 
 
 # ------------------------------------------------ rectangular kw x kh windows
