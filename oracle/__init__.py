@@ -8,7 +8,8 @@ and called through ctypes on host numpy arrays.
 What it computes is the definition of the median filter (Sugy 2025, Section 1):
 every output pixel is the rank-(k*k-1)/2 element of the k x k window around it,
 with replicate borders and IEEE totalOrder for float32; the ``*_rect``
-functions take a kw x kh window (odd sides) instead. ``argmedian_f32`` and
+functions take a kw x kh window (odd sides) instead, and ``median_filter_3d``
+a kx x ky x kz box over a volume. ``argmedian_f32`` and
 ``grad_f32`` add the index of the selected input pixel (lowest plane-flat index
 among window pixels bit-equal to the median) and the gradient scatter in
 ascending output order. Each function is pinned by the CPU oracle tests.
@@ -63,6 +64,9 @@ def _load():
     lib.oracle_median_points_rect.restype = i32
     lib.oracle_argmedian_f32.argtypes = [vp, vp, vp, i64, i64, i32, i64, i64, i32]
     lib.oracle_argmedian_f32.restype = i32
+    lib.oracle_median_filter_3d.argtypes = [vp, vp, i64, i64, i64, i64, i64, i32, i32, i32, i32, i64, i64,
+                                            i32]
+    lib.oracle_median_filter_3d.restype = i32
     lib.oracle_grad_f32.argtypes = [vp, vp, vp, i64]
     lib.oracle_grad_f32.restype = i32
     _lib = lib
@@ -129,6 +133,29 @@ def median_filter_rect(img: np.ndarray, kw: int, kh: int, rows: tuple[int, int] 
     if rc:
         raise ValueError("oracle_median_filter_rect: bad argument (code %d)" % rc)
     return out[a:b].copy() if rows is not None else out
+
+
+def median_filter_3d(vol: np.ndarray, kx: int, ky: int | None = None, kz: int | None = None,
+                     slices: tuple[int, int] | None = None, nthreads: int = 0) -> np.ndarray:
+    """Median of the kx x ky x kz box (odd sides; ky, kz default to kx) around
+    every voxel of a (D, H, W) volume, each axis clamped (replicate border).
+    With ``slices=(a, b)`` only slices a..b-1 are computed and returned."""
+    ky = kx if ky is None else ky
+    kz = kx if kz is None else kz
+    if vol.ndim != 3:
+        raise ValueError("median_filter_3d needs a (D, H, W) volume")
+    if np.dtype(vol.dtype) not in DTYPE_CODE:
+        raise TypeError("unsupported dtype %s" % vol.dtype)
+    vol = np.ascontiguousarray(vol)
+    D, H, W = vol.shape
+    a, b = (0, D) if slices is None else slices
+    out = np.zeros_like(vol)
+    es = vol.dtype.itemsize       # contiguous: rows W*es apart, slices H*W*es apart
+    rc = _load().oracle_median_filter_3d(_ptr(vol), _ptr(out), D, H, W, W * es, H * W * es,
+                                         DTYPE_CODE[vol.dtype], int(kx), int(ky), int(kz), a, b, nthreads)
+    if rc:
+        raise ValueError("oracle_median_filter_3d: bad argument (code %d)" % rc)
+    return out[a:b].copy() if slices is not None else out
 
 
 def median_points_rect(img: np.ndarray, kw: int, kh: int, ys, xs,

@@ -17,7 +17,8 @@
  *   W(y,x)  = { src[B(y+dy,H)][B(x+dx,W)] : dy,dx in [-r, r] }
  *   out(y,x) = element of rank m (0-based) of W(y,x) under the dtype's order
  * A kw x kh window (odd kw columns, odd kh rows) takes dx in [-(kw-1)/2,
- * (kw-1)/2], dy in [-(kh-1)/2, (kh-1)/2], N = kw*kh.
+ * (kw-1)/2], dy in [-(kh-1)/2, (kh-1)/2], N = kw*kh. The 3-D filter takes a
+ * kx x ky x kz box over a volume in the same way, clamping each axis.
  *
  * The paper states no border rule, no float semantics and no gradient; the
  * readings used here are:
@@ -245,6 +246,57 @@ int oracle_median_points(const void* src, int64_t H, int64_t W, int64_t pitch_by
                          int64_t n, void* out, int nthreads)
 {
     return oracle_median_points_rect(src, H, W, pitch_bytes, dtype, k, k, ys, xs, n, out, nthreads);
+}
+
+/* 3-D median filter (the paper's future-work extension to volumes, Section
+ * 7.2): every output voxel is the median of the kx x ky x kz box centred on
+ * it, coordinates clamped in each axis (replicate border), rank
+ * (kx*ky*kz - 1) / 2. The volume is D slices of H rows of W elements; rows
+ * are pitch_bytes apart and slices slice_bytes apart (src and dst share
+ * both). Slices [z_begin, z_end) are computed. Returns 0 or a negative code
+ * on a bad argument. */
+int oracle_median_filter_3d(const void* src, void* dst, int64_t D, int64_t H, int64_t W,
+                            int64_t pitch_bytes, int64_t slice_bytes, int dtype, int kx, int ky,
+                            int kz, int64_t z_begin, int64_t z_end, int nthreads)
+{
+    static const int size_of[4] = {1, 2, 4, 4};
+    int rc = check_args(src, dst, H, W, pitch_bytes, dtype, kx, ky);
+    if (rc) return rc;
+    if (D < 1) return -2;
+    if (kz < 1 || (kz % 2) == 0) return -5;
+    if (slice_bytes < (H - 1) * pitch_bytes + W * size_of[dtype] || slice_bytes % size_of[dtype]) return -3;
+    if (z_begin < 0) z_begin = 0;
+    if (z_end > D) z_end = D;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    const int rx = (kx - 1) / 2, ry = (ky - 1) / 2, rz = (kz - 1) / 2;
+    const int64_t N = (int64_t)kx * ky * kz;
+    const unsigned char* s8 = (const unsigned char*)src;
+    unsigned char* d8 = (unsigned char*)dst;
+#pragma omp parallel
+    {
+        int64_t* buf = (int64_t*)malloc((size_t)N * sizeof(int64_t));
+#pragma omp for schedule(dynamic, 1) collapse(2)
+        for (int64_t z = z_begin; z < z_end; ++z)
+            for (int64_t y = 0; y < H; ++y)
+                for (int64_t x = 0; x < W; ++x) {
+                    int64_t n = 0;
+                    for (int dz = -rz; dz <= rz; ++dz) {
+                        const unsigned char* sl = s8 + clamp_index(z + dz, D) * slice_bytes;
+                        for (int dy = -ry; dy <= ry; ++dy) {
+                            const int64_t yy = clamp_index(y + dy, H);
+                            for (int dx = -rx; dx <= rx; ++dx)
+                                buf[n++] = load_key(sl, pitch_bytes, dtype, yy, clamp_index(x + dx, W));
+                        }
+                    }
+                    store_key(d8 + z * slice_bytes, pitch_bytes, dtype, y, x, select_rank(buf, n, (n - 1) / 2));
+                }
+        free(buf);
+    }
+    return 0;
 }
 
 /* Median value and argmedian of rows [row_begin, row_end) of a contiguous

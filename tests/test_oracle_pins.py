@@ -421,3 +421,99 @@ def test_rect_rows_points_and_bad_sides():
     for kw, kh in ((2, 3), (3, 4), (0, 1), (3, -1)):
         with pytest.raises(ValueError):
             oracle.median_filter_rect(img, kw, kh)
+
+
+# ---------------------------------------------------------------- 3-D boxes
+
+def _volume(dtype, shape, seed):
+    if dtype == np.float32:
+        return np.stack([wl.float_specials_plane(shape[1], shape[2], seed + z) for z in range(shape[0])])
+    return np.stack([wl.uniform_plane(shape[1], shape[2], dtype, seed + z) for z in range(shape[0])])
+
+
+def _brute_sort_median_3d(vol, kx, ky, kz):
+    """Full sort of every edge-padded box under the dtype's order (numpy): an
+    independent algorithm."""
+    rx, ry, rz = (kx - 1) // 2, (ky - 1) // 2, (kz - 1) // 2
+    pad = np.pad(vol, ((rz, rz), (ry, ry), (rx, rx)), mode="edge")
+    win = np.lib.stride_tricks.sliding_window_view(pad, (kz, ky, kx))
+    flat = win.reshape(vol.shape + (kx * ky * kz,))
+    order = np.argsort(_keys(flat), axis=-1, kind="stable")
+    mid = np.take_along_axis(order, np.full(vol.shape + (1,), (kx * ky * kz - 1) // 2), axis=-1)
+    return np.take_along_axis(flat, mid, axis=-1)[..., 0]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("box", [(3, 3, 3), (5, 3, 1), (1, 3, 5), (3, 5, 7), (7, 7, 7), (9, 1, 3)])
+def test_3d_brute_force_full_sort(dtype, box):
+    vol = _volume(dtype, (6, 7, 9), seed=sum(box))
+    got = oracle.median_filter_3d(vol, *box)
+    want = _brute_sort_median_3d(vol, *box)
+    assert got.view(np.uint8).tobytes() == want.view(np.uint8).tobytes()
+
+
+def test_3d_one_slice_deep_box_is_the_2d_filter():
+    """A single slice with kz > 1: every box holds kz copies of the 2-D
+    window (the clamped z coordinates all hit slice 0), and the median of a
+    multiset repeated an odd number of times is its median."""
+    img = wl.uniform_plane(11, 13, np.uint16, seed=3)
+    for kx, ky, kz in ((3, 3, 5), (5, 3, 3), (7, 5, 9)):
+        got = oracle.median_filter_3d(img[None], kx, ky, kz)[0]
+        np.testing.assert_array_equal(got, oracle.median_filter_rect(img, kx, ky))
+
+
+def test_3d_flat_box_is_the_2d_filter_per_slice():
+    vol = _volume(np.uint8, (5, 12, 10), seed=8)
+    got = oracle.median_filter_3d(vol, 5, 3, 1)
+    for z in range(vol.shape[0]):
+        np.testing.assert_array_equal(got[z], oracle.median_filter_rect(vol[z], 5, 3))
+
+
+def test_3d_axis_permutation():
+    """Permuting the volume's axes permutes the box sides (fails if two
+    radii are swapped)."""
+    vol = _volume(np.uint8, (5, 8, 11), seed=21)
+    a = oracle.median_filter_3d(vol, 3, 5, 7)              # kx=3, ky=5, kz=7
+    b = oracle.median_filter_3d(vol.transpose(2, 1, 0), 7, 5, 3)
+    np.testing.assert_array_equal(a, b.transpose(2, 1, 0))
+
+
+def _threshold_decomposition_u8_3d(vol, kx, ky, kz):
+    """median = sum over tau of [#{box >= tau} >= (N+1)/2], counts from
+    summed-volume tables of the edge-padded volume (no sorting)."""
+    rx, ry, rz = (kx - 1) // 2, (ky - 1) // 2, (kz - 1) // 2
+    D, H, W = vol.shape
+    need = (kx * ky * kz + 1) // 2
+    pad = np.pad(vol, ((rz, rz), (ry, ry), (rx, rx)), mode="edge").astype(np.int32)
+    out = np.zeros(vol.shape, dtype=np.int32)
+    for tau in range(1, 256):
+        b = (pad >= tau).astype(np.int32)
+        s = np.zeros((b.shape[0] + 1, b.shape[1] + 1, b.shape[2] + 1), dtype=np.int32)
+        s[1:, 1:, 1:] = b.cumsum(0).cumsum(1).cumsum(2)
+        z0, z1 = slice(0, D), slice(kz, kz + D)
+        y0, y1 = slice(0, H), slice(ky, ky + H)
+        x0, x1 = slice(0, W), slice(kx, kx + W)
+        cnt = (s[z1, y1, x1] - s[z0, y1, x1] - s[z1, y0, x1] - s[z1, y1, x0]
+               + s[z0, y0, x1] + s[z0, y1, x0] + s[z1, y0, x0] - s[z0, y0, x0])
+        out += (cnt >= need)
+    return out.astype(np.uint8)
+
+
+@pytest.mark.parametrize("box", [(3, 3, 3), (5, 5, 5), (9, 7, 5), (11, 11, 11)])
+def test_3d_threshold_decomposition_u8(box):
+    vol = _volume(np.uint8, (9, 10, 12), seed=box[0])
+    np.testing.assert_array_equal(oracle.median_filter_3d(vol, *box), _threshold_decomposition_u8_3d(vol, *box))
+
+
+def test_3d_identity_constant_impulse_and_slices():
+    vol = _volume(np.uint32, (4, 6, 5), seed=2)
+    np.testing.assert_array_equal(oracle.median_filter_3d(vol, 1), vol)
+    c = np.full((5, 6, 7), 77, np.uint8)
+    np.testing.assert_array_equal(oracle.median_filter_3d(c, 5), c)
+    imp = c.copy()
+    imp[2, 3, 3] = 255
+    np.testing.assert_array_equal(oracle.median_filter_3d(imp, 3), c)
+    full = oracle.median_filter_3d(vol, 3, 5, 3)
+    np.testing.assert_array_equal(oracle.median_filter_3d(vol, 3, 5, 3, slices=(1, 3)), full[1:3])
+    with pytest.raises(ValueError):
+        oracle.median_filter_3d(vol, 3, 3, 4)
