@@ -66,7 +66,12 @@ def algorithmic_ops_per_pixel(dtype_code: int, k: int, kh: int | None = None):
     sort the three values of a column (v_min3, v_med3, v_max3), one sorted
     column per pixel, plus 4 ops for the pruned merge of three sorted columns
     (max of minima, median of medians, min of maxima, median of the three);
-    these are 32-bit lane-ops, one element each."""
+    these are 32-bit lane-ops, one element each.
+
+    Data-aware: two lane-ops per merge output (the compare that picks the
+    smaller head and the min that produces it) plus two per compare-exchange
+    of the per-lane sorting networks (min and max), from the schedule; the
+    kernel computes on unpacked 32-bit lanes."""
     from paper_2507_19926_amd import _lib, dagen, netgen as ng
     if kh is not None and kh != k:
         variant, tw, th = _lib.query_rect_config(dtype_code, k, kh)
@@ -82,8 +87,8 @@ def algorithmic_ops_per_pixel(dtype_code: int, k: int, kh: int | None = None):
         net = ng.op_counts(P)["minmax"] / (tw * th)
         srt = ng.op_counts(ng.build_sort_program(kh - th + 1))["minmax"] / th
         return variant, (tw, th), net + srt, packed
-    # data-aware: merge outputs per pixel of the schedule
-    return variant, (tw, th), dagen.schedule(k, tw, th, kh=kh).stats["per_pixel_outputs"], packed
+    st = dagen.schedule(k, tw, th, kh=kh).stats
+    return variant, (tw, th), 2.0 * (st["per_pixel_outputs"] + st["per_pixel_sort_ces"]), False
 
 
 def measured_traffic(k: int, tile):
@@ -114,26 +119,25 @@ def roofline(dtype_code: int, k: int, pixels_per_launch: int, launch_s: float, k
     es = {0: 1, 1: 2, 2: 4, 3: 4}[dtype_code]
     bytes_per_launch = 2 * es * pixels_per_launch
     variant, tile, ops_px, packed = algorithmic_ops_per_pixel(dtype_code, k, kh)
-    if variant == _lib.MF_VARIANT_DATA_AWARE:
-        # each merge output is one LDS read and one LDS write of an element
-        # (2 bytes for 8/16-bit data, 4 for 32-bit)
-        lds_es = 2 if dtype_code in (0, 1) else 4
-        lds_bytes = ops_px * pixels_per_launch * 2 * lds_es
-        t_lds = lds_bytes / LDS_PEAK_BPS
-        t_hbm = bytes_per_launch / HBM_PEAK_BPS
-        if t_lds >= t_hbm:
-            achieved = lds_bytes / launch_s
-            return {"bound": "lds", "achieved": achieved / 1e9, "peak": LDS_PEAK_BPS / 1e9, "unit": "GB/s",
-                    "frac": achieved / LDS_PEAK_BPS, "traffic": None,
-                    "merge_outputs_per_pixel": round(ops_px, 2), "variant": variant, "tile": list(tile)}
     valu_peak = VALU_LANES_PER_S * (2 if packed else 1)    # element-ops/s
     t_hbm = bytes_per_launch / HBM_PEAK_BPS
     t_alu = (ops_px * pixels_per_launch / valu_peak) if ops_px else 0.0
     if ops_px is not None and t_alu > t_hbm:
         achieved = ops_px * pixels_per_launch / launch_s
-        return {"bound": "alu", "achieved": achieved / 1e12, "peak": valu_peak / 1e12,
-                "unit": "Tops/s", "frac": achieved / valu_peak, "traffic": None,
-                "ops_per_pixel": round(ops_px, 2), "variant": variant, "tile": list(tile)}
+        r = {"bound": "alu", "achieved": achieved / 1e12, "peak": valu_peak / 1e12,
+             "unit": "Tops/s", "frac": achieved / valu_peak, "traffic": None,
+             "ops_per_pixel": round(ops_px, 2), "variant": variant, "tile": list(tile)}
+        if variant == _lib.MF_VARIANT_DATA_AWARE:
+            # LDS view of the same launch: each merge output is one element
+            # read and one written (2 bytes for 8/16-bit data, 4 for 32-bit)
+            from paper_2507_19926_amd import dagen
+            st = dagen.schedule(k, tile[0], tile[1], kh=kh).stats
+            lds_es = 2 if dtype_code in (0, 1) else 4
+            r["merge_outputs_per_pixel"] = round(st["per_pixel_outputs"], 2)
+            r["sort_ces_per_pixel"] = round(st["per_pixel_sort_ces"], 2)
+            r["lds_frac"] = round(st["per_pixel_outputs"] * pixels_per_launch * 2 * lds_es / launch_s
+                                  / LDS_PEAK_BPS, 4)
+        return r
     achieved = bytes_per_launch / launch_s
     return {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK_BPS / 1e9, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_BPS, "traffic": None,
@@ -195,8 +199,9 @@ def measured_peaks(dev, stream):
 
 
 def run_extras(args, dev, stream):
-    """dtype sweep (4096^2 planes), batched plan vs per-image launches, and
-    the differentiable form's forward/backward on 32x3x512x512 float32."""
+    """dtype sweep (4096^2 planes), batched plan vs per-image launches, the
+    global-memory multi-pass form on the 30 MP frame, and the differentiable
+    form's forward/backward on 32x3x512x512 float32."""
     import numpy as np
     import torch
 
@@ -258,6 +263,35 @@ def run_extras(args, dev, stream):
                       "buckets": nb}
     plan.close()
     del xs, outs
+
+    # global-memory multi-pass form: the 30 MP frame's three planes at k = 75
+    # (and k = 25) with a 1 GiB workspace, run in slices of tiles
+    from paper_2507_19926_amd.ops import median_filter_global
+    frame = torch.from_numpy(np.ascontiguousarray(wl.rgb30_planes())).to(dev)
+    fo = torch.empty_like(frame)
+    gl = {}
+    for k in (25, 75):
+        slot, allb, tw, th, passes = _lib.global_workspace(_lib.MF_U8, k, 3, frame.shape[1], frame.shape[2])
+        budget = 1 << 30
+        median_filter_global(frame, k, out=fo, budget_bytes=budget)
+        t = _time(lambda: median_filter_global(frame, k, out=fo, budget_bytes=budget), 5, 0, stream)
+        slice_tiles = min(budget // slot, allb // slot)
+        gl[str(k)] = {"frame_ms_median": round(t * 1e3, 3), "mpix_s": round(frame.numel() / t / 1e6, 1),
+                      "tile": [tw, th], "passes": passes, "slot_bytes": slot, "workspace_bytes": min(budget, allb),
+                      "slices": -(-(allb // slot) // slice_tiles), "all_tiles_bytes": allb}
+    out["global_multipass_rgb30"] = gl
+    del frame, fo
+
+    # 3-D boxes: a 256^3 uint8 volume (uniform values), k x k x k
+    from paper_2507_19926_amd.ops import median_filter_3d
+    vol = torch.from_numpy(wl.volume_u8(256)).to(dev)
+    vo = torch.empty_like(vol)
+    b3 = {}
+    for k in (3, 5, 7, 9):
+        t = _time(lambda: median_filter_3d(vol, k, out=vo), 5, 1, stream)
+        b3[str(k)] = {"volume_ms_median": round(t * 1e3, 3), "mvoxel_s": round(vol.numel() / t / 1e6, 1)}
+    out["box3d_256cubed_u8"] = b3
+    del vol, vo
 
     # differentiable form
     x = torch.from_numpy(wl.autograd_tensor()).to(dev)
@@ -371,7 +405,7 @@ def main():
             per_k[str(k)] = {"mpix_s": round(px_step / ls / 1e6, 1),
                              "frame_ms_median": round(ls * 1e3, 4), "bound": r["bound"],
                              "frac": round(r["frac"], 4), "variant": r["variant"], "tile": r["tile"],
-                             "ops_per_pixel": r.get("merge_outputs_per_pixel", r.get("ops_per_pixel"))}
+                             "ops_per_pixel": r.get("ops_per_pixel"), "merge_outputs_per_pixel": r.get("merge_outputs_per_pixel")}
     rect = {}
     if args.sweep_steps > 0 and not args.only_headline:
         for rkw, rkh in wl.RGB30_RECT:
@@ -381,7 +415,7 @@ def main():
                                           "frame_ms_median": round(ls * 1e3, 4),
                                           "bound": r["bound"], "frac": round(r["frac"], 4),
                                           "variant": r["variant"], "tile": r["tile"],
-                                          "ops_per_pixel": r.get("merge_outputs_per_pixel", r.get("ops_per_pixel"))}
+                                          "ops_per_pixel": r.get("ops_per_pixel"), "merge_outputs_per_pixel": r.get("merge_outputs_per_pixel")}
     extras = {}
     if not args.no_extras and not args.only_headline:
         extras = run_extras(args, dev, stream)

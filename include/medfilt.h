@@ -44,7 +44,10 @@ enum mf_border { MF_BORDER_REPLICATE = 0 };
 enum mf_variant {
     MF_VARIANT_AUTO = 0,       /* the library's per-(k, dtype) choice          */
     MF_VARIANT_OBLIVIOUS = 1,  /* register-resident selection network, Sec. 4 */
-    MF_VARIANT_DATA_AWARE = 2  /* LDS-resident merges, Sec. 5                   */
+    MF_VARIANT_DATA_AWARE = 2, /* LDS-resident merges, Sec. 5                   */
+    MF_VARIANT_GLOBAL = 3      /* data-aware, lists in device memory, run in
+                                  passes of two recursion levels over slices of
+                                  tiles (the multi-pass form of Sec. 5.3)       */
 };
 
 enum mf_status {
@@ -60,6 +63,8 @@ enum mf_status {
     MF_ERR_NOMEM = -8,    /* a plan could not allocate its device tables     */
     MF_ERR_PLAN = -9,     /* plan misuse (NULL plan, shape mismatch)          */
     MF_ERR_CONFIG = -10,  /* the requested variant or tile is not available  */
+    MF_ERR_WORKSPACE = -11, /* a caller workspace below one tile's size, or
+                               not 256-byte aligned                          */
     MF_ERR_HIP = -100     /* a HIP runtime call failed; see mf_last_error()  */
 };
 
@@ -166,6 +171,60 @@ int32_t mf_query_config(int32_t dtype, int32_t k, const mf_options* opt,
  * mf_query_config. */
 int32_t mf_query_options(int32_t dtype, int32_t k, const mf_options* opt, mf_options* resolved);
 
+/* ---- Global-memory multi-pass form ------------------------------------
+ * The data-aware variant with its sorted lists in device memory instead of
+ * LDS (Section 5.3: the global-memory realisation runs the recursion in
+ * passes of two levels; Section 7.1: its memory need grows with the number
+ * of tiles in flight). Every root tile's lists take one workspace slot of
+ * slot_bytes; tiles run in slices of workspace_bytes / slot_bytes tiles, and
+ * each slice runs the passes as successive launches, the lists staying in
+ * their slots in between. The root tile is not bounded by the LDS (larger
+ * tiles share more work per pixel). Square windows, 3 <= k <= mf_max_k(),
+ * all four dtypes, results identical to median_filter. Through
+ * median_filter_ex / median_filter_planes (opt->variant = MF_VARIANT_GLOBAL,
+ * optional tile_w / tile_h) the library allocates the workspace (all tiles
+ * at once, capped at 256 MiB) and frees it in stream order; this is the one
+ * plain-path option that allocates device memory. */
+
+/* Workspace sizes for `planes` planes of H x W with root tile tile_w x
+ * tile_h (0 x 0 = the library's): *slot_bytes per tile in flight (the
+ * minimum workspace), *all_bytes for every tile at once (one slice). When
+ * resolved is not NULL it receives the variant, the root tile and, in
+ * `rows`, the number of passes. Host only. MF_ERR_K for k < 3 or even,
+ * MF_ERR_CONFIG for a tile without a schedule. */
+int32_t mf_global_workspace(int32_t dtype, int32_t k, int32_t tile_w, int32_t tile_h,
+                            int64_t planes, int64_t H, int64_t W,
+                            int64_t* slot_bytes, int64_t* all_bytes, mf_options* resolved);
+
+/* The global-memory form over `planes` planes (arguments and errors as
+ * median_filter_planes, k >= 3) with a caller workspace: a device pointer,
+ * 256-byte aligned, of workspace_bytes >= *slot_bytes (MF_ERR_WORKSPACE
+ * otherwise), not overlapping src or dst (MF_ERR_ALIAS). Allocates nothing;
+ * the workspace is in use until the work enqueued on `stream` completes. */
+int32_t median_filter_global(const void* src, void* dst, int64_t planes,
+                             int64_t plane_stride_bytes, int64_t H, int64_t W,
+                             int64_t pitch_bytes, int32_t dtype, int32_t k, int32_t border,
+                             int32_t tile_w, int32_t tile_h, void* workspace,
+                             int64_t workspace_bytes, void* stream);
+
+/* ---- 3-D boxes -----------------------------------------------------------
+ * Median of the k x k x k box around every voxel of a volume (the extension
+ * of hierarchical tiling to a third axis that Section 7.2 proposes for
+ * medical imaging): the data-aware recursion with tiles of t_w x t_h x t_z
+ * voxels, whose lists are a sorted core, faces (one per outside coordinate
+ * on an axis), edges (one per pair of outside coordinates) and raw corners.
+ * Each axis is clamped (replicate border). The volume has D slices of H rows
+ * of W elements; rows are pitch_bytes apart, slices slice_bytes apart
+ * (>= (H-1)*pitch_bytes + W*size and a multiple of the element size unless
+ * D = 1), shared by src and dst, which must not overlap. k odd in
+ * [1, mf_max_k_3d()]; k = 1 copies. Errors as median_filter_planes. */
+int32_t median_filter_3d(const void* src, void* dst, int64_t D, int64_t H, int64_t W,
+                         int64_t pitch_bytes, int64_t slice_bytes, int32_t dtype, int32_t k,
+                         int32_t border, void* stream);
+
+/* Largest k of median_filter_3d. */
+int32_t mf_max_k_3d(void);
+
 /* ---- Batched form -------------------------------------------------------
  * Many images of uneven sizes, kernel diameters and dtypes filtered by ONE
  * hipGraph launch. A plan groups its images by kernel (variant, k, root tile,
@@ -187,7 +246,9 @@ typedef struct mf_plan_s* mf_plan;
 int32_t mf_plan_create(const mf_image* imgs, int32_t n, mf_plan* plan);
 
 /* Same images (shapes, pitches, dtypes, k) with new pointers. Waits for the
- * device to be idle, then rewrites the job tables; the graph is reused. */
+ * plan's last launch to finish (an event recorded by mf_plan_launch; other
+ * work on the device is not waited for), then rewrites the job tables; the
+ * graph is reused. */
 int32_t mf_plan_update(mf_plan plan, const mf_image* imgs, int32_t n);
 
 /* One graph launch on `stream` filtering every image of the plan. */
@@ -196,7 +257,7 @@ int32_t mf_plan_launch(mf_plan plan, void* stream);
 /* Number of kernel groups and total work-groups of a plan (host only). */
 int32_t mf_plan_info(mf_plan plan, int32_t* buckets, int64_t* blocks);
 
-/* Free a plan (waits for the device to be idle). NULL is ignored. */
+/* Free a plan (waits for the plan's last launch to finish). NULL is ignored. */
 void mf_plan_destroy(mf_plan plan);
 
 /* Create a plan, launch it on `stream`, wait for it, destroy it. */

@@ -14,12 +14,12 @@ LIB_PATH = os.path.join(_PKG, "libmedfilt.so")
 
 MF_U8, MF_U16, MF_U32, MF_F32 = 0, 1, 2, 3
 MF_BORDER_REPLICATE = 0
-MF_VARIANT_AUTO, MF_VARIANT_OBLIVIOUS, MF_VARIANT_DATA_AWARE = 0, 1, 2
+MF_VARIANT_AUTO, MF_VARIANT_OBLIVIOUS, MF_VARIANT_DATA_AWARE, MF_VARIANT_GLOBAL = 0, 1, 2, 3
 
 STATUS = {
     0: "MF_OK", -1: "MF_ERR_NULL", -2: "MF_ERR_DIMS", -3: "MF_ERR_PITCH", -4: "MF_ERR_DTYPE",
     -5: "MF_ERR_K", -6: "MF_ERR_BORDER", -7: "MF_ERR_ALIAS", -8: "MF_ERR_NOMEM",
-    -9: "MF_ERR_PLAN", -10: "MF_ERR_CONFIG", -100: "MF_ERR_HIP",
+    -9: "MF_ERR_PLAN", -10: "MF_ERR_CONFIG", -11: "MF_ERR_WORKSPACE", -100: "MF_ERR_HIP",
 }
 
 
@@ -90,6 +90,15 @@ def lib():
     L.mf_plan_destroy.restype = None
     L.median_filter_batched.argtypes = [pim, i32, vp]
     L.median_filter_batched.restype = i32
+    L.mf_global_workspace.argtypes = [i32, i32, i32, i32, i64, i64, i64, ctypes.POINTER(i64),
+                                      ctypes.POINTER(i64), ctypes.POINTER(mf_options)]
+    L.mf_global_workspace.restype = i32
+    L.median_filter_global.argtypes = [vp, vp, i64, i64, i64, i64, i64, i32, i32, i32, i32, i32, vp, i64, vp]
+    L.median_filter_global.restype = i32
+    L.median_filter_3d.argtypes = [vp, vp, i64, i64, i64, i64, i64, i32, i32, i32, vp]
+    L.median_filter_3d.restype = i32
+    L.mf_max_k_3d.argtypes = []
+    L.mf_max_k_3d.restype = i32
     L.mf_list_configs.argtypes = [i32, i32, ctypes.POINTER(mf_options), i32]
     L.mf_list_configs.restype = i32
     L.mf_max_k.argtypes = []
@@ -139,6 +148,17 @@ def query_config(dtype_code: int, k: int, variant: int = MF_VARIANT_AUTO, tile=N
     check(lib().mf_query_config(dtype_code, k, ctypes.byref(o), ctypes.byref(v), ctypes.byref(tw),
                                 ctypes.byref(th)))
     return v.value, tw.value, th.value
+
+
+def global_workspace(dtype_code: int, k: int, planes: int, H: int, W: int, tile=None):
+    """(slot_bytes, all_bytes, tile_w, tile_h, passes) of the global-memory
+    form for planes of H x W."""
+    slot, allb = ctypes.c_int64(), ctypes.c_int64()
+    r = mf_options()
+    tw, th = (0, 0) if tile is None else (int(tile[0]), int(tile[1]))
+    check(lib().mf_global_workspace(dtype_code, k, tw, th, planes, H, W, ctypes.byref(slot),
+                                    ctypes.byref(allb), ctypes.byref(r)))
+    return slot.value, allb.value, r.tile_w, r.tile_h, r.rows
 
 
 def query_options(dtype_code: int, k: int, variant: int = MF_VARIANT_AUTO, tile=None):

@@ -258,6 +258,45 @@ static int32_t check_planes(const void* src, const void* dst, int64_t planes, in
     return MF_OK;
 }
 
+// Global-memory form through median_filter_ex / median_filter_planes: the
+// workspace (all tiles at once, capped at kGlobalBudget; larger images run
+// in slices) is allocated and freed in stream order around the launches.
+constexpr long long kGlobalBudget = 256LL << 20;
+
+static int32_t global_tile_option(int32_t k, const mf_options* opt, int32_t* tw, int32_t* th)
+{
+    *tw = opt ? opt->tile_w : 0;
+    *th = opt ? opt->tile_h : 0;
+    if (opt && (opt->group || opt->form || opt->rows))
+        return fail(MF_ERR_CONFIG, "the global-memory form takes only a root tile");
+    if ((*tw && (!pow2(*tw) || *tw > k)) || (*th && (!pow2(*th) || *th > k)) || *tw < 0 || *th < 0 ||
+        ((*tw == 0) != (*th == 0)))
+        return fail(MF_ERR_CONFIG, "root tile %dx%d is not a pair of powers of two <= k=%d (or 0x0)", *tw, *th, k);
+    return MF_OK;
+}
+
+static int32_t global_with_own_workspace(const void* src, void* dst, int64_t planes, int64_t plane_stride,
+                                         int64_t H, int64_t W, int64_t pitch, int32_t dtype, int32_t k,
+                                         const mf_options* opt, hipStream_t st)
+{
+    int32_t tw = 0, th = 0;
+    int32_t rc = global_tile_option(k, opt, &tw, &th);
+    if (rc) return rc;
+    long long slot = 0, all = 0;
+    int utw = 0, uth = 0;
+    if (!mf_dag_workspace(dtype, k, tw, th, planes, (int)H, (int)W, &slot, &all, &utw, &uth))
+        return fail(MF_ERR_CONFIG, "no global-memory schedule for k=%d tile %dx%d", k, tw, th);
+    long long bytes = all < kGlobalBudget ? all : kGlobalBudget;
+    if (bytes < slot) bytes = slot;
+    void* ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, (size_t)bytes, st);
+    if (e != hipSuccess) return fail(MF_ERR_NOMEM, "workspace of %lld bytes: %s", bytes, hipGetErrorString(e));
+    e = mf_dag_launch(src, dst, (int)planes, plane_stride, (int)H, (int)W, pitch, dtype, k, tw, th, ws, bytes, st);
+    hipError_t f = hipFreeAsync(ws, st);
+    if (e != hipSuccess) return hip_status(e, "global-memory kernel launch");
+    return hip_status(f, "hipFreeAsync(workspace)");
+}
+
 extern "C" {
 
 int32_t median_filter_rect(const void* src, void* dst, int64_t planes, int64_t plane_stride_bytes, int64_t H,
@@ -348,6 +387,9 @@ int32_t median_filter_planes(const void* src, void* dst, int64_t planes, int64_t
         }
         return MF_OK;
     }
+    if (opt && opt->variant == MF_VARIANT_GLOBAL)
+        return global_with_own_workspace(src, dst, planes, plane_stride_bytes, H, W, pitch_bytes, dtype, k, opt,
+                                         st);
     int32_t variant = 0, tw = 0, th = 0, group = 0;
     const OblEntry* e = nullptr;
     rc = resolve(dtype, k, opt, &variant, &tw, &th, &e, &group);
@@ -386,6 +428,16 @@ int32_t mf_query_config(int32_t dtype, int32_t k, const mf_options* opt, int32_t
         *tile_w = *tile_h = 1;
         return MF_OK;
     }
+    if (opt && opt->variant == MF_VARIANT_GLOBAL) {
+        int64_t slot = 0, all = 0;
+        mf_options r = {};
+        const int32_t rc = mf_global_workspace(dtype, k, opt->tile_w, opt->tile_h, 1, 1, 1, &slot, &all, &r);
+        if (rc) return rc;
+        *variant = r.variant;
+        *tile_w = r.tile_w;
+        *tile_h = r.tile_h;
+        return MF_OK;
+    }
     const OblEntry* e = nullptr;
     return resolve(dtype, k, opt, variant, tile_w, tile_h, &e);
 }
@@ -396,6 +448,10 @@ int32_t mf_query_options(int32_t dtype, int32_t k, const mf_options* opt, mf_opt
     if (!resolved) return fail(MF_ERR_NULL, "output pointer is NULL");
     if (!elem_size(dtype)) return fail(MF_ERR_DTYPE, "unknown dtype %d", dtype);
     if (k < 1 || k % 2 == 0 || k > kMaxK) return fail(MF_ERR_K, "k=%d must be odd in [1, %d]", k, kMaxK);
+    if (opt && opt->variant == MF_VARIANT_GLOBAL && k >= 3) {
+        int64_t slot = 0, all = 0;
+        return mf_global_workspace(dtype, k, opt->tile_w, opt->tile_h, 1, 1, 1, &slot, &all, resolved);
+    }
     mf_options r = {};
     if (k == 1) {
         r.tile_w = r.tile_h = 1;
@@ -503,6 +559,114 @@ int32_t mf_list_configs(int32_t dtype, int32_t k, mf_options* out, int32_t cap)
     return n;
 }
 
+int32_t mf_global_workspace(int32_t dtype, int32_t k, int32_t tile_w, int32_t tile_h, int64_t planes, int64_t H,
+                            int64_t W, int64_t* slot_bytes, int64_t* all_bytes, mf_options* resolved)
+{
+    g_last_error.clear();
+    if (!slot_bytes || !all_bytes) return fail(MF_ERR_NULL, "output pointer is NULL");
+    if (!elem_size(dtype)) return fail(MF_ERR_DTYPE, "unknown dtype %d", dtype);
+    if (k < 3 || k % 2 == 0 || k > kMaxK) return fail(MF_ERR_K, "k=%d must be odd in [3, %d]", k, kMaxK);
+    if (planes < 1 || H < 1 || W < 1 || H > (1 << 30) || W > (1 << 30) || planes > ((int64_t)1 << 30))
+        return fail(MF_ERR_DIMS, "planes=%lld H=%lld W=%lld outside [1, 2^30]", (long long)planes, (long long)H,
+                    (long long)W);
+    mf_options o = {};
+    o.tile_w = tile_w;
+    o.tile_h = tile_h;
+    int32_t tw = 0, th = 0;
+    int32_t rc = global_tile_option(k, &o, &tw, &th);
+    if (rc) return rc;
+    long long slot = 0, all = 0;
+    int utw = 0, uth = 0;
+    if (!mf_dag_workspace(dtype, k, tw, th, planes, (int)H, (int)W, &slot, &all, &utw, &uth))
+        return fail(MF_ERR_CONFIG, "no global-memory schedule for k=%d tile %dx%d", k, tw, th);
+    *slot_bytes = slot;
+    *all_bytes = all;
+    if (resolved) {
+        mf_options r = {};
+        r.variant = MF_VARIANT_GLOBAL;
+        r.tile_w = utw;
+        r.tile_h = uth;
+        r.rows = mf_dag_passes(dtype, k, utw, uth);
+        *resolved = r;
+    }
+    return MF_OK;
+}
+
+int32_t median_filter_global(const void* src, void* dst, int64_t planes, int64_t plane_stride_bytes, int64_t H,
+                             int64_t W, int64_t pitch_bytes, int32_t dtype, int32_t k, int32_t border,
+                             int32_t tile_w, int32_t tile_h, void* workspace, int64_t workspace_bytes, void* stream)
+{
+    g_last_error.clear();
+    int32_t rc = validate(src, dst, H, W, pitch_bytes, dtype, k, border);
+    if (rc) return rc;
+    if (k < 3) return fail(MF_ERR_K, "the global-memory form needs k >= 3");
+    rc = check_planes(src, dst, planes, &plane_stride_bytes, H, W, pitch_bytes, dtype);
+    if (rc) return rc;
+    mf_options o = {};
+    o.tile_w = tile_w;
+    o.tile_h = tile_h;
+    int32_t tw = 0, th = 0;
+    rc = global_tile_option(k, &o, &tw, &th);
+    if (rc) return rc;
+    long long slot = 0, all = 0;
+    int utw = 0, uth = 0;
+    if (!mf_dag_workspace(dtype, k, tw, th, planes, (int)H, (int)W, &slot, &all, &utw, &uth))
+        return fail(MF_ERR_CONFIG, "no global-memory schedule for k=%d tile %dx%d", k, tw, th);
+    if (!workspace) return fail(MF_ERR_NULL, "workspace is NULL");
+    if ((uintptr_t)workspace % 256)
+        return fail(MF_ERR_WORKSPACE, "workspace not aligned to 256 bytes");
+    if (workspace_bytes < slot)
+        return fail(MF_ERR_WORKSPACE, "workspace of %lld bytes is below one tile's %lld bytes",
+                    (long long)workspace_bytes, slot);
+    const int s = elem_size(dtype);
+    const uintptr_t img = (uintptr_t)((planes - 1) * plane_stride_bytes + (H - 1) * pitch_bytes + W * s);
+    const uintptr_t a0 = (uintptr_t)workspace, sa = (uintptr_t)src, da = (uintptr_t)dst;
+    const uintptr_t wl = (uintptr_t)workspace_bytes;
+    if ((a0 < sa + img && sa < a0 + wl) || (a0 < da + img && da < a0 + wl))
+        return fail(MF_ERR_ALIAS, "workspace overlaps src or dst");
+    return hip_status(mf_dag_launch(src, dst, (int)planes, plane_stride_bytes, (int)H, (int)W, pitch_bytes, dtype,
+                                    k, tw, th, workspace, workspace_bytes, (hipStream_t)stream),
+                      "global-memory kernel launch");
+}
+
+int32_t mf_max_k_3d(void) { return mf_da3_max_k(); }
+
+int32_t median_filter_3d(const void* src, void* dst, int64_t D, int64_t H, int64_t W, int64_t pitch_bytes,
+                         int64_t slice_bytes, int32_t dtype, int32_t k, int32_t border, void* stream)
+{
+    g_last_error.clear();
+    // the single-plane checks (k = 1 stands in for the box in the k test)
+    int32_t rc = validate(src, dst, H, W, pitch_bytes, dtype, 1, border);
+    if (rc) return rc;
+    const int s = elem_size(dtype);
+    if (D < 1 || D > (1 << 30)) return fail(MF_ERR_DIMS, "D=%lld outside [1, 2^30]", (long long)D);
+    if (k < 1 || k % 2 == 0 || k > mf_da3_max_k())
+        return fail(MF_ERR_K, "k=%d must be odd in [1, %d] for a 3-D box", k, mf_da3_max_k());
+    const int64_t plane = (H - 1) * pitch_bytes + W * s;
+    if (D > 1 && (slice_bytes < plane || slice_bytes % s || slice_bytes > ((int64_t)1 << 46)))
+        return fail(MF_ERR_PITCH, "slice stride %lld: slices of %lld bytes would overlap or misalign",
+                    (long long)slice_bytes, (long long)plane);
+    if (D == 1) slice_bytes = plane;
+    const uintptr_t a0 = (uintptr_t)src, b0 = (uintptr_t)dst;
+    const uintptr_t len = (uintptr_t)((D - 1) * slice_bytes + plane);
+    if (a0 < b0 + len && b0 < a0 + len) return fail(MF_ERR_ALIAS, "src and dst volumes overlap");
+    if (!mf_da3_supports(dtype, k) && k != 1)
+        return fail(MF_ERR_CONFIG, "no 3-D schedule for k=%d", k);
+    hipStream_t st = (hipStream_t)stream;
+    if (k == 1) {
+        for (int64_t z = 0; z < D; ++z) {
+            rc = hip_status(hipMemcpy2DAsync((char*)dst + z * slice_bytes, pitch_bytes,
+                                             (const char*)src + z * slice_bytes, pitch_bytes, W * s, H,
+                                             hipMemcpyDeviceToDevice, st),
+                            "hipMemcpy2DAsync");
+            if (rc) return rc;
+        }
+        return MF_OK;
+    }
+    return hip_status(mf_da3_launch(src, dst, (int)D, (int)H, (int)W, pitch_bytes, slice_bytes, dtype, k, st),
+                      "3-D kernel launch");
+}
+
 int32_t mf_max_k(void) { return kMaxK; }
 
 const char* mf_status_string(int32_t status)
@@ -519,6 +683,7 @@ const char* mf_status_string(int32_t status)
     case MF_ERR_NOMEM: return "out of device memory";
     case MF_ERR_PLAN: return "bad plan";
     case MF_ERR_CONFIG: return "configuration not available";
+    case MF_ERR_WORKSPACE: return "workspace too small or misaligned";
     case MF_ERR_HIP: return "HIP runtime error";
     default: return "unknown status";
     }

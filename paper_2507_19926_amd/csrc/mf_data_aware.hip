@@ -1,25 +1,27 @@
 // Data-aware hierarchical-tiling median filter for gfx950 (Section 5 of
 // Sugy 2025, re-designed around LDS residency).
 //
-// One work-group owns one root tile. Its footprint is read from HBM into LDS
-// once; then a precomputed schedule of two-way merges runs entirely in LDS:
-// column sorts, extra-row sorts and corner sorts as binary reductions from
-// single values, the core's multi-way merge as a binary reduction of sorted
-// columns, and every split's core and row/column extensions level by level
-// (Sections 3.3-3.4, 5.1). The paper's global-memory multi-pass structure is
-// replaced by this LDS-resident sequence of rounds separated by barriers.
+// One work-group owns one root tile (or G small ones, one per lane group).
+// Its footprint is read from HBM into LDS once; then a precomputed schedule
+// runs entirely in LDS, round after round with a work-group barrier between
+// rounds: column, extra-row and corner sorts as per-lane sorting networks
+// over footprint values in registers (Section 5.1), the core's multi-way
+// merge as a binary reduction of two-way merges of sorted columns, and every
+// split's core and row/column extensions level by level (Sections 3.3-3.4).
+// The paper's global-memory multi-pass structure is replaced by this
+// LDS-resident sequence of rounds.
 //
 // The window may be rectangular (k columns by kh rows, both odd): the
 // schedule encodes the recursion for its footprint, the kernel only needs the
 // two radii to place the footprint.
 //
-// Each round is a list of merge-path chunks: a lane finds the chunk's start in
-// its two sorted input windows with a co-rank binary search and then merges
-// up to 16 outputs sequentially. A work-group holds T root tiles (T arenas)
-// that share the schedule; a lane runs its chunk for the T tiles side by side,
-// so T independent chains of LDS reads are in flight per lane. Only the ranks
-// some later step can read are produced (forgetting and pruning as output
-// windows).
+// A merge is cut into chunks of one length per round: a lane finds its
+// chunk's start in the two sorted input windows with a co-rank binary search
+// of a fixed number of halving steps and then takes that many sequential
+// merge steps, each a compare, a min, an LDS store and two LDS loads at
+// addresses derived from one index (every stored list ends with a sentinel,
+// so no step tests for an exhausted input). Only the ranks some later step
+// can read are produced (forgetting and pruning as output windows).
 //
 // 8/16-bit data is held as 16-bit LDS elements, 32-bit data (uint32, float32
 // through an order-preserving key) as 32-bit elements.
@@ -30,10 +32,14 @@
 
 namespace {
 
-// one schedule: window k x kh (columns x rows), LDS element size, root tile,
-// tiles per lane, lane groups per work-group
+// one schedule: window k x kh (columns x rows; k x kh x kz for a 3-D box,
+// kz = 1 for planes), element size, root tile tw x th (x tz), tiles per lane
+// (always 1), lane groups per work-group, memory (0: LDS
+// arena, 1: device workspace of the global form), blob offsets of the items,
+// round boundaries, per-round chunk lengths, per-round recursion levels and
+// median offsets, arena elements
 struct DaEntry {
-    int k, kh, es, tw, th, tiles, groups, c_off, nchunks, r_off, nrounds, o_off, arena;
+    int k, kh, kz, es, tw, th, tz, tiles, groups, mem, c_off, nchunks, r_off, nrounds, l_off, p_off, o_off, arena;
 };
 
 const DaEntry kDaTable[] = {MF_DA_TABLE_ENTRIES};
@@ -57,34 +63,109 @@ __device__ __forceinline__ uint32_t mf_da_key_to_f32(uint32_t k)
     return k ^ ((uint32_t)((int32_t)~k >> 31) | 0x80000000u);
 }
 
-// G*T root tiles (bx*G*T + t, by) of one image, schedule `a`, G = a.groups.
-// The work-group's lanes form G groups of kDaThreads/G lanes; group g owns
-// tiles g*T .. g*T+T-1 and runs every round's chunks for them (small tiles,
-// whose rounds have few chunks, fill the work-group this way). LDS holds G*T
-// arenas of `arena` elements each; a lane executes each of its chunks for its
-// T tiles side by side, so the T co-rank searches and loads are independent
-// and their latencies overlap.
-template <class E, int T>
-__device__ __forceinline__ void
-mf_da_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, int H, int W,
-            long long pitch, int dtype, const MfDaArgs& a, int bx, int by)
+// Batcher's odd-even merge sort of N (a power of two) values in registers,
+// fully unrolled: every index is a compile-time constant.
+template <int N>
+__device__ __forceinline__ void mf_da_sortnet(uint32_t* v)
 {
-    extern __shared__ __align__(16) unsigned char mf_da_lds[];
-    E* lds = reinterpret_cast<E*>(mf_da_lds);
+#pragma unroll
+    for (int p = 1; p < N; p <<= 1)
+#pragma unroll
+        for (int k = p; k >= 1; k >>= 1)
+#pragma unroll
+            for (int j = k % p; j + k < N; j += 2 * k)
+#pragma unroll
+                for (int i = 0; i < k; ++i)
+                    if (i + j + k < N && (i + j) / (2 * p) == (i + j + k) / (2 * p)) {
+                        const uint32_t x = v[i + j], y = v[i + j + k];
+                        v[i + j] = min(x, y);
+                        v[i + j + k] = max(x, y);
+                    }
+}
+
+// Sort item: the n footprint values at base + i*stride (padded to N with the
+// sentinel), sorted by the network; ranks [lo, lo+cnt) are written from
+// out, followed by the sentinel.
+template <class E, int N>
+__device__ __forceinline__ void mf_da_sort(E* __restrict__ gl, const uint4 d)
+{
+    constexpr uint32_t kMask = (1u << 18) - 1;
+    constexpr uint32_t kMax = (uint32_t)(E)~(E)0;
+    const int base = (int)(d.x & kMask), n = (int)(d.x >> 18);
+    const int stride = (int)(d.y & kMask), lo = (int)(d.y >> 18);
+    const int oo = (int)(d.z & kMask), cnt = (int)(d.z >> 18);
+    uint32_t v[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = i < n ? (uint32_t)gl[base + i * stride] : kMax;
+    mf_da_sortnet<N>(v);
+    E* out = gl + oo - lo;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        if (i >= lo && i < lo + cnt) out[i] = (E)v[i];
+    gl[oo + cnt] = (E)kMax;
+}
+
+// Merge chunk: co-rank of rank r0 in (A window, B window), A first on ties,
+// by `steps` halving steps; then C merge steps. The element after each input
+// window is the sentinel or a list element ranked after every output this
+// chunk must produce, so no step tests for an exhausted input; steps past the
+// chunk's needed outputs write into the list's own padding. CLAMP keeps the A
+// index at the window end: needed when data can equal the sentinel value
+// (16-bit and 32-bit data), not for 8-bit data held in 16-bit elements.
+template <class E, bool CLAMP>
+__device__ __forceinline__ void mf_da_merge(E* __restrict__ gl, const uint4 d, const int C)
+{
+    constexpr uint32_t kMask = (1u << 18) - 1;
+    constexpr uint32_t kMax = (uint32_t)(E)~(E)0;
+    const E* __restrict__ A = gl + (d.x & kMask);
+    const E* __restrict__ B = gl + (d.y & kMask);
+    const int na = (int)(d.x >> 18), nb = (int)(d.y >> 18);
+    E* __restrict__ out = gl + (d.z & kMask);
+    const int nvalid = (int)(d.z >> 18);
+    const int r0 = (int)(d.w & kMask), steps = (int)((d.w >> 18) & 15u);
+    const int hi = min(r0, na);
+    int pos = max(0, r0 - nb);
+    for (int s = steps - 1; s >= 0; --s) {
+        const int t = pos + (1 << s) - 1;
+        const int tc = min(t, hi - 1);
+        const uint32_t av = A[tc], bv = B[r0 - 1 - tc];
+        pos = (t < hi && av <= bv) ? t + 1 : pos;
+    }
+    int ia = pos;
+    uint32_t a = A[ia], b = B[r0 - ia];
+    const E* __restrict__ Bq = B + r0 + 1;     // b of step q is Bq[q - ia]
+    for (int q0 = 0; q0 < C; q0 += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool take = a <= b;
+            out[q0 + u] = (E)min(a, b);
+            ia += take ? 1 : 0;
+            if constexpr (CLAMP) ia = min(ia, na);
+            a = A[ia];
+            b = Bq[q0 + u - ia];
+        }
+    }
+    if (d.w & (1u << 22)) out[nvalid] = (E)kMax;
+}
+
+// Footprints of G root tiles (bx*G + t, by) -> arenas gl + t*arena, after
+// the guard, row-major fw x fh (replicate border); the guard's last slot of
+// each arena holds the sentinel. Work-group-wide; no barrier.
+template <class E>
+__device__ __forceinline__ void
+mf_da_load(E* __restrict__ gl, const unsigned char* __restrict__ src, int H, int W, long long pitch, int dtype,
+           const MfDaArgs& a, int G, int bx, int by)
+{
+    constexpr uint32_t kMax = (uint32_t)(E)~(E)0;
     const int tw = a.tw, th = a.th, arena = a.arena;
-    const uint32_t* __restrict__ blob = a.blob;
     const int rx = (a.k - 1) / 2, ry = (a.kh - 1) / 2;
     const int fw = a.k + tw - 1, fh = a.kh + th - 1;
     const int Y0 = by * th;
-    const int G = a.groups, L = kDaThreads / G, NT = G * T;
-    const int gi = threadIdx.x / L, lt = threadIdx.x - gi * L;
-
-    // footprints -> LDS, row-major fw x fh per tile (replicate border)
-    for (int i = threadIdx.x; i < NT * fw * fh; i += kDaThreads) {
+    for (int i = threadIdx.x; i < G * fw * fh; i += kDaThreads) {
         const int t = i / (fw * fh), e = i - t * fw * fh;
         const int y = e / fw, x = e - y * fw;
         const int gy = min(max(Y0 - ry + y, 0), H - 1);
-        const int gx = min(max((bx * NT + t) * tw - rx + x, 0), W - 1);
+        const int gx = min(max((bx * G + t) * tw - rx + x, 0), W - 1);
         const unsigned char* row = src + (long long)gy * pitch;
         uint32_t v;
         if (dtype == MF_U8) v = row[gx];
@@ -93,172 +174,209 @@ mf_da_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
             v = ((const uint32_t*)row)[gx];
             if (dtype == MF_F32) v = mf_da_f32_to_key(v);
         }
-        lds[t * arena + e] = (E)v;
+        gl[t * arena + MF_DA_GUARD + e] = (E)v;
     }
-    __syncthreads();
+    if (threadIdx.x < G) gl[threadIdx.x * arena + MF_DA_GUARD - 1] = (E)kMax;
+}
 
-    const uint4* __restrict__ chunks = reinterpret_cast<const uint4*>(blob + a.c_off);
+// Rounds [r0, r1) of the schedule on one arena, lane lt of the L lanes that
+// share it; a work-group barrier after every round.
+template <class E, bool CLAMP>
+__device__ __forceinline__ void mf_da_rounds(E* __restrict__ gl, const MfDaArgs& a, int r0, int r1, int lt, int L)
+{
+    const uint32_t* __restrict__ blob = a.blob;
+    const uint4* __restrict__ items = reinterpret_cast<const uint4*>(blob + a.c_off);
     const uint32_t* __restrict__ rounds = blob + a.r_off;
-    constexpr uint32_t kMask = (1u << 18) - 1;
-    E* const gl = lds + gi * T * arena;     // this lane group's T arenas
-    for (int rd = 0; rd < a.nrounds; ++rd) {
+    const uint32_t* __restrict__ clen = blob + a.l_off;
+    for (int rd = r0; rd < r1; ++rd) {
         const int c1 = (int)rounds[rd + 1];
-        int c = (int)rounds[rd] + lt;
-        uint4 d = c < c1 ? chunks[c] : make_uint4(0, 0, 0, 0);
-        while (c < c1) {
-            const int cn = c + L;
-            const uint4 dn = cn < c1 ? chunks[cn] : make_uint4(0, 0, 0, 0);   // prefetch
-            const int ao = (int)(d.x & kMask), bo = (int)(d.y & kMask), oo = (int)(d.z & kMask);
-            const int na = (int)(d.x >> 18), nb = (int)(d.y >> 18), n = (int)(d.z >> 18);
-            const int r0 = (int)d.w;
-            // co-rank: number of A elements among the first r0 outputs (A first
-            // on ties); the same bounds for every tile, so one trip count
-            int lo[T], hi[T];
-#pragma unroll
-            for (int t = 0; t < T; ++t) {
-                lo[t] = max(0, r0 - nb);
-                hi[t] = min(r0, na);
-            }
-            for (bool any = true; any;) {
-                any = false;
-#pragma unroll
-                for (int t = 0; t < T; ++t) {
-                    if (lo[t] < hi[t]) {
-                        const E* A = gl + t * arena + ao;
-                        const E* B = gl + t * arena + bo;
-                        const int i = (lo[t] + hi[t]) >> 1;
-                        if (A[i] <= B[r0 - i - 1]) lo[t] = i + 1;
-                        else hi[t] = i;
-                    }
-                    any |= lo[t] < hi[t];
-                }
-            }
-            // sequential two-pointer merge of n outputs, the T tiles side by
-            // side (T independent chains of dependent LDS reads)
-            if constexpr (sizeof(E) == 2) {
-                // 16-bit elements in 32-bit registers: an exhausted side
-                // holds 0x10000, above every element, so one compare picks
-                // the side (A first on ties). pa / pb are the arena indices
-                // of the heads, ea / eb one past the windows.
-                constexpr uint32_t kDone = 0x10000u;
-                int pa[T], pb[T];
-                uint32_t va[T], vb[T];
-                const int ea = ao + na, eb = bo + nb;
-#pragma unroll
-                for (int t = 0; t < T; ++t) {
-                    pa[t] = ao + lo[t];
-                    pb[t] = bo + r0 - lo[t];
-                    va[t] = pa[t] < ea ? (uint32_t)gl[t * arena + pa[t]] : kDone;
-                    vb[t] = pb[t] < eb ? (uint32_t)gl[t * arena + pb[t]] : kDone;
-                }
-                for (int q = 0; q < n; ++q) {
-#pragma unroll
-                    for (int t = 0; t < T; ++t) {
-                        const bool takeA = va[t] <= vb[t];
-                        gl[t * arena + oo + q] = (E)min(va[t], vb[t]);
-                        pa[t] += takeA ? 1 : 0;
-                        pb[t] += takeA ? 0 : 1;
-                        const int p = takeA ? pa[t] : pb[t];
-                        const int e = takeA ? ea : eb;
-                        // index clamped into the arena; past the window the
-                        // value is replaced by kDone
-                        const uint32_t nv = (uint32_t)gl[t * arena + min(p, arena - 1)];
-                        const uint32_t nk = p < e ? nv : kDone;
-                        va[t] = takeA ? nk : va[t];
-                        vb[t] = takeA ? vb[t] : nk;
-                    }
+        const int C = (int)clen[rd];
+        for (int c = (int)rounds[rd] + lt; c < c1; c += L) {
+            const uint4 d = items[c];
+            if (d.w & 0x80000000u) {
+                switch (d.w & 63u) {
+                case 1: mf_da_sort<E, 1>(gl, d); break;
+                case 2: mf_da_sort<E, 2>(gl, d); break;
+                case 4: mf_da_sort<E, 4>(gl, d); break;
+                case 8: mf_da_sort<E, 8>(gl, d); break;
+                case 16: mf_da_sort<E, 16>(gl, d); break;
+                default: mf_da_sort<E, 32>(gl, d); break;
                 }
             } else {
-                int ii[T], jj[T];
-                E va[T], vb[T];
-#pragma unroll
-                for (int t = 0; t < T; ++t) {
-                    const E* A = gl + t * arena + ao;
-                    const E* B = gl + t * arena + bo;
-                    ii[t] = lo[t];
-                    jj[t] = r0 - lo[t];
-                    va[t] = ii[t] < na ? A[ii[t]] : (E)0;
-                    vb[t] = jj[t] < nb ? B[jj[t]] : (E)0;
-                }
-                for (int q = 0; q < n; ++q) {
-#pragma unroll
-                    for (int t = 0; t < T; ++t) {
-                        const bool takeA = (ii[t] < na) && (jj[t] >= nb || va[t] <= vb[t]);
-                        gl[t * arena + oo + q] = takeA ? va[t] : vb[t];
-                        ii[t] += takeA ? 1 : 0;
-                        jj[t] += takeA ? 0 : 1;
-                        // one read refills the side just consumed; the index is
-                        // clamped into the arena (an exhausted side is never used)
-                        const int src_i = takeA ? ao + ii[t] : bo + jj[t];
-                        const E nv = gl[t * arena + min(src_i, arena - 1)];
-                        va[t] = takeA ? nv : va[t];
-                        vb[t] = takeA ? vb[t] : nv;
-                    }
-                }
+                mf_da_merge<E, CLAMP>(gl, d, C);
             }
-            d = dn;
-            c = cn;
         }
         __syncthreads();
     }
+}
 
-    const uint32_t* outs = blob + a.o_off;
-    for (int p = threadIdx.x; p < NT * tw * th; p += kDaThreads) {
+// Medians of G root tiles (bx*G + t, by) from their arenas to dst.
+template <class E>
+__device__ __forceinline__ void
+mf_da_store(const E* __restrict__ gl, unsigned char* __restrict__ dst, int H, int W, long long pitch, int dtype,
+            const MfDaArgs& a, int G, int bx, int by)
+{
+    const int tw = a.tw, th = a.th, arena = a.arena;
+    const int Y0 = by * th;
+    const uint32_t* outs = a.blob + a.o_off;
+    for (int p = threadIdx.x; p < G * tw * th; p += kDaThreads) {
         const int t = p / (tw * th), e = p - t * tw * th;
-        const int y = Y0 + e / tw, x = (bx * NT + t) * tw + e % tw;
+        const int y = Y0 + e / tw, x = (bx * G + t) * tw + e % tw;
         if (y >= H || x >= W) continue;
         unsigned char* row = dst + (long long)y * pitch;
-        const uint32_t v = (uint32_t)lds[t * arena + outs[e]];
+        const uint32_t v = (uint32_t)gl[t * arena + outs[e]];
         if (dtype == MF_U8) row[x] = (unsigned char)v;
         else if (dtype == MF_U16) ((uint16_t*)row)[x] = (uint16_t)v;
         else ((uint32_t*)row)[x] = (dtype == MF_F32) ? mf_da_key_to_f32(v) : v;
     }
 }
 
-template <class E, int T>
+// G root tiles (bx*G + g, by) of one image, schedule `a`, G = a.groups, in
+// LDS. The work-group's lanes form G groups of kDaThreads/G lanes; group g
+// owns tile g and runs every round's items for it (small tiles, whose rounds
+// have few items, fill the work-group this way). LDS holds G arenas of
+// `arena` elements.
+template <class E, bool CLAMP>
+__device__ __forceinline__ void
+mf_da_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, int H, int W,
+            long long pitch, int dtype, const MfDaArgs& a, int bx, int by)
+{
+    extern __shared__ __align__(16) unsigned char mf_da_lds[];
+    E* lds = reinterpret_cast<E*>(mf_da_lds);
+    const int G = a.groups, L = kDaThreads / G;
+    const int gi = threadIdx.x / L, lt = threadIdx.x - gi * L;
+    mf_da_load<E>(lds, src, H, W, pitch, dtype, a, G, bx, by);
+    __syncthreads();
+    mf_da_rounds<E, CLAMP>(lds + gi * a.arena, a, 0, a.nrounds, lt, L);
+    mf_da_store<E>(lds, dst, H, W, pitch, dtype, a, G, bx, by);
+}
+
+template <class E, bool CLAMP>
 __global__ void __launch_bounds__(kDaThreads)
 mf_da_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, int H, int W,
              long long pitch, long long plane_stride, int dtype, MfDaArgs a, int ntx)
 {
     const long long po = (long long)blockIdx.y * plane_stride;   // plane = blockIdx.y
-    mf_da_block<E, T>(src + po, dst + po, H, W, pitch, dtype, a, blockIdx.x % ntx, blockIdx.x / ntx);
+    mf_da_block<E, CLAMP>(src + po, dst + po, H, W, pitch, dtype, a, blockIdx.x % ntx, blockIdx.x / ntx);
 }
 
-// Batched form: blocks of every image of a job table (same k, tile, tiles per
-// work-group and element size), image found by binary search over first
-// block indices.
-template <class E, int T>
+// Batched form, persistent: a resident-sized grid walks the nblocks blocks
+// of every image of a job table (same k, tile and element size), work-group
+// w taking blocks w, w + gridDim.x, ...; image found by binary search over
+// the first block indices.
+template <class E, bool CLAMP>
 __global__ void __launch_bounds__(kDaThreads)
-mf_da_kernel_batched(const MfJob* __restrict__ jobs, int njobs, MfDaArgs a)
+mf_da_kernel_batched(const MfJob* __restrict__ jobs, int njobs, int nblocks, MfDaArgs a)
 {
-    const int b = blockIdx.x;
-    int lo = 0, hi = njobs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].block_begin <= b) lo = mid;
-        else hi = mid - 1;
+    for (int b = blockIdx.x; b < nblocks; b += gridDim.x) {
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].block_begin <= b) lo = mid;
+            else hi = mid - 1;
+        }
+        const MfJob j = jobs[lo];
+        const int lb = b - j.block_begin;
+        mf_da_block<E, CLAMP>(j.src, j.dst, j.H, j.W, j.pitch, j.dtype, a, lb % j.nbx, lb / j.nbx);
+        __syncthreads();   // the next block reuses the LDS
     }
-    const MfJob j = jobs[lo];
-    const int lb = b - j.block_begin;
-    mf_da_block<E, T>(j.src, j.dst, j.H, j.W, j.pitch, j.dtype, a, lb % j.nbx, lb / j.nbx);
+}
+
+// Global-memory multi-pass form (Section 5.3: passes of two recursion levels
+// over a slice of tiles, lists in device memory). One work-group per tile
+// of the slice [tile0, tile0 + gridDim.x); work-group b keeps the tile's
+// lists in workspace slot b (arena elements) from pass to pass. A launch
+// runs rounds [r0, r1): the first pass also loads the footprint, the last
+// one stores the medians. Tiles are numbered plane by plane, row-major.
+template <class E, bool CLAMP>
+__global__ void __launch_bounds__(kDaThreads)
+mf_dag_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, int H, int W,
+              long long pitch, long long plane_stride, int dtype, MfDaArgs a, int ntx, int tiles_per_plane,
+              long long tile0, E* __restrict__ ws, int r0, int r1, int first, int last)
+{
+    const long long tile = tile0 + blockIdx.x;
+    const long long plane = tile / tiles_per_plane;
+    const int t = (int)(tile - plane * tiles_per_plane);
+    const int bx = t % ntx, by = t / ntx;
+    E* gl = ws + (size_t)blockIdx.x * (size_t)a.arena;
+    if (first) {
+        mf_da_load<E>(gl, src + plane * plane_stride, H, W, pitch, dtype, a, 1, bx, by);
+        __syncthreads();
+    }
+    mf_da_rounds<E, CLAMP>(gl, a, r0, r1, threadIdx.x, kDaThreads);
+    if (last) mf_da_store<E>(gl, dst + plane * plane_stride, H, W, pitch, dtype, a, 1, bx, by);
+}
+
+// 3-D box median (the hierarchical recursion with a third axis): one root
+// tile of tw x th x tz voxels per work-group, its (k+tw-1) x (kh+th-1) x
+// (kz+tz-1) footprint in LDS (each axis clamped), the schedule's rounds, and
+// the tile's medians stored. Rows are pitch bytes apart, slices slice bytes
+// apart; work-group b is tile (b % ntx, b / ntx % nty, b / (ntx*nty)).
+template <class E, bool CLAMP>
+__global__ void __launch_bounds__(kDaThreads)
+mf_da3_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, int D, int H, int W,
+              long long pitch, long long slice, int dtype, MfDaArgs a, int ntx, int nty)
+{
+    extern __shared__ __align__(16) unsigned char mf_da_lds[];
+    constexpr uint32_t kMax = (uint32_t)(E)~(E)0;
+    E* lds = reinterpret_cast<E*>(mf_da_lds);
+    const int b = blockIdx.x;
+    const int bx = b % ntx, by = (b / ntx) % nty, bz = b / (ntx * nty);
+    const int fw = a.k + a.tw - 1, fh = a.kh + a.th - 1, fd = a.kz + a.tz - 1;
+    const int rx = (a.k - 1) / 2, ry = (a.kh - 1) / 2, rz = (a.kz - 1) / 2;
+    const int X0 = bx * a.tw - rx, Y0 = by * a.th - ry, Z0 = bz * a.tz - rz;
+    for (int i = threadIdx.x; i < fw * fh * fd; i += kDaThreads) {
+        const int z = i / (fw * fh), r = i - z * fw * fh;
+        const int y = r / fw, x = r - y * fw;
+        const int gz = min(max(Z0 + z, 0), D - 1), gy = min(max(Y0 + y, 0), H - 1);
+        const int gx = min(max(X0 + x, 0), W - 1);
+        const unsigned char* row = src + (long long)gz * slice + (long long)gy * pitch;
+        uint32_t v;
+        if (dtype == MF_U8) v = row[gx];
+        else if (dtype == MF_U16) v = ((const uint16_t*)row)[gx];
+        else {
+            v = ((const uint32_t*)row)[gx];
+            if (dtype == MF_F32) v = mf_da_f32_to_key(v);
+        }
+        lds[MF_DA_GUARD + i] = (E)v;
+    }
+    if (threadIdx.x == 0) lds[MF_DA_GUARD - 1] = (E)kMax;
+    __syncthreads();
+    mf_da_rounds<E, CLAMP>(lds, a, 0, a.nrounds, threadIdx.x, kDaThreads);
+    const uint32_t* outs = a.blob + a.o_off;
+    const int tv = a.tw * a.th * a.tz;
+    for (int p = threadIdx.x; p < tv; p += kDaThreads) {
+        const int pz = p / (a.tw * a.th), r = p - pz * a.tw * a.th;
+        const int py = r / a.tw, px = r - py * a.tw;
+        const int z = bz * a.tz + pz, y = by * a.th + py, x = bx * a.tw + px;
+        if (z >= D || y >= H || x >= W) continue;
+        unsigned char* row = dst + (long long)z * slice + (long long)y * pitch;
+        const uint32_t v = (uint32_t)lds[outs[p]];
+        if (dtype == MF_U8) row[x] = (unsigned char)v;
+        else if (dtype == MF_U16) ((uint16_t*)row)[x] = (uint16_t)v;
+        else ((uint32_t*)row)[x] = (dtype == MF_F32) ? mf_da_key_to_f32(v) : v;
+    }
 }
 
 namespace {
 
-// kernel pointers by (element size, tiles per work-group)
-template <class E>
-const void* da_kernel(int T, bool batched)
+// kernel pointers by value class: 16-bit elements for 8-bit data (no clamp:
+// a value never equals the sentinel) and for 16-bit data, 32-bit elements
+// for 32-bit data
+const void* da3_kernel_for_dtype(int dtype)
 {
-    switch (T) {
-    case 1: return batched ? (const void*)mf_da_kernel_batched<E, 1> : (const void*)mf_da_kernel<E, 1>;
-    case 2: return batched ? (const void*)mf_da_kernel_batched<E, 2> : (const void*)mf_da_kernel<E, 2>;
-    default: return batched ? (const void*)mf_da_kernel_batched<E, 4> : (const void*)mf_da_kernel<E, 4>;
-    }
+    if (dtype == MF_U8) return (const void*)mf_da3_kernel<uint16_t, false>;
+    if (dtype == MF_U16) return (const void*)mf_da3_kernel<uint16_t, true>;
+    return (const void*)mf_da3_kernel<uint32_t, true>;
 }
 
-const void* da_kernel_for(const DaEntry* e, bool batched)
+const void* da_kernel_for_dtype(int dtype, bool batched)
 {
-    return e->es == 2 ? da_kernel<uint16_t>(e->tiles, batched) : da_kernel<uint32_t>(e->tiles, batched);
+    if (dtype == MF_U8)
+        return batched ? (const void*)mf_da_kernel_batched<uint16_t, false> : (const void*)mf_da_kernel<uint16_t, false>;
+    if (dtype == MF_U16)
+        return batched ? (const void*)mf_da_kernel_batched<uint16_t, true> : (const void*)mf_da_kernel<uint16_t, true>;
+    return batched ? (const void*)mf_da_kernel_batched<uint32_t, true> : (const void*)mf_da_kernel<uint32_t, true>;
 }
 
 }  // namespace
@@ -272,8 +390,8 @@ const DaEntry* da_find(int dtype, int k, int tw, int th, int group, int kh = 0)
     if (kh == 0) kh = k;
     for (int i = 0; i < kDaCount; ++i) {
         const DaEntry& e = kDaTable[i];
-        if (e.k == k && e.kh == kh && e.es == es && (tw == 0 || e.tw == tw) && (th == 0 || e.th == th) &&
-            (group == 0 || e.tiles == group))
+        if (e.mem == 0 && e.kz == 1 && e.k == k && e.kh == kh && e.es == es && (tw == 0 || e.tw == tw) &&
+            (th == 0 || e.th == th) && (group == 0 || e.tiles == group))
             return &e;
     }
     return nullptr;
@@ -297,13 +415,12 @@ hipError_t da_blob(const uint32_t** out)
         void* p = nullptr;
         e = hipGetSymbolAddress(&p, HIP_SYMBOL(mf_da_blob));
         if (e != hipSuccess) return e;
-        for (int es = 2; es <= 4; es += 2)
-            for (int T = 1; T <= 4; T *= 2)
-                for (int bt = 0; bt < 2; ++bt) {
-                    const void* fn = es == 2 ? da_kernel<uint16_t>(T, bt) : da_kernel<uint32_t>(T, bt);
-                    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-                    if (e != hipSuccess) return e;
-                }
+        for (int dt = MF_U8; dt <= MF_U32; ++dt)
+            for (int bt = 0; bt < 3; ++bt) {
+                const void* fn = bt == 2 ? da3_kernel_for_dtype(dt) : da_kernel_for_dtype(dt, bt != 0);
+                e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                if (e != hipSuccess) return e;
+            }
         g_da_blob_dev[dev] = (const uint32_t*)p;
     }
     *out = g_da_blob_dev[dev];
@@ -333,7 +450,7 @@ int mf_da_list(int dtype, int k, int* tw, int* th, int* group, int cap)
     int n = 0;
     for (int i = 0; i < kDaCount; ++i) {
         const DaEntry& e = kDaTable[i];
-        if (e.k != k || e.kh != k || e.es != es) continue;
+        if (e.mem != 0 || e.kz != 1 || e.k != k || e.kh != k || e.es != es) continue;
         if (n < cap) {
             tw[n] = e.tw;
             th[n] = e.th;
@@ -350,11 +467,14 @@ static MfDaArgs da_args(const DaEntry* e, const uint32_t* blob)
     a.blob = blob;
     a.k = e->k;
     a.kh = e->kh;
+    a.kz = e->kz;
+    a.tz = e->tz;
     a.tw = e->tw;
     a.th = e->th;
     a.c_off = e->c_off;
     a.r_off = e->r_off;
     a.nrounds = e->nrounds;
+    a.l_off = e->l_off;
     a.o_off = e->o_off;
     a.arena = e->arena;
     a.groups = e->groups;
@@ -379,7 +499,7 @@ hipError_t mf_da_launch(const void* src, void* dst, int planes, long long plane_
         const unsigned char* s8 = (const unsigned char*)src + p0 * plane_stride;
         unsigned char* d8 = (unsigned char*)dst + p0 * plane_stride;
         void* args[] = {&s8, &d8, &H, &W, &pitch, &plane_stride, &dtype, &a, (void*)&ntx};
-        err = hipLaunchKernel(da_kernel_for(e, false), dim3(ntx * nty, np), dim3(kDaThreads), args, lds, stream);
+        err = hipLaunchKernel(da_kernel_for_dtype(dtype, false), dim3(ntx * nty, np), dim3(kDaThreads), args, lds, stream);
         if (err != hipSuccess) return err;
     }
     return hipSuccess;
@@ -393,10 +513,162 @@ hipError_t mf_da_batched(int dtype, int k, int tw, int th, int group, MfBatchedK
     hipError_t err = da_blob(&blob);
     if (err != hipSuccess) return err;
     *args = da_args(e, blob);
-    kern->fn = da_kernel_for(e, true);
+    kern->fn = da_kernel_for_dtype(dtype, true);
     kern->threads = kDaThreads;
     kern->lds = (size_t)e->arena * e->es * e->tiles * e->groups;
     kern->bw = e->tw * e->tiles * e->groups;
     kern->bh = e->th;
     return hipSuccess;
+}
+
+// ---- Global-memory multi-pass form ------------------------------------
+
+namespace {
+
+const DaEntry* dag_find(int dtype, int k, int tw, int th)
+{
+    const int es = (dtype == MF_U8 || dtype == MF_U16) ? 2 : 4;
+    for (int i = 0; i < kDaCount; ++i) {
+        const DaEntry& e = kDaTable[i];
+        if (e.mem == 1 && e.kz == 1 && e.k == k && e.kh == k && e.es == es && (tw == 0 || e.tw == tw) &&
+            (th == 0 || e.th == th))
+            return &e;
+    }
+    // any schedule of this element size and tile also runs from the workspace
+    if (tw && th) {
+        for (int i = 0; i < kDaCount; ++i) {
+            const DaEntry& e = kDaTable[i];
+            if (e.kz == 1 && e.k == k && e.kh == k && e.es == es && e.tw == tw && e.th == th && e.groups == 1)
+                return &e;
+        }
+    }
+    return nullptr;
+}
+
+const void* dag_kernel_for_dtype(int dtype)
+{
+    if (dtype == MF_U8) return (const void*)mf_dag_kernel<uint16_t, false>;
+    if (dtype == MF_U16) return (const void*)mf_dag_kernel<uint16_t, true>;
+    return (const void*)mf_dag_kernel<uint32_t, true>;
+}
+
+long long dag_slot_bytes(const DaEntry* e) { return (((long long)e->arena * e->es) + 255) / 256 * 256; }
+
+}  // namespace
+
+bool mf_dag_supports(int dtype, int k, int tw, int th) { return dag_find(dtype, k, tw, th) != nullptr; }
+
+bool mf_dag_workspace(int dtype, int k, int tw, int th, long long planes, int H, int W, long long* slot_bytes,
+                      long long* all_bytes, int* used_tw, int* used_th)
+{
+    const DaEntry* e = dag_find(dtype, k, tw, th);
+    if (!e) return false;
+    const long long ntx = (W + e->tw - 1) / e->tw, nty = (H + e->th - 1) / e->th;
+    *slot_bytes = dag_slot_bytes(e);
+    *all_bytes = *slot_bytes * ntx * nty * planes;
+    *used_tw = e->tw;
+    *used_th = e->th;
+    return true;
+}
+
+int mf_dag_passes(int dtype, int k, int tw, int th)
+{
+    const DaEntry* e = dag_find(dtype, k, tw, th);
+    if (!e) return 0;
+    const uint32_t* phase = reinterpret_cast<const uint32_t*>(mf_da_blob_host) + e->p_off;
+    int n = 0;
+    for (int r = 0; r < e->nrounds; ++r)
+        if (r == 0 || phase[r] / 2 != phase[r - 1] / 2) ++n;
+    return n;
+}
+
+hipError_t mf_dag_launch(const void* src, void* dst, int planes, long long plane_stride, int H, int W,
+                         long long pitch, int dtype, int k, int tw, int th, void* ws, long long ws_bytes,
+                         hipStream_t stream)
+{
+    const DaEntry* e = dag_find(dtype, k, tw, th);
+    if (!e) return hipErrorInvalidValue;
+    const uint32_t* blob = nullptr;
+    hipError_t err = da_blob(&blob);
+    if (err != hipSuccess) return err;
+    MfDaArgs a = da_args(e, blob);
+    a.groups = 1;
+    const int ntx = (W + e->tw - 1) / e->tw, nty = (H + e->th - 1) / e->th;
+    const int per_plane = ntx * nty;
+    const long long total = (long long)per_plane * planes;
+    const long long slot = dag_slot_bytes(e);
+    long long slice = ws_bytes / slot;
+    if (slice < 1) return hipErrorInvalidValue;
+    if (slice > total) slice = total;
+    if (slice > 0x7fffffffLL) slice = 0x7fffffffLL;
+    // passes: consecutive rounds of two recursion levels each (the
+    // initialisation is level 0)
+    const uint32_t* phase = reinterpret_cast<const uint32_t*>(mf_da_blob_host) + e->p_off;
+    int bounds[64];
+    int nb = 0;
+    for (int r = 0; r < e->nrounds && nb < 63; ++r)
+        if (r == 0 || phase[r] / 2 != phase[r - 1] / 2) bounds[nb++] = r;
+    bounds[nb] = e->nrounds;
+    const void* fn = dag_kernel_for_dtype(dtype);
+    for (long long t0 = 0; t0 < total; t0 += slice) {
+        const unsigned grid = (unsigned)(total - t0 < slice ? total - t0 : slice);
+        for (int p = 0; p < nb; ++p) {
+            int r0 = bounds[p], r1 = bounds[p + 1], first = p == 0, last = p == nb - 1;
+            void* args[] = {&src, &dst, &H, &W, &pitch, &plane_stride, &dtype, &a, (void*)&ntx, (void*)&per_plane,
+                            &t0, &ws, &r0, &r1, &first, &last};
+            err = hipLaunchKernel(fn, dim3(grid), dim3(kDaThreads), args, 0, stream);
+            if (err != hipSuccess) return err;
+        }
+    }
+    return hipSuccess;
+}
+
+// ---- 3-D boxes --------------------------------------------------------
+
+namespace {
+
+const DaEntry* da3_find(int dtype, int k)
+{
+    const int es = (dtype == MF_U8 || dtype == MF_U16) ? 2 : 4;
+    for (int i = 0; i < kDaCount; ++i) {
+        const DaEntry& e = kDaTable[i];
+        if (e.kz > 1 && e.k == k && e.kh == k && e.kz == k && e.es == es) return &e;
+    }
+    return nullptr;
+}
+
+}  // namespace
+
+bool mf_da3_supports(int dtype, int k) { return da3_find(dtype, k) != nullptr; }
+
+int mf_da3_max_k()
+{
+    int m = 0;
+    for (int i = 0; i < kDaCount; ++i)
+        if (kDaTable[i].kz > 1 && kDaTable[i].kz > m) m = kDaTable[i].kz;
+    return m;
+}
+
+void mf_da3_tile(int dtype, int k, int* tw, int* th, int* tz)
+{
+    const DaEntry* e = da3_find(dtype, k);
+    *tw = e ? e->tw : 0;
+    *th = e ? e->th : 0;
+    *tz = e ? e->tz : 0;
+}
+
+hipError_t mf_da3_launch(const void* src, void* dst, int D, int H, int W, long long pitch, long long slice, int dtype,
+                         int k, hipStream_t stream)
+{
+    const DaEntry* e = da3_find(dtype, k);
+    if (!e) return hipErrorInvalidValue;
+    const uint32_t* blob = nullptr;
+    hipError_t err = da_blob(&blob);
+    if (err != hipSuccess) return err;
+    MfDaArgs a = da_args(e, blob);
+    const int ntx = (W + e->tw - 1) / e->tw, nty = (H + e->th - 1) / e->th, ntz = (D + e->tz - 1) / e->tz;
+    if ((long long)ntx * nty * ntz > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    const size_t lds = (size_t)e->arena * e->es;
+    void* args[] = {&src, &dst, &D, &H, &W, &pitch, &slice, &dtype, &a, (void*)&ntx, (void*)&nty};
+    return hipLaunchKernel(da3_kernel_for_dtype(dtype), dim3(ntx * nty * ntz), dim3(kDaThreads), args, lds, stream);
 }

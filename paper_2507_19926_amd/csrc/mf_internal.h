@@ -67,10 +67,31 @@ int mf_da_list(int dtype, int k, int* tw, int* th, int* group, int cap);
 // schedule offsets are filled into *args (see mf_da_batched_args).
 struct MfDaArgs {
     const uint32_t* blob;
-    int k, kh, tw, th, c_off, r_off, nrounds, o_off, arena;   // window k columns x kh rows
+    int k, kh, tw, th, c_off, r_off, nrounds, l_off, o_off, arena;   // window k columns x kh rows
     int groups;   // lane groups per work-group, each with its own root tiles
+    int kz, tz;   // 3-D boxes: box depth and root tile depth (1 for planes)
 };
 hipError_t mf_da_batched(int dtype, int k, int tw, int th, int group, MfBatchedKernel* kern, MfDaArgs* args);
+
+// Global-memory multi-pass data-aware form: square k, root tile tw x th (0 =
+// the library's), lists in a caller workspace of ws_bytes (device pointer,
+// 256-byte aligned). Tiles run in slices of ws_bytes / slot_bytes, each
+// slice in passes of two recursion levels (one launch per pass).
+bool mf_dag_supports(int dtype, int k, int tw, int th);
+bool mf_dag_workspace(int dtype, int k, int tw, int th, long long planes, int H, int W, long long* slot_bytes,
+                      long long* all_bytes, int* used_tw, int* used_th);
+int mf_dag_passes(int dtype, int k, int tw, int th);
+hipError_t mf_dag_launch(const void* src, void* dst, int planes, long long plane_stride, int H, int W,
+                         long long pitch, int dtype, int k, int tw, int th, void* ws, long long ws_bytes,
+                         hipStream_t stream);
+
+// 3-D box median, cubic k x k x k (mf_da3_supports): one kernel launch over
+// a D x H x W volume, rows pitch bytes apart, slices slice bytes apart.
+bool mf_da3_supports(int dtype, int k);
+int mf_da3_max_k();
+void mf_da3_tile(int dtype, int k, int* tw, int* th, int* tz);
+hipError_t mf_da3_launch(const void* src, void* dst, int D, int H, int W, long long pitch, long long slice, int dtype,
+                         int k, hipStream_t stream);
 
 // Differentiable form (mf_autograd.hip).
 hipError_t mf_ag_argmedian_launch(const float* src, const float* med, int32_t* idx, int64_t planes, int H,

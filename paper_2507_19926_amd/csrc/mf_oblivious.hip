@@ -599,23 +599,26 @@ mf_obl_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__
     mf_obl_block<NET, V, RY, NW>(src + po, dst + po, H, W, pitch, dtype, blockIdx.x % nbx, blockIdx.x / nbx);
 }
 
-// Batched form: the grid covers the blocks of every image of a job table
-// (images sharing k, root tile and value class); each work-group finds its
-// image by binary search over the jobs' first block indices.
+// Batched form, persistent: a resident-sized grid walks the nblocks blocks
+// of every image of a job table (images sharing k, root tile and value
+// class), work-group w taking blocks w, w + gridDim.x, ...; for each block it
+// finds the image by binary search over the jobs' first block indices.
 template <class NET, class V, int RY, int NW>
 __global__ void __launch_bounds__(64 * NW, MfVTraits<V>::PACK ? NET::MIN_WAVES : 1)
-mf_obl_kernel_batched(const MfJob* __restrict__ jobs, int njobs)
+mf_obl_kernel_batched(const MfJob* __restrict__ jobs, int njobs, int nblocks)
 {
-    const int b = blockIdx.x;
-    int lo = 0, hi = njobs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].block_begin <= b) lo = mid;
-        else hi = mid - 1;
+    for (int b = blockIdx.x; b < nblocks; b += gridDim.x) {
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].block_begin <= b) lo = mid;
+            else hi = mid - 1;
+        }
+        const MfJob j = jobs[lo];
+        const int lb = b - j.block_begin;
+        mf_obl_block<NET, V, RY, NW>(j.src, j.dst, j.H, j.W, j.pitch, j.dtype, lb % j.nbx, lb / j.nbx);
+        __syncthreads();   // the next block reuses the LDS
     }
-    const MfJob j = jobs[lo];
-    const int lb = b - j.block_begin;
-    mf_obl_block<NET, V, RY, NW>(j.src, j.dst, j.H, j.W, j.pitch, j.dtype, lb % j.nbx, lb / j.nbx);
 }
 
 template <class NET, class V, int RY, int NW>

@@ -3,10 +3,11 @@
 //
 // A plan groups its images into buckets that share a kernel (variant, k, root
 // tile, value class). Each bucket gets a job table in device memory (one MfJob
-// per image, with the index of its first grid block) and one kernel node whose
-// grid covers every block of every image of the bucket. The nodes have no
-// dependencies, so the graph runs the buckets as parallel branches. Updating a
-// plan with new pointers rewrites the job tables only; the graph is unchanged.
+// per image, with the index of its first block) and one kernel node running a
+// persistent kernel: a resident-sized grid whose work-groups walk every block
+// of every image of the bucket. The nodes have no dependencies, so the graph
+// runs the buckets as parallel branches. Updating a plan with new pointers
+// rewrites the job tables only; the graph is unchanged.
 #include <hip/hip_runtime.h>
 
 #include <stdarg.h>
@@ -39,6 +40,7 @@ struct Bucket {
     long long blocks = 0;
     MfJob* d_jobs = nullptr;
     int njobs = 0;
+    int nblocks = 0;
 };
 
 int elem_size(int dtype) { return dtype == MF_U8 ? 1 : dtype == MF_U16 ? 2 : 4; }
@@ -58,6 +60,8 @@ struct mf_plan_s {
     void* d_buf = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;      // recorded after every launch of the plan
+    bool launched = false;
     int device = 0;
 };
 
@@ -67,10 +71,25 @@ static void plan_free(mf_plan_s* p)
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->d_buf) (void)hipFree(p->d_buf);
+    if (p->done) (void)hipEventDestroy(p->done);
     delete p;
 }
 
-static int32_t check_images(const mf_image* imgs, int32_t n)
+// Work-groups of a persistent batched launch: as many as the device keeps
+// resident for this kernel (occupancy per CU x CUs), at most one per block.
+unsigned mf_internal_resident_grid(const MfBatchedKernel& k, long long blocks)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k.fn, k.threads, k.lds) != hipSuccess ||
+        cus < 1 || per_cu < 1)
+        return (unsigned)blocks;
+    const long long resident = (long long)cus * per_cu;
+    return (unsigned)(blocks < resident ? blocks : resident);
+}
+
+int32_t mf_internal_check_images(const mf_image* imgs, int32_t n)
 {
     if (!imgs) return mf_internal_fail(MF_ERR_NULL, "image list is NULL");
     if (n < 1) return mf_internal_fail(MF_ERR_DIMS, "a plan needs at least one image");
@@ -141,7 +160,7 @@ int32_t mf_plan_create(const mf_image* imgs, int32_t n, mf_plan* out)
 {
     if (!out) return mf_internal_fail(MF_ERR_NULL, "plan output pointer is NULL");
     *out = nullptr;
-    int32_t rc = check_images(imgs, n);
+    int32_t rc = mf_internal_check_images(imgs, n);
     if (rc) return rc;
     mf_plan_s* p = new (std::nothrow) mf_plan_s;
     if (!p) return mf_internal_fail(MF_ERR_NOMEM, "host allocation failed");
@@ -212,6 +231,11 @@ int32_t mf_plan_create(const mf_image* imgs, int32_t n, mf_plan* out)
         plan_free(p);
         return rc;
     }
+    e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        plan_free(p);
+        return hip_fail(e, "hipEventCreateWithFlags");
+    }
     e = hipGraphCreate(&p->graph, 0);
     if (e != hipSuccess) {
         plan_free(p);
@@ -221,11 +245,12 @@ int32_t mf_plan_create(const mf_image* imgs, int32_t n, mf_plan* out)
         hipKernelNodeParams kp;
         memset(&kp, 0, sizeof kp);
         kp.func = (void*)b.kern.fn;
-        kp.gridDim = dim3((unsigned)b.blocks);
+        kp.gridDim = dim3(mf_internal_resident_grid(b.kern, b.blocks));
         kp.blockDim = dim3(b.kern.threads);
         kp.sharedMemBytes = (unsigned)b.kern.lds;
-        void* args_obl[] = {&b.d_jobs, &b.njobs};
-        void* args_da[] = {&b.d_jobs, &b.njobs, &b.da};
+        b.nblocks = (int)b.blocks;
+        void* args_obl[] = {&b.d_jobs, &b.njobs, &b.nblocks};
+        void* args_da[] = {&b.d_jobs, &b.njobs, &b.nblocks, &b.da};
         kp.kernelParams = b.variant == MF_VARIANT_OBLIVIOUS ? args_obl : args_da;
         kp.extra = nullptr;
         hipGraphNode_t node;
@@ -247,7 +272,7 @@ int32_t mf_plan_create(const mf_image* imgs, int32_t n, mf_plan* out)
 int32_t mf_plan_update(mf_plan p, const mf_image* imgs, int32_t n)
 {
     if (!p) return mf_internal_fail(MF_ERR_PLAN, "plan is NULL");
-    int32_t rc = check_images(imgs, n);
+    int32_t rc = mf_internal_check_images(imgs, n);
     if (rc) return rc;
     if (n != (int32_t)p->imgs.size()) return mf_internal_fail(MF_ERR_PLAN, "image count differs from the plan");
     for (int i = 0; i < n; ++i) {
@@ -256,9 +281,12 @@ int32_t mf_plan_update(mf_plan p, const mf_image* imgs, int32_t n)
             a.border != b.border)
             return mf_internal_fail(MF_ERR_PLAN, "image shape, pitch, dtype or k differs from the plan");
     }
-    // the job tables may be in use by a launch still running
-    hipError_t e = hipDeviceSynchronize();
-    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    // the job tables may be in use by a launch still running: wait for the
+    // plan's last launch only (other work on the device goes on)
+    if (p->launched) {
+        hipError_t e = hipEventSynchronize(p->done);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    }
     p->imgs.assign(imgs, imgs + n);
     fill_jobs(p);
     return upload_jobs(p);
@@ -268,13 +296,17 @@ int32_t mf_plan_launch(mf_plan p, void* stream)
 {
     if (!p) return mf_internal_fail(MF_ERR_PLAN, "plan is NULL");
     hipError_t e = hipGraphLaunch(p->exec, (hipStream_t)stream);
-    return e == hipSuccess ? MF_OK : hip_fail(e, "hipGraphLaunch");
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    e = hipEventRecord(p->done, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    p->launched = true;
+    return MF_OK;
 }
 
 void mf_plan_destroy(mf_plan p)
 {
     if (!p) return;
-    (void)hipDeviceSynchronize();
+    if (p->launched) (void)hipEventSynchronize(p->done);   // the plan's last launch, nothing else
     plan_free(p);
 }
 

@@ -1,12 +1,13 @@
 """Build-time schedule generator for the data-aware hierarchical median filter.
 
 The data-aware variant (Sugy 2025, Section 5) keeps the tile recursion of
-Section 3 but realises every sort and merge with data-dependent two-way
-merges in LDS:
+Section 3 but realises every sort and merge with data-dependent work in LDS:
 
-* sorting a column, an extra row or a group of corners is a binary reduction
-  of two-way merges starting from single footprint values (Section 5.1:
-  many small sorts, merged pairwise);
+* sorting a column, an extra row or a group of corners (footprint values
+  that lie on one line) is one per-lane sorting network over at most
+  SORT_MAX values held in registers (Section 5.1: the many small sorts run as
+  sorting networks per thread); longer lines are cut into such pieces, which
+  are then merged;
 * a multi-way merge is a binary reduction of two-way merges, halving the
   number of lists each round (Section 5.1);
 * every two-way merge is executed with merge path: its output is cut into
@@ -20,31 +21,57 @@ so no element outside it is ever produced.
 
 The generator records, for one root tile of t_w x t_h pixels, a DAG of list
 nodes, assigns each node the recursion level (phase) that creates it,
-schedules the merges of each phase in dependency rounds, allocates LDS
-(first fit, freed after the last reader) and emits compact descriptors:
+schedules the work of each phase in dependency rounds, allocates LDS (first
+fit, freed after the last reader) and emits compact items of 4 words.
 
-* one chunk = 4 words: a_off | na << 18, b_off | nb << 18, out_off | n << 18,
-  r0 (the rank, within the merge of the two input windows, of the chunk's
-  first output);
-* rounds = ranges of chunks separated by a work-group barrier;
-* outputs = LDS offset of each pixel's median.
+Every stored list is followed by one sentinel slot holding the largest
+element value, so a merge never tests whether an input is exhausted: the
+element after an input window is either that sentinel or a list element
+ranked after every output the merge must produce, and in both cases it is
+never chosen while needed outputs remain.
 
-Offsets are in elements of the LDS arena; the raw footprint occupies
-[0, fw*fh) row-major with fw = k+t_w-1.
+Items (4 uint32 words):
+
+* merge chunk: w0 = a_off | na << 18, w1 = b_off | nb << 18,
+  w2 = out_off | nvalid << 18, w3 = r0 | steps << 18 | last << 22.
+  The lane finds the co-rank of rank r0 (the chunk's first output, counted in
+  the merge of the two input windows; A first on ties) in `steps` halving
+  steps, then emits the round's chunk length C of outputs (C is uniform over
+  a round; a merge's last chunk is aligned to end at its window's end and may
+  overlap the previous one, rewriting the same values). When `last` is set
+  the lane then writes the sentinel at out_off + nvalid.
+* sort: w0 = base | n << 18, w1 = stride | lo << 18, w2 = out_off | (hi-lo) << 18,
+  w3 = SORT_FLAG | N: the n footprint values at base + i*stride are sorted by
+  the network for N (a power of two >= n, padded with the largest value); ranks
+  [lo, hi) are written from out_off, followed by the sentinel.
+
+Per round: the item range (work-group barrier between rounds) and the chunk
+length C. Offsets are in elements of the LDS arena: a guard of GUARD elements
+(its last slot holds the sentinel value and stands in for empty input
+windows), then the raw footprint (row-major, fw = k_w+t_w-1 wide), then the
+lists; the arena ends with a pad that absorbs the reads and writes a chunk
+makes past its needed outputs.
 """
 from __future__ import annotations
 
-import math
 from dataclasses import dataclass, field
 
 import numpy as np
 
-CHUNK = 4           # shortest merge-path chunk (outputs)
+CHUNK = 4           # shortest merge-path chunk; every chunk length is a multiple of it
 LANES = 512         # threads of a data-aware work-group: a round's outputs are
                     # cut into about this many chunks
 OFF_BITS = 18       # arena offsets and sizes share a 32-bit word
 MAX_OFF = 1 << OFF_BITS
 MAX_LEN = 1 << (32 - OFF_BITS)
+SORT_MAX = 32       # largest per-lane sorting network
+ROUNDS = "phase"    # round assignment: "asap" over the whole DAG, or "phase"
+                    # (ASAP within each recursion level)
+GUARD = 4           # arena elements before the footprint; slot GUARD-1 holds the sentinel
+SENTINEL_SLOT = GUARD - 1
+SORT_FLAG = 1 << 31
+STEP_SHIFT = 18
+LAST_BIT = 1 << 22
 
 
 @dataclass
@@ -54,6 +81,7 @@ class Node:
     a: tuple | None = None          # (node, lo, hi) input views
     b: tuple | None = None
     raw: tuple | None = None        # (x, y) for a single footprint value
+    line: tuple | None = None       # sort node: (base, stride, n) footprint offsets
     phase: int = 0
     need_lo: int = 0
     need_hi: int = 0
@@ -61,12 +89,14 @@ class Node:
     off: int = -1
     rnd: int = -1
     role: str = ""
+    store: int = 0                  # allocated elements (window + pad + sentinel)
 
 
 class Dag:
-    def __init__(self, fw: int):
+    def __init__(self, fw: int, fh: int = 0):
         self.nodes: list[Node] = []
         self.fw = fw
+        self.fh = fh            # footprint rows (needed for 3-D points)
         self.phase = 0
         self.role = ""
         self._raw = {}
@@ -102,8 +132,32 @@ class Dag:
             lists = nxt
         return lists[0]
 
-    def sort(self, values: list[tuple]) -> tuple:
-        return self.reduce(values)
+    def offset(self, p: tuple) -> int:
+        """Arena offset of footprint point (x, y) or (x, y, z)."""
+        x, y = p[0], p[1]
+        z = p[2] if len(p) > 2 else 0
+        return GUARD + (z * self.fh + y) * self.fw + x
+
+    def _line(self, pts: list[tuple]) -> Node:
+        """Sort node over footprint points that lie on one line (equal steps)."""
+        offs = [self.offset(p) for p in pts]
+        stride = offs[1] - offs[0] if len(offs) > 1 else 1
+        assert stride > 0 and all(offs[i] == offs[0] + i * stride for i in range(len(offs)))
+        n = Node(len(self.nodes), len(pts), line=(offs[0], stride, len(pts)), phase=self.phase,
+                 role=self.role)
+        self.nodes.append(n)
+        return n
+
+    def sort(self, pts: list[tuple]) -> tuple:
+        """Sorted list of the footprint values at pts ((x, y) or (x, y, z) on
+        one line):
+        sorting networks over pieces of at most SORT_MAX values, merged."""
+        if not pts:
+            return (None, 0, 0)
+        npc = -(-len(pts) // SORT_MAX)
+        step = -(-len(pts) // npc)
+        pieces = [self._line(pts[i:i + step]) for i in range(0, len(pts), step)]
+        return self.reduce([(p, 0, p.size) for p in pieces])
 
 
 def trim(ref: tuple, unseen: int) -> tuple:
@@ -135,11 +189,11 @@ def build_dag(k: int, tw: int, th: int, kh: int | None = None):
 
     def col(x, ys):
         D.role = "sort_col"
-        return D.sort([D.raw(x, y) for y in ys])
+        return D.sort([(x, y) for y in ys])
 
     def row(y, xs):
         D.role = "sort_row"
-        return D.sort([D.raw(x, y) for x in xs])
+        return D.sort([(x, y) for x in xs])
 
     D.phase = 0
     cols = [col(x, core_y) for x in core_x]
@@ -170,7 +224,7 @@ def build_dag(k: int, tw: int, th: int, kh: int | None = None):
                 nrows = {}
                 for y, r in xrows.items():
                     D.role = "sort_corner"
-                    cs = D.sort([D.raw(x, y) for x in added])
+                    cs = D.sort([(x, y) for x in added])
                     D.role = "extend"
                     nrows[y] = D.merge(r, cs)
                 children.append((cox, oy, hh, h, c, ncols, nrows))
@@ -187,7 +241,7 @@ def build_dag(k: int, tw: int, th: int, kh: int | None = None):
                 ncols = {}
                 for x, cl in xcols.items():
                     D.role = "sort_corner"
-                    cs = D.sort([D.raw(x, y) for y in added])
+                    cs = D.sort([(x, y) for y in added])
                     D.role = "extend"
                     ncols[x] = D.merge(cl, cs)
                 children.append((ox, coy, w, hh, c, ncols, nrows))
@@ -196,6 +250,142 @@ def build_dag(k: int, tw: int, th: int, kh: int | None = None):
 
     recurse(0, 0, tw, th, core, xcols, xrows, 0)
     outs = [outputs[(px, py)] for py in range(th) for px in range(tw)]
+    return D, outs
+
+
+def build_dag3(kx: int, ky: int, kz: int, tx: int, ty: int, tz: int):
+    """DAG of the hierarchical recursion for a tx x ty x tz root tile of a 3-D
+    box median (kx x ky x kz, odd sides): the recursion of build_dag with a
+    third axis.
+
+    A tile's footprint is (kx+tx-1) x (ky+ty-1) x (kz+tz-1); its core (the
+    intersection of its voxels' boxes) spans [t_a-1, k_a) on every axis a.
+    Besides the trimmed sorted core a tile keeps, for every axis a and every
+    footprint coordinate c outside the core on a, a face list (the values at
+    a = c over the core ranges of the other two axes), for every pair of
+    axes and pair of outside coordinates an edge list (over the core range of
+    the third axis), and reads corners (outside on all three) as raw values.
+    A split halves the longest side (x before y before z on ties); each
+    child's core grows by the face lists of its added coordinates on the
+    split axis and is trimmed; its other faces grow by the edge lists at the
+    added coordinates; its edges that do not involve the split axis grow by
+    the sorted corners at the added coordinates.
+
+    Returns (dag, outputs) with outputs[(pz*ty + py)*tx + px] a (node, lo,
+    lo+1) view of that voxel's median."""
+    k = (kx, ky, kz)
+    t0 = (tx, ty, tz)
+    for a in range(3):
+        assert k[a] % 2 == 1 and 1 <= t0[a] <= k[a]
+    D = Dag(kx + tx - 1, ky + ty - 1)
+    N = kx * ky * kz
+    core_r = [range(t0[a] - 1, k[a]) for a in range(3)]
+    extra_c = [list(range(0, t0[a] - 1)) + list(range(k[a], k[a] + t0[a] - 1)) for a in range(3)]
+
+    def line(axis, fixed: dict, rng) -> tuple:
+        """Sorted values along `axis` over rng, the other coordinates fixed."""
+        pts = []
+        for v in rng:
+            p = dict(fixed)
+            p[axis] = v
+            pts.append((p[0], p[1], p[2]))
+        return D.sort(pts)
+
+    D.phase = 0
+    D.role = "sort_line"
+    # z-lines over the core z range at every (x, y) the core, x faces, y faces
+    # and xy edges need
+    zl = {}
+    for x in list(core_r[0]) + extra_c[0]:
+        for y in list(core_r[1]) + extra_c[1]:
+            if x in extra_c[0] and y in extra_c[1]:
+                continue
+            zl[(x, y)] = line(2, {0: x, 1: y}, core_r[2])
+    D.role = "core_init"
+    core = D.reduce([zl[(x, y)] for x in core_r[0] for y in core_r[1]])
+    core = trim(core, N - len(core_r[0]) * len(core_r[1]) * len(core_r[2]))
+    D.role = "face_init"
+    face = [dict(), dict(), dict()]
+    for c in extra_c[0]:
+        face[0][c] = D.reduce([zl[(c, y)] for y in core_r[1]])
+    for c in extra_c[1]:
+        face[1][c] = D.reduce([zl[(x, c)] for x in core_r[0]])
+    for c in extra_c[2]:
+        D.role = "sort_line"
+        xs = [line(0, {1: y, 2: c}, core_r[0]) for y in core_r[1]]
+        D.role = "face_init"
+        face[2][c] = D.reduce(xs)
+    D.role = "sort_line"
+    edge = {(0, 1): {}, (0, 2): {}, (1, 2): {}}
+    for cx in extra_c[0]:
+        for cy in extra_c[1]:
+            edge[(0, 1)][(cx, cy)] = line(2, {0: cx, 1: cy}, core_r[2])
+        for cz in extra_c[2]:
+            edge[(0, 2)][(cx, cz)] = line(1, {0: cx, 2: cz}, core_r[1])
+    for cy in extra_c[1]:
+        for cz in extra_c[2]:
+            edge[(1, 2)][(cy, cz)] = line(0, {1: cy, 2: cz}, core_r[0])
+    outputs = {}
+
+    def recurse(o, t, core, face, edge, level):
+        if t == (1, 1, 1):
+            assert core[2] - core[1] == 1
+            outputs[o] = core
+            return
+        a = max(range(3), key=lambda i: (t[i], -i))     # longest side, x first on ties
+        b, c = [i for i in range(3) if i != a]
+        half = t[a] // 2
+        children = []
+        for side in (0, 1):
+            D.phase = level + 1
+            if side == 0:
+                co = o[a]
+                added = list(range(o[a] + half - 1, o[a] + t[a] - 1))
+            else:
+                co = o[a] + half
+                added = list(range(o[a] + k[a], o[a] + k[a] + half))
+            nt = list(t)
+            nt[a] = half
+            no = list(o)
+            no[a] = co
+            D.role = "core_extra"
+            e = D.reduce([face[a][x] for x in added])
+            D.role = "core_merge"
+            cm = D.merge(core, e)
+            cm = trim(cm, N - (k[0] - nt[0] + 1) * (k[1] - nt[1] + 1) * (k[2] - nt[2] + 1))
+            nface = [dict(), dict(), dict()]
+            keep_a = list(range(co, co + half - 1)) + list(range(co + k[a], co + k[a] + half - 1))
+            nface[a] = {x: face[a][x] for x in keep_a}
+            for f in (b, c):
+                g = c if f == b else b
+                pair = (min(a, f), max(a, f))
+                for cf, lst in face[f].items():
+                    D.role = "face_extra"
+                    ex = D.reduce([edge[pair][(x, cf) if a < f else (cf, x)] for x in added])
+                    D.role = "face_merge"
+                    nface[f][cf] = D.merge(lst, ex)
+            nedge = {(0, 1): {}, (0, 2): {}, (1, 2): {}}
+            for pair in nedge:
+                if a in pair:
+                    ia = pair.index(a)
+                    nedge[pair] = {key: v for key, v in edge[pair].items() if key[ia] in keep_a}
+                else:
+                    for (c1, c2), lst in edge[pair].items():
+                        D.role = "sort_corner"
+                        pts = []
+                        for x in added:
+                            q = [0, 0, 0]
+                            q[pair[0]], q[pair[1]], q[a] = c1, c2, x
+                            pts.append(tuple(q))
+                        cs = D.sort(pts)
+                        D.role = "extend"
+                        nedge[pair][(c1, c2)] = D.merge(lst, cs)
+            children.append((tuple(no), tuple(nt), cm, nface, nedge))
+        for ch in children:
+            recurse(*ch, level + 1)
+
+    recurse((0, 0, 0), t0, core, face, edge, 0)
+    outs = [outputs[(px, py, pz)] for pz in range(tz) for py in range(ty) for px in range(tx)]
     return D, outs
 
 
@@ -227,13 +417,18 @@ class Schedule:
     th: int
     fw: int
     fh: int
-    chunks: np.ndarray          # (n_chunks, 4) uint32
-    rounds: np.ndarray          # (n_rounds + 1,) int32 chunk offsets
+    items: np.ndarray           # (n_items, 4) uint32
+    rounds: np.ndarray          # (n_rounds + 1,) int32 item offsets
+    chunk_len: np.ndarray       # (n_rounds,) int32 merge chunk length C per round
+    round_phase: np.ndarray     # (n_rounds,) int32 recursion level of each round (0 = initialisation)
     outputs: np.ndarray         # (tw*th,) int32 arena offsets
-    arena: int                  # elements of LDS the schedule needs
+    arena: int                  # elements of LDS the schedule needs (pad included)
     merge_outputs: int          # elements produced by all merges
     stats: dict
     kh: int = 0                 # window rows (0: k, the square filter)
+    fd: int = 1                 # footprint depth (3-D boxes; 1 for planes)
+    kz: int = 1                 # box depth (3-D)
+    tz: int = 1                 # root tile depth (3-D)
 
     @property
     def kw(self) -> int:
@@ -243,10 +438,15 @@ class Schedule:
     def rows(self) -> int:
         return self.kh or self.k
 
+    @property
+    def chunks(self) -> np.ndarray:
+        return self.items
+
 
 def _window_inputs(n: Node):
     """Input windows (storage offset, count) and the first output rank
-    relative to the merge of those windows, for node n's needed window."""
+    relative to the merge of those windows, for node n's needed window. An
+    empty window points at the arena's sentinel slot."""
     lo, hi = n.need_lo, n.need_hi
     res = []
     starts = []
@@ -257,59 +457,106 @@ def _window_inputs(n: Node):
         a1 = min(ls, hi)
         if a1 < a0:
             a1 = a0
-        # storage of m covers [m.need_lo, m.need_hi)
-        off = m.off + (s_lo + a0 - (m.need_lo if m.raw is None else 0))
-        res.append((off, a1 - a0))
+        if a1 == a0:
+            res.append((SENTINEL_SLOT, 0))
+        else:
+            # storage of m covers [m.need_lo, m.need_hi) and its sentinel
+            res.append((m.off + (s_lo + a0 - m.need_lo), a1 - a0))
         starts.append(a0)
     r0 = lo - starts[0] - starts[1]
     return res[0], res[1], r0
 
 
+# comparators of Batcher's odd-even merge sort of N = 2^p values
+_OEMS_CES = {1: 0, 2: 1, 4: 5, 8: 19, 16: 63, 32: 191}
+
+
+def _pow2_at_least(n: int) -> int:
+    p = 1
+    while p < n:
+        p *= 2
+    return p
+
+
 def schedule(k: int, tw: int, th: int, chunk: int = CHUNK, lanes: int = LANES,
              kh: int | None = None) -> Schedule:
-    """Rounds of windowed merges for root tile tw x th. Every round's outputs
-    are cut into chunks of max(chunk, ceil(outputs / lanes)) so that one
-    round keeps about `lanes` threads busy with chains as short as the round
-    allows (a lane runs a co-rank search, then its chunk sequentially)."""
+    """Rounds of sorts and windowed merges for root tile tw x th. A round's
+    merges are cut into chunks of one length C = a multiple of `chunk`, at
+    least ceil(outputs / lanes), so that one round keeps about `lanes`
+    threads busy with chains as short as the round allows (a lane runs a
+    co-rank search, then C sequential merge steps)."""
     kh = k if kh is None else kh
     D, outs = build_dag(k, tw, th, kh)
+    S = _schedule_dag(D, outs, k + tw - 1, (kh + th - 1), 1, tw * th, chunk, lanes)
+    S.k, S.tw, S.th, S.kh = k, tw, th, kh
+    return S
+
+
+def schedule3(kx: int, ky: int, kz: int, tx: int, ty: int, tz: int, chunk: int = CHUNK,
+              lanes: int = LANES) -> Schedule:
+    """As schedule, for the 3-D box kx x ky x kz and root tile tx x ty x tz."""
+    D, outs = build_dag3(kx, ky, kz, tx, ty, tz)
+    S = _schedule_dag(D, outs, kx + tx - 1, ky + ty - 1, kz + tz - 1, tx * ty * tz, chunk, lanes)
+    S.k, S.tw, S.th, S.kh, S.kz, S.tz = kx, tx, ty, ky, kz, tz
+    return S
+
+
+def _schedule_dag(D: Dag, outs: list, fw: int, fh: int, fd: int, npx: int, chunk: int, lanes: int) -> Schedule:
+    """Rounds, LDS allocation and items of a DAG whose footprint is
+    fw x fh x fd (fd = 1 for planes) and whose tile has npx outputs."""
     propagate_windows(D, outs)
-    fw, fh = k + tw - 1, kh + th - 1
-    merges = [n for n in D.nodes if n.a is not None and n.need_hi > n.need_lo]
-    # rounds: per phase, ASAP by dependency depth within the phase
-    depth = {}
-    for n in merges:
-        d = 0
-        for src in (n.a, n.b):
-            m = src[0]
-            if m.a is not None and m.need_hi > m.need_lo and m.phase == n.phase:
-                d = max(d, depth[m.nid] + 1)
-        depth[n.nid] = d
-    phases = sorted(set(n.phase for n in merges))
-    order = []
-    for p in phases:
-        pm = [n for n in merges if n.phase == p]
-        dmax = max(depth[n.nid] for n in pm)
-        for d in range(dmax + 1):
-            order.append([n for n in pm if depth[n.nid] == d])
+    work = [n for n in D.nodes if (n.a is not None or n.line is not None) and n.need_hi > n.need_lo]
+    if ROUNDS == "asap":
+        # rounds: ASAP over the whole DAG (a node runs in the round after its
+        # last input), so the reductions that build the next level's added
+        # lists overlap the current level's core merge
+        depth = {}
+        for n in work:
+            d = 0
+            if n.a is not None:
+                for src in (n.a, n.b):
+                    m = src[0]
+                    if m.nid in depth:
+                        d = max(d, depth[m.nid] + 1)
+            depth[n.nid] = d
+        order = [[] for _ in range(max(depth.values()) + 1)]
+        for n in work:
+            order[depth[n.nid]].append(n)
+    else:
+        # rounds: per phase, ASAP by dependency depth within the phase
+        depth = {}
+        for n in work:
+            d = 0
+            if n.a is not None:
+                for src in (n.a, n.b):
+                    m = src[0]
+                    if m.nid in depth and m.phase == n.phase:
+                        d = max(d, depth[m.nid] + 1)
+            depth[n.nid] = d
+        phases = sorted(set(n.phase for n in work))
+        order = []
+        for p in phases:
+            pm = [n for n in work if n.phase == p]
+            dmax = max(depth[n.nid] for n in pm)
+            for d in range(dmax + 1):
+                order.append([n for n in pm if depth[n.nid] == d])
     for r, group in enumerate(order):
         for n in group:
             n.rnd = r
     # last round in which each node is read (outputs: forever)
     last_read = {}
-    for n in merges:
+    for n in work:
+        if n.a is None:
+            continue
         for src in (n.a, n.b):
             m = src[0]
             last_read[m.nid] = max(last_read.get(m.nid, -1), n.rnd)
     for (n, _, _) in outs:
         last_read[n.nid] = len(order) + 1
-    # allocation: raw footprint fixed at [0, fw*fh); first fit for the rest
-    for n in D.nodes:
-        if n.raw is not None:
-            n.off = n.raw[1] * fw + n.raw[0]
-    free = [(fw * fh, 1 << 40)]      # (start, end) holes, sorted
-    peak = fw * fh
-    live_by_end = {}
+    # allocation: guard + raw footprint fixed at [0, GUARD + fw*fh); first fit for the rest
+    base = GUARD + fw * fh * fd
+    free = [(base, 1 << 40)]         # (start, end) holes, sorted
+    peak = base
 
     def alloc(size):
         nonlocal peak
@@ -333,74 +580,209 @@ def schedule(k: int, tw: int, th: int, chunk: int = CHUNK, lanes: int = LANES,
                 merged.append((a, b))
         free[:] = merged
 
-    chunks = []
+    items = []
     rounds = [0]
+    clens = []
+    cmax = chunk
     for r, group in enumerate(order):
+        merges = [n for n in group if n.a is not None]
+        total = sum(n.need_hi - n.need_lo for n in merges)
+        C = max(chunk, -(-total // lanes))
+        C = -(-C // chunk) * chunk
+        cmax = max(cmax, C)
         for n in group:
-            n.off = alloc(n.need_hi - n.need_lo)
-        total = sum(n.need_hi - n.need_lo for n in group)
-        step = max(chunk, -(-total // lanes))
-        rchunks = []
-        for n in group:
-            (aoff, na), (boff, nb), r0 = _window_inputs(n)
             nout = n.need_hi - n.need_lo
+            n.store = (max(nout, C) if n.a is not None else nout) + 1
+            n.off = alloc(n.store)
+        sorts = []
+        chunks = []
+        for n in group:
+            nout = n.need_hi - n.need_lo
+            if n.line is not None:
+                b0, stride, cnt = n.line
+                N = _pow2_at_least(cnt)
+                assert N <= SORT_MAX and b0 < MAX_OFF and stride < MAX_OFF and n.off < MAX_OFF
+                sorts.append((N, (b0 | (cnt << OFF_BITS), stride | (n.need_lo << OFF_BITS),
+                                  n.off | (nout << OFF_BITS), SORT_FLAG | N)))
+                continue
+            (aoff, na), (boff, nb), r0 = _window_inputs(n)
             assert 0 <= r0 and r0 + nout <= na + nb, (n.nid, r0, nout, na, nb)
-            for c0 in range(0, nout, step):
-                c = min(step, nout - c0)
+            starts = list(range(0, nout - C + 1, C)) if nout >= C else [0]
+            if nout > C and nout % C:
+                starts.append(nout - C)
+            for ci, c0 in enumerate(starts):
+                last = ci == len(starts) - 1
+                nvalid = C if nout >= C else nout
+                rr = r0 + c0
+                lo_i, hi_i = max(0, rr - nb), min(rr, na)
+                steps = max(hi_i - lo_i, 0).bit_length()
                 for off in (aoff, boff, n.off + c0):
                     assert 0 <= off < MAX_OFF
-                assert na < MAX_LEN and nb < MAX_LEN and c < MAX_LEN
-                # a lane's work: co-rank search steps plus sequential outputs
-                span = min(r0 + c0, na) - max(0, r0 + c0 - nb)
-                cost = max(span, 0).bit_length() + c
-                rchunks.append((cost, (aoff | (na << OFF_BITS), boff | (nb << OFF_BITS),
-                                       (n.off + c0) | (c << OFF_BITS), r0 + c0)))
-        # costliest first: the chunks of one wave (64 consecutive lanes) then
-        # take about the same time, so fewer lanes sit idle in a busy wave
-        rchunks.sort(key=lambda t: -t[0])
-        chunks.extend(ch for _, ch in rchunks)
-        rounds.append(len(chunks))
+                assert na < MAX_LEN and nb < MAX_LEN and nvalid < MAX_LEN and rr < (1 << STEP_SHIFT)
+                assert steps < 16
+                chunks.append((steps, (aoff | (na << OFF_BITS), boff | (nb << OFF_BITS),
+                                       (n.off + c0) | (nvalid << OFF_BITS),
+                                       rr | (steps << STEP_SHIFT) | (LAST_BIT if last else 0))))
+        # sorts first (by network size), then chunks by search depth: the 64
+        # lanes of a wave then run the same code with about the same trip count
+        sorts.sort(key=lambda t: t[0])
+        chunks.sort(key=lambda t: -t[0])
+        items.extend(it for _, it in sorts)
+        items.extend(it for _, it in chunks)
+        rounds.append(len(items))
+        clens.append(C)
         # free storage whose last reader ran in this round
-        for n in merges:
+        for n in work:
             if last_read.get(n.nid, -1) == r and n.off >= 0:
-                release(n.off, n.need_hi - n.need_lo)
+                release(n.off, n.store)
                 n.off = -2 - n.off  # mark released (keeps the value recoverable)
-    # every access of the kernel stays inside the arena
-    ch = np.array(chunks, dtype=np.int64).reshape(-1, 4)
-    if len(ch):
-        m = (1 << OFF_BITS) - 1
-        for col in range(3):
-            assert np.all((ch[:, col] & m) + (ch[:, col] >> OFF_BITS) <= peak)
-        assert np.all(ch[:, 3] + (ch[:, 2] >> OFF_BITS) <= (ch[:, 0] >> OFF_BITS) + (ch[:, 1] >> OFF_BITS))
+    arena = peak + cmax + 4
+    it = np.array(items, dtype=np.int64).reshape(-1, 4)
+    m = (1 << OFF_BITS) - 1
+    if len(it):
+        isort = (it[:, 3] & SORT_FLAG) != 0
+        mg = it[~isort]
+        # merge reads: one element before each window (co-rank guard) up to
+        # the window end plus a chunk length (steps past the needed outputs)
+        for col in range(2):
+            assert np.all((mg[:, col] & m) >= 1)
+            assert np.all((mg[:, col] & m) + (mg[:, col] >> OFF_BITS) + cmax + 1 <= arena)
+        assert np.all((mg[:, 2] & m) + cmax + 1 <= arena)
+        srt = it[isort]
+        assert np.all((srt[:, 0] & m) + (srt[:, 1] & m) * ((srt[:, 0] >> OFF_BITS) - 1) < GUARD + fw * fh * fd)
+        assert np.all((srt[:, 2] & m) + (srt[:, 2] >> OFF_BITS) + 1 <= arena)
     outputs = []
     for (n, lo, hi) in outs:
         off = n.off if n.off >= 0 else (-2 - n.off)
-        if n.raw is not None:
-            outputs.append(n.off)
-        else:
-            outputs.append(off + (lo - n.need_lo))
+        outputs.append(off + (lo - n.need_lo))
     assert all(0 <= o < peak for o in outputs)
+    merges = [n for n in work if n.a is not None]
     merge_outputs = sum(n.need_hi - n.need_lo for n in merges)
+    sort_outputs = sum(n.need_hi - n.need_lo for n in work if n.line is not None)
     by_role = {}
-    for n in merges:
+    for n in work:
         by_role[n.role] = by_role.get(n.role, 0) + (n.need_hi - n.need_lo)
-    st = {"rounds": len(order), "chunks": len(chunks), "merge_outputs": merge_outputs,
-          "per_pixel_by_role": {r: round(v / (tw * th), 1) for r, v in sorted(by_role.items())},
-          "per_pixel_outputs": merge_outputs / (tw * th), "arena": peak,
+    nmerge_items = int(np.sum((it[:, 3] & SORT_FLAG) == 0)) if len(it) else 0
+    # compare-exchanges of the sorting networks the sort items run
+    sort_ces = sum(_OEMS_CES[int(w3) & 0xFFFF] for w3 in it[:, 3] if int(w3) & SORT_FLAG) if len(it) else 0
+    st = {"rounds": len(order), "chunks": nmerge_items, "sorts": len(items) - nmerge_items,
+          "merge_outputs": merge_outputs, "sort_outputs": sort_outputs,
+          "per_pixel_by_role": {r: round(v / npx, 1) for r, v in sorted(by_role.items())},
+          "per_pixel_outputs": merge_outputs / npx, "arena": arena,
+          "per_pixel_sort_ces": sort_ces / npx,
           "merges": len(merges)}
-    return Schedule(k, tw, th, fw, fh, np.array(chunks, dtype=np.uint32).reshape(-1, 4),
-                    np.array(rounds, dtype=np.int32), np.array(outputs, dtype=np.int32), peak,
-                    merge_outputs, st, kh)
+    # recursion level of each round (non-decreasing): the deepest level any of
+    # its nodes belongs to, so far
+    rphase, top = [], 0
+    for group in order:
+        top = max(top, max(n.phase for n in group))
+        rphase.append(top)
+    return Schedule(0, 0, 0, fw, fh, np.array(items, dtype=np.uint32).reshape(-1, 4),
+                    np.array(rounds, dtype=np.int32), np.array(clens, dtype=np.int32),
+                    np.array(rphase, dtype=np.int32), np.array(outputs, dtype=np.int32), arena,
+                    merge_outputs, st, 0, fd)
 
 
 # ------------------------------------------------------------- CPU model
 
+def _sentinel(dtype) -> int:
+    return 0xFFFF if np.dtype(dtype).itemsize <= 2 else 0xFFFFFFFF
+
+
+def _to_keys(win: np.ndarray, dtype):
+    """Elements as the kernel holds them: 16-bit for 8/16-bit data, else
+    32-bit (float32 through the order-preserving key)."""
+    et = np.uint16 if np.dtype(dtype).itemsize <= 2 else np.uint32
+    if dtype == np.float32:
+        b = win.view(np.uint32)
+        return et, b ^ np.where(b >> 31 == 1, np.uint32(0xFFFFFFFF), np.uint32(0x80000000))
+    return et, win.astype(et)
+
+
+def _from_keys(out: np.ndarray, dtype) -> np.ndarray:
+    if dtype == np.float32:
+        k32 = out.astype(np.uint32)
+        bits = k32 ^ np.where(k32 >> 31 == 1, np.uint32(0x80000000), np.uint32(0xFFFFFFFF))
+        return bits.view(np.float32)
+    return out.astype(dtype)
+
+
+def _execute(S: Schedule, keys: np.ndarray, et, clamp: bool, exact: bool) -> np.ndarray:
+    """Run every round's items on T arenas at once (keys: (T, footprint)
+    elements) and return the (T, tile pixels) medians. The arena starts
+    filled with noise, so nothing may rely on unwritten slots."""
+    T = keys.shape[0]
+    MAXV = _sentinel(et)
+    g = np.random.default_rng(S.arena)
+    arena = g.integers(0, MAXV + 1, size=(T, S.arena), dtype=np.uint64).astype(et)
+    arena[:, SENTINEL_SLOT] = MAXV
+    arena[:, GUARD:GUARD + keys.shape[1]] = keys
+    mask = (1 << OFF_BITS) - 1
+    rows = np.arange(T)
+    for ri in range(len(S.rounds) - 1):
+        C = int(S.chunk_len[ri])
+        for c in S.items[S.rounds[ri]:S.rounds[ri + 1]]:
+            w0, w1, w2, w3 = (int(v) for v in c)
+            if w3 & SORT_FLAG:
+                base, n = w0 & mask, w0 >> OFF_BITS
+                stride, lo = w1 & mask, w1 >> OFF_BITS
+                ooff, cnt = w2 & mask, w2 >> OFF_BITS
+                N = w3 & 0xFFFF
+                assert n <= N <= SORT_MAX
+                vals = np.full((T, N), MAXV, dtype=et)
+                vals[:, :n] = arena[:, base + stride * np.arange(n)]
+                vals = np.sort(vals, axis=1)
+                arena[:, ooff:ooff + cnt] = vals[:, lo:lo + cnt]
+                arena[:, ooff + cnt] = MAXV
+                continue
+            aoff, na = w0 & mask, w0 >> OFF_BITS
+            boff, nb = w1 & mask, w1 >> OFF_BITS
+            ooff, nvalid = w2 & mask, w2 >> OFF_BITS
+            r0, steps, last = w3 & ((1 << STEP_SHIFT) - 1), (w3 >> STEP_SHIFT) & 15, bool(w3 & LAST_BIT)
+            if not exact:
+                A = arena[:, aoff:aoff + na]
+                B = arena[:, boff:boff + nb]
+                m = np.sort(np.concatenate([A, B], axis=1), axis=1)
+                arena[:, ooff:ooff + nvalid] = m[:, r0:r0 + nvalid]
+                if last:
+                    arena[:, ooff + nvalid] = MAXV
+                continue
+            lo_i, hi_i = max(0, r0 - nb), min(r0, na)
+            pos = np.full(T, lo_i, dtype=np.int64)
+            for st in range(steps):
+                step = 1 << (steps - 1 - st)
+                t = pos + step - 1
+                tc = np.minimum(t, hi_i - 1)
+                av = arena[rows, aoff + tc]
+                bv = arena[rows, boff + r0 - 1 - tc]
+                pos = np.where((t < hi_i) & (av <= bv), t + 1, pos)
+            ia = pos.copy()
+            a = arena[rows, aoff + ia]
+            b = arena[rows, boff + (r0 - ia)]
+            for q in range(C):
+                take = a <= b
+                arena[:, ooff + q] = np.minimum(a, b)
+                ia = ia + take
+                if clamp:
+                    ia = np.minimum(ia, na)
+                ib = r0 + q + 1 - ia
+                a = arena[rows, aoff + ia]
+                b = arena[rows, boff + ib]
+            if last:
+                arena[:, ooff + nvalid] = MAXV
+    return arena[:, S.outputs]
+
+
 def run_schedule_on_image(S: Schedule, img: np.ndarray, exact_merge_path: bool = False) -> np.ndarray:
     """Execute a schedule on every root tile of img (replicate border).
 
-    Each chunk merges its two input windows and keeps ranks [r0, r0+n); with
-    exact_merge_path the chunk is executed the way the kernel does it (co-rank
-    binary search, then a sequential merge), per tile."""
+    With exact_merge_path=False each merge chunk is checked against a sort of
+    its two input windows; with True every item is executed the way the
+    kernel executes it, for all tiles at once: the co-rank search with its
+    step count and clamped reads, the C merge steps that read the sentinels
+    and run past the needed outputs, the sentinel writes, and the ia clamp
+    that 16-bit and 32-bit data use (8-bit data held in 16-bit elements never
+    equals the sentinel and runs without it)."""
     kw, kh, tw, th = S.kw, S.rows, S.tw, S.th
     H, W = img.shape
     nty, ntx = -(-H // th), -(-W // tw)
@@ -409,28 +791,35 @@ def run_schedule_on_image(S: Schedule, img: np.ndarray, exact_merge_path: bool =
     pad = img[ys][:, xs]
     win = np.lib.stride_tricks.sliding_window_view(pad, (S.fh, S.fw))[::th, ::tw]
     T = nty * ntx
-    arena = np.zeros((T, S.arena), dtype=img.dtype)
-    arena[:, :S.fw * S.fh] = win.reshape(T, S.fw * S.fh)
-    mask = (1 << OFF_BITS) - 1
-    for ri in range(len(S.rounds) - 1):
-        for c in S.chunks[S.rounds[ri]:S.rounds[ri + 1]]:
-            aoff, na = int(c[0]) & mask, int(c[0]) >> OFF_BITS
-            boff, nb = int(c[1]) & mask, int(c[1]) >> OFF_BITS
-            ooff, n = int(c[2]) & mask, int(c[2]) >> OFF_BITS
-            r0 = int(c[3])
-            A = arena[:, aoff:aoff + na]
-            B = arena[:, boff:boff + nb]
-            if not exact_merge_path:
-                m = np.sort(np.concatenate([A, B], axis=1), axis=1)
-                arena[:, ooff:ooff + n] = m[:, r0:r0 + n]
-            else:
-                for t in range(T):
-                    arena[t, ooff:ooff + n] = _merge_path_chunk(A[t], B[t], r0, n)
-    out = np.empty((nty * th, ntx * tw), dtype=img.dtype)
-    for i, off in enumerate(S.outputs):
+    et, keys = _to_keys(np.ascontiguousarray(win.reshape(T, S.fw * S.fh)), img.dtype)
+    med = _execute(S, keys, et, img.dtype.itemsize >= 2, exact_merge_path)
+    out = np.empty((nty * th, ntx * tw), dtype=et)
+    for i in range(tw * th):
         py, px = divmod(i, tw)
-        out[py::th, px::tw] = arena[:, off].reshape(nty, ntx)
-    return out[:H, :W]
+        out[py::th, px::tw] = med[:, i].reshape(nty, ntx)
+    return _from_keys(out[:H, :W], img.dtype)
+
+
+def run_schedule_on_volume(S: Schedule, vol: np.ndarray, exact_merge_path: bool = False) -> np.ndarray:
+    """As run_schedule_on_image, for a 3-D schedule (schedule3) on every root
+    tile of a (D, H, W) volume (each axis clamped)."""
+    kx, ky, kz, tx, ty, tz = S.k, S.kh, S.kz, S.tw, S.th, S.tz
+    Dd, H, W = vol.shape
+    ntz, nty, ntx = -(-Dd // tz), -(-H // ty), -(-W // tx)
+    zs = np.clip(np.arange(ntz * tz + kz - 1) - (kz - 1) // 2, 0, Dd - 1)
+    ys = np.clip(np.arange(nty * ty + ky - 1) - (ky - 1) // 2, 0, H - 1)
+    xs = np.clip(np.arange(ntx * tx + kx - 1) - (kx - 1) // 2, 0, W - 1)
+    pad = vol[zs][:, ys][:, :, xs]
+    win = np.lib.stride_tricks.sliding_window_view(pad, (S.fd, S.fh, S.fw))[::tz, ::ty, ::tx]
+    T = ntz * nty * ntx
+    et, keys = _to_keys(np.ascontiguousarray(win.reshape(T, S.fw * S.fh * S.fd)), vol.dtype)
+    med = _execute(S, keys, et, vol.dtype.itemsize >= 2, exact_merge_path)
+    out = np.empty((ntz * tz, nty * ty, ntx * tx), dtype=et)
+    for i in range(tx * ty * tz):
+        pz, rem = divmod(i, tx * ty)
+        py, px = divmod(rem, tx)
+        out[pz::tz, py::ty, px::tx] = med[:, i].reshape(ntz, nty, ntx)
+    return _from_keys(out[:Dd, :H, :W], vol.dtype)
 
 
 def _merge_path_chunk(A, B, r0, n):
@@ -451,4 +840,3 @@ def _merge_path_chunk(A, B, r0, n):
         else:
             out.append(B[j]); j += 1
     return out
-

@@ -29,6 +29,9 @@ TILE_CANDIDATES = [(t, t) for t in (1, 2, 4, 8, 16, 32)] + [(2 * t, t) for t in 
 RECT_MAX_SIDE = 31
 RECT_SHAPES = [(kw, kh) for kw in range(1, RECT_MAX_SIDE + 1, 2)
                for kh in range(1, RECT_MAX_SIDE + 1, 2) if kw != kh]
+# 3-D boxes (cubic k) and the root tiles tried for them
+K3 = [3, 5, 7, 9, 11, 13, 15]
+TILES3 = [(1, 1, 1), (2, 2, 2), (4, 2, 2), (4, 4, 2), (4, 4, 4), (8, 4, 4), (8, 8, 4)]
 
 
 def tile_options(kw: int, kh: int) -> list:
@@ -46,7 +49,8 @@ def tile_options(kw: int, kh: int) -> list:
 
 def _cost(S: dagen.Schedule) -> float:
     px = S.tw * S.th
-    return S.stats["per_pixel_outputs"] + 10.0 * S.stats["chunks"] / px + S.fw * S.fh / px
+    return (S.stats["per_pixel_outputs"] + 10.0 * S.stats["chunks"] / px + 8.0 * S.stats["sorts"] / px
+            + S.fw * S.fh / px)
 
 
 # LDS budgets of the candidates: 3, 2 and 1 work-groups per CU
@@ -97,17 +101,62 @@ MAX_GROUPS = 32      # lane groups per work-group: at least 16 lanes each
 
 def lane_groups(S: dagen.Schedule, elem_bytes: int = 4) -> int:
     """Lane groups G for a small root tile: enough groups that a group's
-    kDaThreads/G lanes match the schedule's mean chunks per round (lanes
+    kDaThreads/G lanes match the schedule's mean items per round (lanes
     beyond that would idle), a power of two <= MAX_GROUPS, and G arenas
     within half the LDS (two work-groups per CU)."""
     rounds = max(1, len(S.rounds) - 1)
-    mean = max(1.0, len(S.chunks) / rounds)
+    mean = max(1.0, len(S.items) / rounds)
     g = 1
     while g < MAX_GROUPS and dagen.LANES / (2 * g) >= mean:
         g *= 2
     while g > 1 and g * S.arena * elem_bytes > LDS_BYTES // 2:
         g //= 2
     return g
+
+
+def global_tile(k: int, cache: dict):
+    """Root tile of the global-memory form for a square k x k window: the
+    lowest estimated work among the candidates whose arena the item format
+    can address, with no LDS budget (the lists live in a device workspace)."""
+    best = None
+    for (tw, th) in tile_options(k, k):
+        key = (k, k, tw, th)
+        if key not in cache:
+            cache[key] = _schedule_or_none(key)
+        S = cache[key]
+        if S is None:
+            continue
+        c = _cost(S)
+        if best is None or c < best[0]:
+            best = (c, tw, th)
+    return best[1], best[2]
+
+
+def _cost3(S: dagen.Schedule) -> float:
+    px = S.tw * S.th * S.tz
+    return (S.stats["per_pixel_outputs"] + 10.0 * S.stats["chunks"] / px + 8.0 * S.stats["sorts"] / px
+            + S.fw * S.fh * S.fd / px)
+
+
+def tile3(k: int, elem_bytes: int, cache3: dict):
+    """Root tile of the 3-D k x k x k box: the lowest estimated work among
+    TILES3 whose LDS arena fits one work-group per CU."""
+    best = None
+    for t in TILES3:
+        if max(t) > k:
+            continue
+        if t not in cache3.setdefault(k, {}):
+            try:
+                cache3[k][t] = dagen.schedule3(k, k, k, *t)
+            except (AssertionError, RuntimeError):
+                cache3[k][t] = None
+        S = cache3[k][t]
+        if S is None or S.arena * elem_bytes > LDS_BYTES:
+            continue
+        c = _cost3(S)
+        if best is None or c < best[0]:
+            best = (c, t)
+    return best[1]
 
 
 def choose_tile(k: int, elem_bytes: int, cache: dict, kh: int | None = None):
@@ -134,8 +183,29 @@ def generate(out_dir: str, workers: int | None = None) -> dict:
         cache = {key: _schedule_or_none(key) for key in keys}
     entries = []
     placed = {}
+    cache3: dict = {}
     words: list[np.ndarray] = []
     pos = 0
+
+    def place(S: dagen.Schedule, key) -> tuple:
+        """Blob words of one schedule (stored once per key): items first
+        (16-byte aligned), then round boundaries, per-round chunk lengths,
+        per-round recursion levels and median offsets."""
+        nonlocal pos
+        if key not in placed:
+            pad = (-pos) % 4
+            if pad:
+                words.append(np.zeros(pad, np.uint32))
+                pos += pad
+            offs = []
+            for arr in (S.items.reshape(-1), S.rounds, S.chunk_len, S.round_phase, S.outputs):
+                offs.append(pos)
+                words.append(arr.astype(np.uint32))
+                pos += len(arr)
+            c_off, r_off, l_off, p_off, o_off = offs
+            placed[key] = (c_off, len(S.items), r_off, len(S.rounds) - 1, l_off, p_off, o_off, S.arena)
+        return placed[key]
+
     for es in (2, 4):
         for (kw, kh) in windows():
             # rectangular windows keep one tile (no tuned choice), shared by
@@ -151,27 +221,18 @@ def generate(out_dir: str, workers: int | None = None) -> dict:
                 opts = [(tw, th, T, lane_groups(cache[(kw, kh, tw, th)]))]
             for (tw, th, T, G) in opts:
                 key = (kw, kh, tw, th, G)
-                if key not in placed:
-                    S = cache[key[:4]] if G == 1 else dagen.schedule(kw, tw, th, kh=kh,
-                                                                     lanes=dagen.LANES // G)
-                    assert S.arena * (es if kw == kh else 4) * T * G <= LDS_BYTES
-                    ch = S.chunks.reshape(-1).astype(np.uint32)
-                    rd = S.rounds.astype(np.uint32)
-                    ou = S.outputs.astype(np.uint32)
-                    # chunks first (16-byte aligned), then rounds, then outputs
-                    pad = (-pos) % 4
-                    if pad:
-                        words.append(np.zeros(pad, np.uint32))
-                        pos += pad
-                    c_off = pos
-                    words.append(ch); pos += len(ch)
-                    r_off = pos
-                    words.append(rd); pos += len(rd)
-                    o_off = pos
-                    words.append(ou); pos += len(ou)
-                    placed[key] = (c_off, len(S.chunks), r_off, len(S.rounds) - 1, o_off, S.arena)
-                c_off, nch, r_off, nr, o_off, arena = placed[key]
-                entries.append((kw, kh, es, tw, th, T, G, c_off, nch, r_off, nr, o_off, arena))
+                S = cache[key[:4]] if G == 1 else dagen.schedule(kw, tw, th, kh=kh, lanes=dagen.LANES // G)
+                assert S.arena * (es if kw == kh else 4) * T * G <= LDS_BYTES
+                entries.append((kw, kh, 1, es, tw, th, 1, T, G, 0) + place(S, key))
+        # global-memory form (square windows): lists in a device workspace,
+        # so the tile is not bounded by the LDS
+        for k in KS:
+            tw, th = global_tile(k, cache)
+            entries.append((k, k, 1, es, tw, th, 1, 1, 1, 1) + place(cache[(k, k, tw, th)], (k, k, tw, th, 1)))
+        # 3-D boxes
+        for k in K3:
+            t = tile3(k, es, cache3)
+            entries.append((k, k, k, es) + t + (1, 1, 0) + place(cache3[k][t], (k, k, k) + t))
     blob = np.concatenate(words).astype("<u4")
     bpath = os.path.join(out_dir, "mf_da_blob.bin")
     data = blob.tobytes()
@@ -179,14 +240,16 @@ def generate(out_dir: str, workers: int | None = None) -> dict:
         with open(bpath, "wb") as f:
             f.write(data)
     lines = ["// Generated by emit_da.py: data-aware schedules, one entry per",
-             "// (k_w, k_h, LDS element size, root tile, tiles per lane, lane groups).",
+             "// (k_w, k_h, k_z, element size, root tile t_w x t_h x t_z, tiles per lane,",
+             "// lane groups, memory: 0 = LDS arena, 1 = device workspace).",
              "#pragma once",
              "#define MF_DA_BLOB_WORDS %d" % len(blob),
              "#define MF_DA_CHUNK %d" % dagen.CHUNK,
+             "#define MF_DA_GUARD %d" % dagen.GUARD,
              "#define MF_DA_RECT_MAX_SIDE %d" % RECT_MAX_SIDE,
              "#define MF_DA_TABLE_ENTRIES \\"]
     for e in entries:
-        lines.append("    {%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d}, \\" % e)
+        lines.append("    {" + ", ".join("%d" % v for v in e) + "}, \\")
     lines.append("")
     text = "\n".join(lines) + "\n"
     hpath = os.path.join(out_dir, "mf_da_table.h")

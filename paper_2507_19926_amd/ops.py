@@ -69,6 +69,62 @@ def median_filter(x: torch.Tensor, k: int, out: torch.Tensor | None = None,
     return out
 
 
+def median_filter_global(x: torch.Tensor, k: int, out: torch.Tensor | None = None, tile=None,
+                         budget_bytes: int | None = None) -> torch.Tensor:
+    """The global-memory multi-pass form (median_filter_global) over the
+    equally spaced (H, W) planes of x: the workspace is a torch allocation of
+    min(budget_bytes, every tile at once) bytes, at least one tile's slot;
+    the library runs the tiles in slices that fit it."""
+    if not x.is_cuda:
+        raise ValueError("median_filter_global needs a GPU tensor")
+    code = dtype_code(x.dtype)
+    if x.stride(-1) != 1:
+        x = x.contiguous()
+    H, W = x.shape[-2], x.shape[-1]
+    if out is None:
+        out = torch.empty(x.shape, dtype=x.dtype, device=x.device)
+    if out.shape != x.shape or out.dtype != x.dtype or out.stride() != x.stride():
+        raise ValueError("out must match x in shape, dtype and strides")
+    es = x.element_size()
+    px = x.reshape(-1, H, W) if x.dim() > 2 else x.unsqueeze(0)
+    n = px.shape[0]
+    stride = px.stride(0) * es if n > 1 else 0
+    slot, allb, _, _, _ = _lib.global_workspace(code, int(k), n, H, W, tile)
+    nbytes = allb if budget_bytes is None else max(slot, min(allb, int(budget_bytes)))
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=x.device)
+    wp = (ws.data_ptr() + 255) // 256 * 256
+    tw, th = (0, 0) if tile is None else (int(tile[0]), int(tile[1]))
+    _lib.check(_lib.lib().median_filter_global(x.data_ptr(), out.data_ptr(), n, stride, H, W, x.stride(-2) * es,
+                                               code, int(k), _lib.MF_BORDER_REPLICATE, tw, th, wp, nbytes,
+                                               _stream_handle(x.device)))
+    # ws goes back to torch's caching allocator on the stream the kernels
+    # were enqueued on, so no later allocation can reuse it before they finish
+    return out
+
+
+def median_filter_3d(x: torch.Tensor, k: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Exact k x k x k box median (each axis clamped) of a (D, H, W) device
+    volume, through median_filter_3d; rows may be pitched, slices equally
+    spaced."""
+    if not x.is_cuda:
+        raise ValueError("median_filter_3d needs a GPU tensor")
+    if x.dim() != 3:
+        raise ValueError("median_filter_3d needs a (D, H, W) volume")
+    code = dtype_code(x.dtype)
+    if x.stride(-1) != 1:
+        x = x.contiguous()
+    if out is None:
+        out = torch.empty(x.shape, dtype=x.dtype, device=x.device)
+    if out.shape != x.shape or out.dtype != x.dtype or out.stride() != x.stride():
+        raise ValueError("out must match x in shape, dtype and strides")
+    D, H, W = x.shape
+    es = x.element_size()
+    _lib.check(_lib.lib().median_filter_3d(x.data_ptr(), out.data_ptr(), D, H, W, x.stride(1) * es,
+                                           x.stride(0) * es, code, int(k), _lib.MF_BORDER_REPLICATE,
+                                           _stream_handle(x.device)))
+    return out
+
+
 def median_filter_rect(x: torch.Tensor, kw: int, kh: int, out: torch.Tensor | None = None,
                        variant: int = _lib.MF_VARIANT_AUTO) -> torch.Tensor:
     """Exact median of the kw x kh window (kw columns, kh rows, both odd;
@@ -222,3 +278,4 @@ def median_filter_batched(xs, ks, outs=None):
     dev = xs[0].device
     _lib.check(_lib.lib().median_filter_batched(arr, len(arr), _stream_handle(dev)))
     return outs
+

@@ -144,3 +144,8 @@ def float_specials_plane(H: int, W: int, seed: int) -> np.ndarray:
     pick = g.random((H, W)) < 0.3
     bits[pick] = specials[g.integers(0, len(specials), size=int(pick.sum()))]
     return bits.view(np.float32)
+
+
+def volume_u8(side: int = 256, seed: int = BASE_SEED + 5) -> np.ndarray:
+    """(side, side, side) uint8 volume, uniform 0..255 (3-D box filter input)."""
+    return rng(seed).integers(0, 256, size=(side, side, side), dtype=np.uint8)

@@ -210,3 +210,52 @@ def test_plan_validation():
     assert L.mf_plan_launch(None, None) == -9
     assert L.mf_plan_update(None, arr, 2) == -9
     L.mf_plan_destroy(None)
+
+
+def test_global_form_validation():
+    """Workspace query and the global-memory entry's host checks (no GPU
+    work): sizes consistent with the tiles, every error before a launch."""
+    L = _lib.lib()
+    slot, allb, tw, th, passes = _lib.global_workspace(_lib.MF_U8, 75, 3, 4480, 6720)
+    assert slot > 0 and slot % 256 == 0 and passes >= 2
+    assert allb == slot * 3 * (-(-4480 // th)) * (-(-6720 // tw))
+    s2, a2, tw2, th2, _ = _lib.global_workspace(_lib.MF_F32, 25, 1, 100, 100, tile=(16, 8))
+    assert (tw2, th2) == (16, 8) and a2 == s2 * 13 * 7
+    o = _lib.options()
+    o.variant = _lib.MF_VARIANT_GLOBAL
+    r = _lib.mf_options()
+    assert L.mf_query_options(0, 51, ctypes.byref(o), ctypes.byref(r)) == 0 and r.variant == 3 and r.rows >= 2
+    for args, code in (((0, 4, 0, 0), -5), ((0, 1, 0, 0), -5), ((9, 25, 0, 0), -4), ((0, 25, 3, 3), -10),
+                       ((0, 25, 16, 0), -10), ((0, 25, 32, 32), -10)):
+        sl, al = ctypes.c_int64(), ctypes.c_int64()
+        assert L.mf_global_workspace(*args, 1, 64, 64, ctypes.byref(sl), ctypes.byref(al), None) == code, args
+    A, B, WS = 0x10000000, 0x20000000, 0x30000000
+
+    def g(ws=WS, nbytes=slot, k=75, src=A, dst=B):
+        return L.median_filter_global(src, dst, 1, 0, 64, 64, 64, 0, k, 0, 0, 0, ws, nbytes, None)
+
+    assert g(ws=None) == -1
+    assert g(ws=WS + 16) == -11
+    assert g(nbytes=100) == -11
+    assert g(ws=A + 256) == -7
+    assert g(k=1) == -5 and g(k=76) == -5
+    assert g(src=None) == -1
+    assert L.mf_status_string(-11).decode() != "unknown status"
+
+
+def test_3d_entry_validation():
+    """3-D box entry: host checks before any GPU work."""
+    L = _lib.lib()
+    A, B = 0x10000000, 0x20000000
+
+    def c(src=A, dst=B, D=4, H=8, W=8, pitch=8, slice_=64, dtype=0, k=3, border=0):
+        return L.median_filter_3d(src, dst, D, H, W, pitch, slice_, dtype, k, border, None)
+
+    assert L.mf_max_k_3d() >= 15
+    assert c(src=None) == -1
+    assert c(D=0) == -2 and c(H=0) == -2
+    assert c(pitch=7) == -3 and c(slice_=63) == -3 and c(dtype=1, pitch=16, slice_=129) == -3
+    assert c(dtype=5) == -4
+    assert c(k=4) == -5 and c(k=L.mf_max_k_3d() + 2) == -5
+    assert c(border=2) == -6
+    assert c(dst=A + 100) == -7

@@ -23,7 +23,7 @@ def test_schedule_matches_oracle(k, tw, th):
     np.testing.assert_array_equal(dg.run_schedule_on_image(S, ties), oracle.median_filter(ties, k))
 
 
-@pytest.mark.parametrize("k,tw,th", [(3, 2, 2), (5, 4, 2), (9, 4, 4), (11, 8, 4)])
+@pytest.mark.parametrize("k,tw,th", [(3, 2, 2), (5, 4, 2), (9, 4, 4), (11, 8, 4), (17, 8, 8), (25, 16, 8)])
 def test_schedule_exact_merge_path(k, tw, th):
     S = dg.schedule(k, tw, th)
     img = wl.tie_heavy_plane(9, 11, np.uint16, levels=4, seed=k)
@@ -95,3 +95,84 @@ def test_rect_windows_listed():
     assert (3, 3) in ws and (75, 75) in ws and (31, 1) in ws and (1, 31) in ws
     assert all(kw % 2 and kh % 2 for kw, kh in ws) and len(ws) == len(set(ws))
 
+
+
+def test_blob_layout_as_the_kernel_reads_it(tmp_path):
+    """The generated blob and table, decoded the way the kernel reads them
+    (items, round boundaries, per-round chunk lengths and median offsets at
+    the table's word offsets), equal the generator's schedules; every chunk
+    length is a positive multiple of the chunk quantum and every item stays
+    inside its entry."""
+    import re
+    info = emit_da.generate(str(tmp_path), workers=4)
+    blob = np.fromfile(tmp_path / "mf_da_blob.bin", dtype="<u4")
+    text = (tmp_path / "mf_da_table.h").read_text()
+    assert int(re.search(r"MF_DA_BLOB_WORDS (\d+)", text).group(1)) == len(blob)
+    assert int(re.search(r"MF_DA_GUARD (\d+)", text).group(1)) == dg.GUARD
+    rows = [tuple(int(v) for v in m.group(1).split(","))
+            for m in re.finditer(r"\{([0-9, ]+)\}", text)]
+    assert len(rows) == info["entries"]
+    seen = 0
+    for (kw, kh, kz, es, tw, th, tz, T, G, mem, c_off, nch, r_off, nr, l_off, p_off, o_off, arena) in rows:
+        assert T == 1 and G >= 1 and c_off % 4 == 0 and mem in (0, 1)
+        assert (kz, tz) == (1, 1) or (kz == kw == kh and mem == 0 and G == 1)
+        rounds = blob[r_off:r_off + nr + 1]
+        clen = blob[l_off:l_off + nr]
+        phase = blob[p_off:p_off + nr]
+        assert rounds[0] == 0 and rounds[-1] == nch and np.all(np.diff(rounds.astype(np.int64)) >= 0)
+        assert np.all(clen >= dg.CHUNK) and np.all(clen % dg.CHUNK == 0) and np.all(clen <= 256)
+        assert phase[0] == 0 and np.all(np.diff(phase.astype(np.int64)) >= 0)
+        assert mem == 1 or (arena * es * G) <= emit_da.LDS_BYTES
+        assert arena + 64 < dg.MAX_OFF
+        if kz == 1 and (kw, kh, tw, th) in ((25, 25, 16, 16), (35, 35, 16, 8), (9, 31, 2, 8), (5, 3, 4, 2)) and seen < 6:
+            S = dg.schedule(kw, tw, th, kh=kh, lanes=dg.LANES // G)
+            assert np.array_equal(blob[c_off:c_off + 4 * nch].reshape(-1, 4), S.items)
+            assert np.array_equal(rounds, S.rounds) and np.array_equal(clen, S.chunk_len)
+            assert np.array_equal(phase, S.round_phase)
+            assert np.array_equal(blob[o_off:o_off + tw * th], S.outputs) and arena == S.arena
+            seen += 1
+    assert seen >= 3
+    # one global-memory entry per (square k, element size)
+    glob = [r for r in rows if r[9] == 1]
+    assert sorted(set((r[0], r[3]) for r in glob)) == sorted((k, es) for k in emit_da.KS for es in (2, 4))
+    # one 3-D entry per (cubic k, element size), its schedule as schedule3 makes it
+    box = [r for r in rows if r[2] > 1]
+    assert sorted((r[0], r[3]) for r in box) == sorted((k, es) for k in emit_da.K3 for es in (2, 4))
+    r = [r for r in box if r[0] == 7 and r[3] == 2][0]
+    S = dg.schedule3(7, 7, 7, r[4], r[5], r[6])
+    assert np.array_equal(blob[r[10]:r[10] + 4 * r[11]].reshape(-1, 4), S.items) and r[17] == S.arena
+
+
+@pytest.mark.parametrize("k,tw,th", [(5, 4, 2), (9, 4, 4), (13, 8, 8), (25, 16, 8)])
+def test_sentinel_ties_exact_model(k, tw, th):
+    """16-bit and 32-bit data that equals the sentinel value (the largest
+    element) in most windows: the kernel's exact merge procedure (sentinel
+    reads, clamped A index) still gives the oracle's median."""
+    S = dg.schedule(k, tw, th)
+    t = wl.tie_heavy_plane(17, 21, np.uint8, levels=3, seed=k)
+    for dt, top in ((np.uint16, 0xFFFF), (np.uint32, 0xFFFFFFFF)):
+        img = np.where(t == 0, 0, np.where(t == 1, top - 1, top)).astype(dt)
+        np.testing.assert_array_equal(dg.run_schedule_on_image(S, img, exact_merge_path=True),
+                                      oracle.median_filter(img, k))
+    f = wl.float_specials_plane(13, 19, k)
+    got = dg.run_schedule_on_image(S, f, exact_merge_path=True)
+    assert got.view(np.uint32).tobytes() == oracle.median_filter(f, k).view(np.uint32).tobytes()
+
+
+@pytest.mark.parametrize("box,tile", [((3, 3, 3), (2, 2, 2)), ((5, 5, 5), (4, 4, 2)), ((7, 7, 7), (4, 4, 4)),
+                                      ((5, 3, 7), (2, 2, 4)), ((3, 5, 1), (2, 4, 1)), ((9, 9, 9), (8, 4, 4))])
+def test_3d_schedule_matches_oracle(box, tile):
+    """The 3-D recursion (faces, edges and corners around a box core, split
+    along the longest tile side) reproduces the oracle's box median, with
+    sorted chunks and with the kernel's exact merge procedure."""
+    S = dg.schedule3(*box, *tile)
+    assert (S.fw, S.fh, S.fd) == tuple(box[a] + tile[a] - 1 for a in range(3))
+    for dt, seed in ((np.uint8, 1), (np.uint16, 2), (np.float32, 3)):
+        if dt == np.float32:
+            vol = np.stack([wl.float_specials_plane(9, 11, seed + z) for z in range(7)])
+        else:
+            vol = np.stack([wl.uniform_plane(9, 11, dt, seed + z) for z in range(7)])
+        want = oracle.median_filter_3d(vol, *box)
+        for exact in (False, True):
+            got = dg.run_schedule_on_volume(S, vol, exact_merge_path=exact)
+            assert got.view(np.uint8).tobytes() == want.view(np.uint8).tobytes(), (dt, exact)
