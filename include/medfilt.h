@@ -263,6 +263,22 @@ void mf_plan_destroy(mf_plan plan);
 /* Create a plan, launch it on `stream`, wait for it, destroy it. */
 int32_t median_filter_batched(const mf_image* imgs, int32_t n, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the batched form
+ * without a plan. Same images, conventions and results as
+ * median_filter_batched, but nothing is allocated: the per-image job records
+ * go to a static device array of the library (MF_NOALLOC_MAX_IMAGES records
+ * of 48 bytes, 192 KiB, one per GPU, held until the process ends), and the
+ * kernels (one per group of images sharing a kernel, plus one small launch
+ * per 64 records that writes the records) are enqueued on `stream`; the call
+ * returns without waiting. n must be in [1, MF_NOALLOC_MAX_IMAGES]
+ * (MF_ERR_DIMS otherwise); argument errors as mf_plan_create, before any GPU
+ * work. Every call on one GPU shares that GPU's array and overwrites it:
+ * calls that overlap on one GPU (other streams or threads) race, so the
+ * caller must order them (the same stream orders them). */
+#define MF_NOALLOC_MAX_IMAGES 4096
+int32_t median_filter_batched_noalloc(const mf_image* imgs, int32_t n, void* stream);
+
 /* Differentiable form, forward: median (as median_filter) and argmedian of
  * `planes` contiguous float32 planes of H x W (NCHW-style, plane stride H*W).
  * idx[p] is the plane-local flat index y*W + x of the input pixel the median

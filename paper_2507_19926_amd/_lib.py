@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_PKG, "libmedfilt.so")
 MF_U8, MF_U16, MF_U32, MF_F32 = 0, 1, 2, 3
 MF_BORDER_REPLICATE = 0
 MF_VARIANT_AUTO, MF_VARIANT_OBLIVIOUS, MF_VARIANT_DATA_AWARE, MF_VARIANT_GLOBAL = 0, 1, 2, 3
+MF_NOALLOC_MAX_IMAGES = 4096
 
 STATUS = {
     0: "MF_OK", -1: "MF_ERR_NULL", -2: "MF_ERR_DIMS", -3: "MF_ERR_PITCH", -4: "MF_ERR_DTYPE",
@@ -99,6 +100,8 @@ def lib():
     L.median_filter_3d.restype = i32
     L.mf_max_k_3d.argtypes = []
     L.mf_max_k_3d.restype = i32
+    L.median_filter_batched_noalloc.argtypes = [pim, i32, vp]
+    L.median_filter_batched_noalloc.restype = i32
     L.mf_list_configs.argtypes = [i32, i32, ctypes.POINTER(mf_options), i32]
     L.mf_list_configs.restype = i32
     L.mf_max_k.argtypes = []

@@ -151,7 +151,8 @@ def build(jobs: int | None = None, verbose: bool = False, incremental: bool = Fa
         with open(blob_cpp, "w") as f:
             f.write(text)
     srcs = [os.path.join(CSRC, "mf_api.cpp"), os.path.join(CSRC, "mf_plan.cpp"), os.path.join(CSRC, "mf_data_aware.hip"),
-            os.path.join(CSRC, "mf_autograd.hip"), os.path.join(CSRC, "mf_strip.hip"), os.path.join(CSRC, "mf_peaks.hip"), blob_cpp] + obl_srcs
+            os.path.join(CSRC, "mf_autograd.hip"), os.path.join(CSRC, "mf_strip.hip"), os.path.join(CSRC, "mf_peaks.hip"),
+            os.path.join(CSRC, "mf_noalloc.hip"), blob_cpp] + obl_srcs
     objs = []
     jobs = jobs or min(16, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:

@@ -279,3 +279,13 @@ def median_filter_batched(xs, ks, outs=None):
     _lib.check(_lib.lib().median_filter_batched(arr, len(arr), _stream_handle(dev)))
     return outs
 
+
+def median_filter_batched_noalloc(xs, ks, outs):
+    """Batched filter through the entry point that allocates nothing on the
+    device (job records in the library's static per-GPU table); enqueued on
+    the current stream, not waited for. `outs` must be given: this wrapper
+    allocates nothing either."""
+    arr = _images(xs, outs, ks)
+    dev = xs[0].device
+    _lib.check(_lib.lib().median_filter_batched_noalloc(arr, len(arr), _stream_handle(dev)))
+    return outs

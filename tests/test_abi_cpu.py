@@ -212,6 +212,29 @@ def test_plan_validation():
     L.mf_plan_destroy(None)
 
 
+def test_noalloc_batched_validation():
+    """The no-allocation batched entry rejects bad lists on the host, before
+    any GPU work: NULL list, empty list, more images than its static table,
+    bad images and overlapping destinations."""
+    L = _lib.lib()
+    arr = (_lib.mf_image * 2)()
+    for i in range(2):
+        arr[i].src, arr[i].dst = 0x10000000 + i * 0x100000, 0x20000000 + i * 0x100000
+        arr[i].H, arr[i].W, arr[i].pitch_bytes, arr[i].dtype, arr[i].k, arr[i].border = 16, 16, 16, 0, 3, 0
+    assert L.median_filter_batched_noalloc(None, 1, None) == -1
+    assert L.median_filter_batched_noalloc(arr, 0, None) == -2
+    assert L.median_filter_batched_noalloc(arr, 4097, None) == -2
+    assert "4096" in L.mf_last_error().decode()
+    arr[1].k = 1
+    assert L.median_filter_batched_noalloc(arr, 2, None) == -5
+    arr[1].k = 3
+    arr[1].dtype = 9
+    assert L.median_filter_batched_noalloc(arr, 2, None) == -4
+    arr[1].dtype = 0
+    arr[1].dst = arr[0].src + 8
+    assert L.median_filter_batched_noalloc(arr, 2, None) == -7
+
+
 def test_global_form_validation():
     """Workspace query and the global-memory entry's host checks (no GPU
     work): sizes consistent with the tiles, every error before a launch."""
