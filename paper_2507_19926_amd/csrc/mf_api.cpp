@@ -114,7 +114,7 @@ const OblEntry* find_obl(int k, int tw, int th, int nw, int form, int rows)
 
 // Resolve (dtype, k, opt) to a variant and root tile. Host only.
 int32_t resolve(int32_t dtype, int32_t k, const mf_options* opt, int32_t* variant, int32_t* tw,
-                int32_t* th, const OblEntry** obl, int32_t* group = nullptr)
+                int32_t* th, const OblEntry** obl, int32_t* group = nullptr, int32_t* da_form = nullptr)
 {
     mf_options o = {};
     if (opt) o = *opt;
@@ -123,6 +123,7 @@ int32_t resolve(int32_t dtype, int32_t k, const mf_options* opt, int32_t* varian
     if (o.group != 0 && o.group != 1 && o.group != 2 && o.group != 4)
         return fail(MF_ERR_CONFIG, "tiles per work-group %d not in {0, 1, 2, 4}", o.group);
     if (group) *group = 0;
+    if (da_form) *da_form = 0;
     if ((o.tile_w && (!pow2(o.tile_w) || o.tile_w > k)) || (o.tile_h && (!pow2(o.tile_h) || o.tile_h > k)) ||
         o.tile_w < 0 || o.tile_h < 0)
         return fail(MF_ERR_CONFIG, "root tile %dx%d is not a pair of powers of two <= k=%d", o.tile_w,
@@ -144,11 +145,12 @@ int32_t resolve(int32_t dtype, int32_t k, const mf_options* opt, int32_t* varian
                     *obl = e;
                     return MF_OK;
                 }
-            } else if (mf_da_supports(dtype, k, a.tw, a.th, a.group)) {
+            } else if (mf_da_supports(dtype, k, a.tw, a.th, a.group, 0, a.form)) {
                 *variant = MF_VARIANT_DATA_AWARE;
                 *tw = a.tw;
                 *th = a.th;
                 if (group) *group = a.group;
+                if (da_form) *da_form = a.form;
                 return MF_OK;
             }
             break;  // a stale entry: fall back to the built-in order
@@ -168,17 +170,21 @@ int32_t resolve(int32_t dtype, int32_t k, const mf_options* opt, int32_t* varian
             return fail(MF_ERR_CONFIG, "no oblivious network compiled for k=%d tile %dx%d", k, o.tile_w,
                         o.tile_h);
     }
-    int dtw = o.tile_w, dth = o.tile_h, dg = o.group;
-    if (!dtw && !dth && !dg) {
-        mf_da_default_tile(dtype, k, &dtw, &dth, &dg);
+    // data-aware: form 1 = rounds per recursion level, 2 = rounds over the
+    // whole schedule (3 is the oblivious column-strip form only)
+    int dtw = o.tile_w, dth = o.tile_h, dg = o.group, df = o.form;
+    if (df == 3) return fail(MF_ERR_CONFIG, "form 3 is the oblivious column-strip form (k = 3)");
+    if (!dtw && !dth && !dg && !df) {
+        mf_da_default_tile(dtype, k, &dtw, &dth, &dg, 0, &df);
     }
-    if (!mf_da_supports(dtype, k, dtw, dth, dg))
-        return fail(MF_ERR_CONFIG, "data-aware variant does not support k=%d tile %dx%d group %d", k, dtw, dth,
-                    dg);
+    if (!mf_da_supports(dtype, k, dtw, dth, dg, 0, df))
+        return fail(MF_ERR_CONFIG, "data-aware variant does not support k=%d tile %dx%d group %d form %d", k, dtw,
+                    dth, dg, df);
     *variant = MF_VARIANT_DATA_AWARE;
     *tw = dtw;
     *th = dth;
     if (group) *group = dg;
+    if (da_form) *da_form = df;
     return MF_OK;
 }
 
@@ -220,10 +226,10 @@ int32_t mf_internal_validate(const void* src, const void* dst, int64_t H, int64_
 int32_t mf_internal_fail(int32_t code, const char* msg) { return fail(code, "%s", msg); }
 
 int32_t mf_internal_resolve(int32_t dtype, int32_t k, int32_t* variant, int32_t* tw, int32_t* th,
-                            int32_t* group, MfBatchedKernel* obl_p16, MfBatchedKernel* obl_u32)
+                            int32_t* group, MfBatchedKernel* obl_p16, MfBatchedKernel* obl_u32, int32_t* da_form)
 {
     const OblEntry* e = nullptr;
-    int32_t rc = resolve(dtype, k, nullptr, variant, tw, th, &e, group);
+    int32_t rc = resolve(dtype, k, nullptr, variant, tw, th, &e, group, da_form);
     if (rc) return rc;
     // the column-strip form has no batched kernel: plans use k's default
     // network
@@ -390,9 +396,9 @@ int32_t median_filter_planes(const void* src, void* dst, int64_t planes, int64_t
     if (opt && opt->variant == MF_VARIANT_GLOBAL)
         return global_with_own_workspace(src, dst, planes, plane_stride_bytes, H, W, pitch_bytes, dtype, k, opt,
                                          st);
-    int32_t variant = 0, tw = 0, th = 0, group = 0;
+    int32_t variant = 0, tw = 0, th = 0, group = 0, da_form = 0;
     const OblEntry* e = nullptr;
-    rc = resolve(dtype, k, opt, &variant, &tw, &th, &e, &group);
+    rc = resolve(dtype, k, opt, &variant, &tw, &th, &e, &group, &da_form);
     if (rc) return rc;
     if (variant == MF_VARIANT_OBLIVIOUS) {
         mf_launch_fn fn = (dtype == MF_U8 || dtype == MF_U16) ? e->p16 : e->u32;
@@ -400,7 +406,7 @@ int32_t median_filter_planes(const void* src, void* dst, int64_t planes, int64_t
                           "oblivious kernel launch");
     }
     return hip_status(mf_da_launch(src, dst, (int)planes, plane_stride_bytes, (int)H, (int)W, pitch_bytes, dtype, k,
-                                   tw, th, group, st),
+                                   tw, th, group, st, 0, da_form),
                       "data-aware kernel launch");
 }
 
@@ -459,17 +465,18 @@ int32_t mf_query_options(int32_t dtype, int32_t k, const mf_options* opt, mf_opt
         return MF_OK;
     }
     const OblEntry* e = nullptr;
-    int32_t group = 0;
-    const int32_t rc = resolve(dtype, k, opt, &r.variant, &r.tile_w, &r.tile_h, &e, &group);
+    int32_t group = 0, da_form = 0;
+    const int32_t rc = resolve(dtype, k, opt, &r.variant, &r.tile_w, &r.tile_h, &e, &group, &da_form);
     if (rc) return rc;
     if (e) {
         r.group = e->nw;
         r.form = e->form;
         r.rows = e->ry;
     } else {
-        int tw = 0, th = 0, g = 0;
-        if (!group) mf_da_default_tile(dtype, k, &tw, &th, &g);
+        int tw = 0, th = 0, g = 0, f = 0;
+        if (!group || !da_form) mf_da_default_tile(dtype, k, &tw, &th, &g, 0, &f);
         r.group = group ? group : g;
+        r.form = da_form ? da_form : f;
     }
     *resolved = r;
     return MF_OK;
@@ -542,15 +549,15 @@ int32_t mf_list_configs(int32_t dtype, int32_t k, mf_options* out, int32_t cap)
             }
             ++n;
         }
-        int tw[32], th[32], gr[32];
-        const int m = mf_da_list(dtype, k, tw, th, gr, 32);
+        int tw[32], th[32], gr[32], fm[32];
+        const int m = mf_da_list(dtype, k, tw, th, gr, 32, fm);
         for (int i = 0; i < m && i < 32; ++i) {
             if (n < cap) {
                 out[n].variant = MF_VARIANT_DATA_AWARE;
                 out[n].tile_w = tw[i];
                 out[n].tile_h = th[i];
                 out[n].group = gr[i];
-                out[n].form = 0;
+                out[n].form = fm[i];
                 out[n].rows = 0;
             }
             ++n;

@@ -35,11 +35,13 @@ namespace {
 // one schedule: window k x kh (columns x rows; k x kh x kz for a 3-D box,
 // kz = 1 for planes), element size, root tile tw x th (x tz), tiles per lane
 // (always 1), lane groups per work-group, memory (0: LDS
-// arena, 1: device workspace of the global form), blob offsets of the items,
+// arena, 1: device workspace of the global form), round mode (0: rounds per
+// recursion level, 1: rounds over the whole schedule), blob offsets of the items,
 // round boundaries, per-round chunk lengths, per-round recursion levels and
 // median offsets, arena elements
 struct DaEntry {
-    int k, kh, kz, es, tw, th, tz, tiles, groups, mem, c_off, nchunks, r_off, nrounds, l_off, p_off, o_off, arena;
+    int k, kh, kz, es, tw, th, tz, tiles, groups, mem, mode, c_off, nchunks, r_off, nrounds, l_off, p_off, o_off,
+        arena;
 };
 
 const DaEntry kDaTable[] = {MF_DA_TABLE_ENTRIES};
@@ -307,11 +309,13 @@ mf_dag_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__
     if (last) mf_da_store<E>(gl, dst + plane * plane_stride, H, W, pitch, dtype, a, 1, bx, by);
 }
 
-// 3-D box median (the hierarchical recursion with a third axis): one root
-// tile of tw x th x tz voxels per work-group, its (k+tw-1) x (kh+th-1) x
-// (kz+tz-1) footprint in LDS (each axis clamped), the schedule's rounds, and
-// the tile's medians stored. Rows are pitch bytes apart, slices slice bytes
-// apart; work-group b is tile (b % ntx, b / ntx % nty, b / (ntx*nty)).
+// 3-D box median (the hierarchical recursion with a third axis): G root tiles
+// of tw x th x tz voxels per work-group, side by side along x (G = a.groups
+// lane groups of kDaThreads/G lanes, small tiles filling the work-group),
+// each tile's (k+tw-1) x (kh+th-1) x (kz+tz-1) footprint in its own LDS arena
+// (each axis clamped), the schedule's rounds, and the tiles' medians stored.
+// Rows are pitch bytes apart, slices slice bytes apart; work-group b covers
+// tile columns (b % ntx)*G .. +G-1, row b / ntx % nty, slab b / (ntx*nty).
 template <class E, bool CLAMP>
 __global__ void __launch_bounds__(kDaThreads)
 mf_da3_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, int D, int H, int W,
@@ -320,16 +324,20 @@ mf_da3_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__
     extern __shared__ __align__(16) unsigned char mf_da_lds[];
     constexpr uint32_t kMax = (uint32_t)(E)~(E)0;
     E* lds = reinterpret_cast<E*>(mf_da_lds);
+    const int G = a.groups, L = kDaThreads / G;
+    const int gi = threadIdx.x / L, lt = threadIdx.x - gi * L;
     const int b = blockIdx.x;
     const int bx = b % ntx, by = (b / ntx) % nty, bz = b / (ntx * nty);
     const int fw = a.k + a.tw - 1, fh = a.kh + a.th - 1, fd = a.kz + a.tz - 1;
+    const int fp = fw * fh * fd;
     const int rx = (a.k - 1) / 2, ry = (a.kh - 1) / 2, rz = (a.kz - 1) / 2;
-    const int X0 = bx * a.tw - rx, Y0 = by * a.th - ry, Z0 = bz * a.tz - rz;
-    for (int i = threadIdx.x; i < fw * fh * fd; i += kDaThreads) {
-        const int z = i / (fw * fh), r = i - z * fw * fh;
+    const int Y0 = by * a.th - ry, Z0 = bz * a.tz - rz;
+    for (int i = threadIdx.x; i < G * fp; i += kDaThreads) {
+        const int t = i / fp, e = i - t * fp;
+        const int z = e / (fw * fh), r = e - z * fw * fh;
         const int y = r / fw, x = r - y * fw;
         const int gz = min(max(Z0 + z, 0), D - 1), gy = min(max(Y0 + y, 0), H - 1);
-        const int gx = min(max(X0 + x, 0), W - 1);
+        const int gx = min(max((bx * G + t) * a.tw - rx + x, 0), W - 1);
         const unsigned char* row = src + (long long)gz * slice + (long long)gy * pitch;
         uint32_t v;
         if (dtype == MF_U8) v = row[gx];
@@ -338,20 +346,21 @@ mf_da3_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__
             v = ((const uint32_t*)row)[gx];
             if (dtype == MF_F32) v = mf_da_f32_to_key(v);
         }
-        lds[MF_DA_GUARD + i] = (E)v;
+        lds[t * a.arena + MF_DA_GUARD + e] = (E)v;
     }
-    if (threadIdx.x == 0) lds[MF_DA_GUARD - 1] = (E)kMax;
+    if (threadIdx.x < G) lds[threadIdx.x * a.arena + MF_DA_GUARD - 1] = (E)kMax;
     __syncthreads();
-    mf_da_rounds<E, CLAMP>(lds, a, 0, a.nrounds, threadIdx.x, kDaThreads);
+    mf_da_rounds<E, CLAMP>(lds + gi * a.arena, a, 0, a.nrounds, lt, L);
     const uint32_t* outs = a.blob + a.o_off;
     const int tv = a.tw * a.th * a.tz;
-    for (int p = threadIdx.x; p < tv; p += kDaThreads) {
+    for (int q = threadIdx.x; q < G * tv; q += kDaThreads) {
+        const int t = q / tv, p = q - t * tv;
         const int pz = p / (a.tw * a.th), r = p - pz * a.tw * a.th;
         const int py = r / a.tw, px = r - py * a.tw;
-        const int z = bz * a.tz + pz, y = by * a.th + py, x = bx * a.tw + px;
+        const int z = bz * a.tz + pz, y = by * a.th + py, x = (bx * G + t) * a.tw + px;
         if (z >= D || y >= H || x >= W) continue;
         unsigned char* row = dst + (long long)z * slice + (long long)y * pitch;
-        const uint32_t v = (uint32_t)lds[outs[p]];
+        const uint32_t v = (uint32_t)lds[t * a.arena + outs[p]];
         if (dtype == MF_U8) row[x] = (unsigned char)v;
         else if (dtype == MF_U16) ((uint16_t*)row)[x] = (uint16_t)v;
         else ((uint32_t*)row)[x] = (dtype == MF_F32) ? mf_da_key_to_f32(v) : v;
@@ -383,15 +392,17 @@ const void* da_kernel_for_dtype(int dtype, bool batched)
 
 namespace {
 
-// kh = 0: the square k x k window
-const DaEntry* da_find(int dtype, int k, int tw, int th, int group, int kh = 0)
+// kh = 0: the square k x k window; form 0 = any round mode (the first
+// entry, the default), 1 = rounds per recursion level, 2 = over the whole
+// schedule
+const DaEntry* da_find(int dtype, int k, int tw, int th, int group, int kh = 0, int form = 0)
 {
     const int es = (dtype == MF_U8 || dtype == MF_U16) ? 2 : 4;
     if (kh == 0) kh = k;
     for (int i = 0; i < kDaCount; ++i) {
         const DaEntry& e = kDaTable[i];
         if (e.mem == 0 && e.kz == 1 && e.k == k && e.kh == kh && e.es == es && (tw == 0 || e.tw == tw) &&
-            (th == 0 || e.th == th) && (group == 0 || e.tiles == group))
+            (th == 0 || e.th == th) && (group == 0 || e.tiles == group) && (form == 0 || e.mode == form - 1))
             return &e;
     }
     return nullptr;
@@ -429,22 +440,23 @@ hipError_t da_blob(const uint32_t** out)
 
 }  // namespace
 
-bool mf_da_supports(int dtype, int k, int tw, int th, int group, int kh)
+bool mf_da_supports(int dtype, int k, int tw, int th, int group, int kh, int form)
 {
-    return da_find(dtype, k, tw, th, group, kh) != nullptr;
+    return da_find(dtype, k, tw, th, group, kh, form) != nullptr;
 }
 
 int mf_da_rect_max_side() { return MF_DA_RECT_MAX_SIDE; }
 
-void mf_da_default_tile(int dtype, int k, int* tw, int* th, int* group, int kh)
+void mf_da_default_tile(int dtype, int k, int* tw, int* th, int* group, int kh, int* form)
 {
     const DaEntry* e = da_find(dtype, k, 0, 0, 0, kh);
     *tw = e ? e->tw : 0;
     *th = e ? e->th : 0;
     *group = e ? e->tiles : 0;
+    if (form) *form = e ? e->mode + 1 : 0;
 }
 
-int mf_da_list(int dtype, int k, int* tw, int* th, int* group, int cap)
+int mf_da_list(int dtype, int k, int* tw, int* th, int* group, int cap, int* form)
 {
     const int es = (dtype == MF_U8 || dtype == MF_U16) ? 2 : 4;
     int n = 0;
@@ -455,6 +467,7 @@ int mf_da_list(int dtype, int k, int* tw, int* th, int* group, int cap)
             tw[n] = e.tw;
             th[n] = e.th;
             group[n] = e.tiles;
+            if (form) form[n] = e.mode + 1;
         }
         ++n;
     }
@@ -482,9 +495,10 @@ static MfDaArgs da_args(const DaEntry* e, const uint32_t* blob)
 }
 
 hipError_t mf_da_launch(const void* src, void* dst, int planes, long long plane_stride, int H, int W,
-                        long long pitch, int dtype, int k, int tw, int th, int group, hipStream_t stream, int kh)
+                        long long pitch, int dtype, int k, int tw, int th, int group, hipStream_t stream, int kh,
+                        int form)
 {
-    const DaEntry* e = da_find(dtype, k, tw, th, group, kh);
+    const DaEntry* e = da_find(dtype, k, tw, th, group, kh, form);
     if (!e) return hipErrorInvalidValue;
     const uint32_t* blob = nullptr;
     hipError_t err = da_blob(&blob);
@@ -505,9 +519,10 @@ hipError_t mf_da_launch(const void* src, void* dst, int planes, long long plane_
     return hipSuccess;
 }
 
-hipError_t mf_da_batched(int dtype, int k, int tw, int th, int group, MfBatchedKernel* kern, MfDaArgs* args)
+hipError_t mf_da_batched(int dtype, int k, int tw, int th, int group, MfBatchedKernel* kern, MfDaArgs* args,
+                         int form)
 {
-    const DaEntry* e = da_find(dtype, k, tw, th, group);
+    const DaEntry* e = da_find(dtype, k, tw, th, group, 0, form);
     if (!e) return hipErrorInvalidValue;
     const uint32_t* blob = nullptr;
     hipError_t err = da_blob(&blob);
@@ -666,9 +681,10 @@ hipError_t mf_da3_launch(const void* src, void* dst, int D, int H, int W, long l
     hipError_t err = da_blob(&blob);
     if (err != hipSuccess) return err;
     MfDaArgs a = da_args(e, blob);
-    const int ntx = (W + e->tw - 1) / e->tw, nty = (H + e->th - 1) / e->th, ntz = (D + e->tz - 1) / e->tz;
+    const int bw = e->tw * e->groups;     // voxels of a work-group along x
+    const int ntx = (W + bw - 1) / bw, nty = (H + e->th - 1) / e->th, ntz = (D + e->tz - 1) / e->tz;
     if ((long long)ntx * nty * ntz > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    const size_t lds = (size_t)e->arena * e->es;
+    const size_t lds = (size_t)e->arena * e->es * e->groups;
     void* args[] = {&src, &dst, &D, &H, &W, &pitch, &slice, &dtype, &a, (void*)&ntx, (void*)&nty};
     return hipLaunchKernel(da3_kernel_for_dtype(dtype), dim3(ntx * nty * ntz), dim3(kDaThreads), args, lds, stream);
 }

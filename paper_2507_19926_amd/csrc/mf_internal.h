@@ -54,15 +54,17 @@ hipError_t mf_strip3_launch_u32(const void* src, void* dst, int planes, long lon
 // the square k x k window; otherwise the window is k columns by kh rows (a
 // generated rectangular shape, both sides odd and at most
 // mf_da_rect_max_side()).
+// form: 0 = the default round mode of the entry found, 1 = rounds per
+// recursion level, 2 = rounds over the whole schedule.
 hipError_t mf_da_launch(const void* src, void* dst, int planes, long long plane_stride, int H, int W,
                         long long pitch, int dtype, int k, int tw, int th, int group, hipStream_t stream,
-                        int kh = 0);
-bool mf_da_supports(int dtype, int k, int tw, int th, int group, int kh = 0);
+                        int kh = 0, int form = 0);
+bool mf_da_supports(int dtype, int k, int tw, int th, int group, int kh = 0, int form = 0);
 int mf_da_rect_max_side();
-void mf_da_default_tile(int dtype, int k, int* tw, int* th, int* group, int kh = 0);
-// Data-aware entries for (dtype, k): fills up to cap (tw, th, group) triples,
-// returns the count.
-int mf_da_list(int dtype, int k, int* tw, int* th, int* group, int cap);
+void mf_da_default_tile(int dtype, int k, int* tw, int* th, int* group, int kh = 0, int* form = nullptr);
+// Data-aware entries for (dtype, k): fills up to cap (tw, th, group[, form])
+// tuples, returns the count.
+int mf_da_list(int dtype, int k, int* tw, int* th, int* group, int cap, int* form = nullptr);
 // Batched data-aware kernel for (dtype class, k, tile); the blob pointer and
 // schedule offsets are filled into *args (see mf_da_batched_args).
 struct MfDaArgs {
@@ -71,7 +73,8 @@ struct MfDaArgs {
     int groups;   // lane groups per work-group, each with its own root tiles
     int kz, tz;   // 3-D boxes: box depth and root tile depth (1 for planes)
 };
-hipError_t mf_da_batched(int dtype, int k, int tw, int th, int group, MfBatchedKernel* kern, MfDaArgs* args);
+hipError_t mf_da_batched(int dtype, int k, int tw, int th, int group, MfBatchedKernel* kern, MfDaArgs* args,
+                         int form = 0);
 
 // Global-memory multi-pass data-aware form: square k, root tile tw x th (0 =
 // the library's), lists in a caller workspace of ws_bytes (device pointer,

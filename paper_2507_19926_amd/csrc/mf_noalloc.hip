@@ -23,9 +23,10 @@
 
 int32_t mf_internal_fail(int32_t code, const char* msg);
 int32_t mf_internal_resolve(int32_t dtype, int32_t k, int32_t* variant, int32_t* tw, int32_t* th,
-                            int32_t* group, MfBatchedKernel* obl_p16, MfBatchedKernel* obl_u32);
+                            int32_t* group, MfBatchedKernel* obl_p16, MfBatchedKernel* obl_u32, int32_t* da_form);
 int32_t mf_internal_check_images(const mf_image* imgs, int32_t n);
-unsigned mf_internal_resident_grid(const MfBatchedKernel& k, long long blocks);
+void mf_internal_batched_grids(int n, const MfBatchedKernel* kern, const long long* blocks, const int* k,
+                                unsigned* grid);
 
 // The job records of the last call on this GPU (MF_NOALLOC_MAX_IMAGES x 48
 // bytes). In host code the name is only a symbol handle; kernels get the
@@ -43,7 +44,7 @@ struct JobPack {
 };
 
 struct NaBucket {
-    int variant, k, tw, th, group, packed;
+    int variant, k, tw, th, group, packed;   // packed: the kernel class of the bucket
     MfBatchedKernel kern;
     MfDaArgs da;
     int first, count;        // records [first, first + count) of the static array
@@ -55,6 +56,10 @@ MfJob* g_ptr[kMaxDevices];               // device address of `scratch`, per dev
 NaBucket g_buckets[kMaxBuckets];
 int g_bucket_of[MF_NOALLOC_MAX_IMAGES];
 MfJob g_jobs[MF_NOALLOC_MAX_IMAGES];
+MfBatchedKernel g_kern[kMaxBuckets];     // per-bucket launch shapes of the call
+long long g_blocks[kMaxBuckets];
+int g_k[kMaxBuckets];
+unsigned g_grid[kMaxBuckets];
 
 int32_t hip_fail(hipError_t e, const char* what)
 {
@@ -98,11 +103,16 @@ extern "C" int32_t median_filter_batched_noalloc(const mf_image* imgs, int32_t n
     int nb = 0;
     for (int i = 0; i < n; ++i) {
         const mf_image& m = imgs[i];
-        int32_t variant = 0, tw = 0, th = 0, group = 0;
+        int32_t variant = 0, tw = 0, th = 0, group = 0, da_form = 0;
         MfBatchedKernel kp16 = {}, ku32 = {};
-        rc = mf_internal_resolve(m.dtype, m.k, &variant, &tw, &th, &group, &kp16, &ku32);
+        rc = mf_internal_resolve(m.dtype, m.k, &variant, &tw, &th, &group, &kp16, &ku32, &da_form);
         if (rc) return rc;
-        const int packed = (m.dtype == MF_U8 || m.dtype == MF_U16) ? 1 : 0;
+        // kernel class: the oblivious kernels serve 8- and 16-bit data alike;
+        // the data-aware kernels differ for 8-bit data (no sentinel clamp),
+        // 16-bit and 32-bit data
+        const int packed = variant == MF_VARIANT_DATA_AWARE
+                               ? 8 + (m.dtype == MF_U8 ? 0 : m.dtype == MF_U16 ? 1 : 2) * 4 + da_form
+                               : (m.dtype == MF_U8 || m.dtype == MF_U16) ? 1 : 0;
         int b = 0;
         while (b < nb && !(g_buckets[b].variant == variant && g_buckets[b].k == m.k && g_buckets[b].tw == tw &&
                            g_buckets[b].th == th && g_buckets[b].group == group && g_buckets[b].packed == packed))
@@ -120,7 +130,7 @@ extern "C" int32_t median_filter_batched_noalloc(const mf_image* imgs, int32_t n
             if (variant == MF_VARIANT_OBLIVIOUS) {
                 B.kern = packed ? kp16 : ku32;
             } else {
-                e = mf_da_batched(m.dtype, m.k, tw, th, group, &B.kern, &B.da);
+                e = mf_da_batched(m.dtype, m.k, tw, th, group, &B.kern, &B.da, da_form);
                 if (e != hipSuccess) return hip_fail(e, "data-aware batched kernel");
             }
         }
@@ -155,6 +165,12 @@ extern "C" int32_t median_filter_batched_noalloc(const mf_image* imgs, int32_t n
     for (int b = 0; b < nb; ++b)
         if (g_buckets[b].blocks > 0x7fffffffLL)
             return mf_internal_fail(MF_ERR_DIMS, "a bucket needs more than 2^31-1 work-groups");
+    for (int b = 0; b < nb; ++b) {
+        g_kern[b] = g_buckets[b].kern;
+        g_blocks[b] = g_buckets[b].blocks;
+        g_k[b] = g_buckets[b].k;
+    }
+    mf_internal_batched_grids(nb, g_kern, g_blocks, g_k, g_grid);
     hipStream_t s = (hipStream_t)stream;
     for (int i0 = 0; i0 < n; i0 += kPackJobs) {
         const int cnt = n - i0 < kPackJobs ? n - i0 : kPackJobs;
@@ -173,7 +189,7 @@ extern "C" int32_t median_filter_batched_noalloc(const mf_image* imgs, int32_t n
         int nblocks = (int)B.blocks;
         void* args_obl[] = {&jobs, &njobs, &nblocks};
         void* args_da[] = {&jobs, &njobs, &nblocks, &B.da};
-        e = hipLaunchKernel(B.kern.fn, dim3(mf_internal_resident_grid(B.kern, B.blocks)), dim3(B.kern.threads),
+        e = hipLaunchKernel(B.kern.fn, dim3(g_grid[b]), dim3(B.kern.threads),
                             B.variant == MF_VARIANT_OBLIVIOUS ? args_obl : args_da, B.kern.lds, s);
         if (e != hipSuccess) return hip_fail(e, "batched kernel launch");
     }

@@ -65,7 +65,7 @@ OFF_BITS = 18       # arena offsets and sizes share a 32-bit word
 MAX_OFF = 1 << OFF_BITS
 MAX_LEN = 1 << (32 - OFF_BITS)
 SORT_MAX = 32       # largest per-lane sorting network
-ROUNDS = "phase"    # round assignment: "asap" over the whole DAG, or "phase"
+ROUNDS = "asap"     # round assignment: "asap" over the whole DAG, or "phase"
                     # (ASAP within each recursion level)
 GUARD = 4           # arena elements before the footprint; slot GUARD-1 holds the sentinel
 SENTINEL_SLOT = GUARD - 1
@@ -479,34 +479,39 @@ def _pow2_at_least(n: int) -> int:
 
 
 def schedule(k: int, tw: int, th: int, chunk: int = CHUNK, lanes: int = LANES,
-             kh: int | None = None) -> Schedule:
+             kh: int | None = None, rounds: str | None = None) -> Schedule:
     """Rounds of sorts and windowed merges for root tile tw x th. A round's
     merges are cut into chunks of one length C = a multiple of `chunk`, at
     least ceil(outputs / lanes), so that one round keeps about `lanes`
     threads busy with chains as short as the round allows (a lane runs a
-    co-rank search, then C sequential merge steps)."""
+    co-rank search, then C sequential merge steps). `rounds` is "phase"
+    (ASAP within each recursion level) or "asap" (over the whole schedule;
+    fewer rounds and barriers, more LDS), default ROUNDS."""
     kh = k if kh is None else kh
     D, outs = build_dag(k, tw, th, kh)
-    S = _schedule_dag(D, outs, k + tw - 1, (kh + th - 1), 1, tw * th, chunk, lanes)
+    S = _schedule_dag(D, outs, k + tw - 1, (kh + th - 1), 1, tw * th, chunk, lanes, rounds)
     S.k, S.tw, S.th, S.kh = k, tw, th, kh
     return S
 
 
 def schedule3(kx: int, ky: int, kz: int, tx: int, ty: int, tz: int, chunk: int = CHUNK,
-              lanes: int = LANES) -> Schedule:
+              lanes: int = LANES, rounds: str | None = None) -> Schedule:
     """As schedule, for the 3-D box kx x ky x kz and root tile tx x ty x tz."""
     D, outs = build_dag3(kx, ky, kz, tx, ty, tz)
-    S = _schedule_dag(D, outs, kx + tx - 1, ky + ty - 1, kz + tz - 1, tx * ty * tz, chunk, lanes)
+    S = _schedule_dag(D, outs, kx + tx - 1, ky + ty - 1, kz + tz - 1, tx * ty * tz, chunk, lanes, rounds)
     S.k, S.tw, S.th, S.kh, S.kz, S.tz = kx, tx, ty, ky, kz, tz
     return S
 
 
-def _schedule_dag(D: Dag, outs: list, fw: int, fh: int, fd: int, npx: int, chunk: int, lanes: int) -> Schedule:
+def _schedule_dag(D: Dag, outs: list, fw: int, fh: int, fd: int, npx: int, chunk: int, lanes: int,
+                  rounds: str | None = None) -> Schedule:
     """Rounds, LDS allocation and items of a DAG whose footprint is
     fw x fh x fd (fd = 1 for planes) and whose tile has npx outputs."""
     propagate_windows(D, outs)
     work = [n for n in D.nodes if (n.a is not None or n.line is not None) and n.need_hi > n.need_lo]
-    if ROUNDS == "asap":
+    mode = ROUNDS if rounds is None else rounds
+    assert mode in ("asap", "phase")
+    if mode == "asap":
         # rounds: ASAP over the whole DAG (a node runs in the round after its
         # last input), so the reductions that build the next level's added
         # lists overlap the current level's core merge
@@ -583,6 +588,7 @@ def _schedule_dag(D: Dag, outs: list, fw: int, fh: int, fd: int, npx: int, chunk
     items = []
     rounds = [0]
     clens = []
+    st_mode = mode
     cmax = chunk
     for r, group in enumerate(order):
         merges = [n for n in group if n.a is not None]
@@ -665,17 +671,18 @@ def _schedule_dag(D: Dag, outs: list, fw: int, fh: int, fd: int, npx: int, chunk
     nmerge_items = int(np.sum((it[:, 3] & SORT_FLAG) == 0)) if len(it) else 0
     # compare-exchanges of the sorting networks the sort items run
     sort_ces = sum(_OEMS_CES[int(w3) & 0xFFFF] for w3 in it[:, 3] if int(w3) & SORT_FLAG) if len(it) else 0
-    st = {"rounds": len(order), "chunks": nmerge_items, "sorts": len(items) - nmerge_items,
+    st = {"rounds": len(order), "chunks": nmerge_items, "round_mode": st_mode, "sorts": len(items) - nmerge_items,
           "merge_outputs": merge_outputs, "sort_outputs": sort_outputs,
           "per_pixel_by_role": {r: round(v / npx, 1) for r, v in sorted(by_role.items())},
           "per_pixel_outputs": merge_outputs / npx, "arena": arena,
           "per_pixel_sort_ces": sort_ces / npx,
           "merges": len(merges)}
-    # recursion level of each round (non-decreasing): the deepest level any of
-    # its nodes belongs to, so far
+    # recursion level of each round (non-decreasing): the shallowest level
+    # among its nodes (the level whose core the round advances; with ASAP
+    # rounds later levels' sorts and reductions run early), as a running max
     rphase, top = [], 0
     for group in order:
-        top = max(top, max(n.phase for n in group))
+        top = max(top, min(n.phase for n in group))
         rphase.append(top)
     return Schedule(0, 0, 0, fw, fh, np.array(items, dtype=np.uint32).reshape(-1, 4),
                     np.array(rounds, dtype=np.int32), np.array(clens, dtype=np.int32),

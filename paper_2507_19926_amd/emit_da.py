@@ -57,42 +57,53 @@ def _cost(S: dagen.Schedule) -> float:
 LDS_BUDGETS = (LDS_BYTES // 3, LDS_BYTES // 2, LDS_BYTES)
 
 
+# round modes (dagen.schedule): index 0 = rounds per recursion level, 1 =
+# rounds over the whole schedule (fewer barriers, more LDS); the table stores
+# the index, mf_options.form = index + 1
+MODES = ("phase", "asap")
+
+
 def _schedule_or_none(key):
-    kw, kh, tw, th = key
+    kw, kh, tw, th = key[:4]
+    mode = key[4] if len(key) > 4 else dagen.ROUNDS
     try:
-        return dagen.schedule(kw, tw, th, kh=kh)
+        return dagen.schedule(kw, tw, th, kh=kh, rounds=mode)
     except (AssertionError, RuntimeError):
         return None
 
 
 def candidates(k: int, elem_bytes: int, cache: dict, kh: int | None = None,
-               budgets=LDS_BUDGETS):
-    """(tile_w, tile_h, tiles per work-group) options for a k x kh window
-    (kh defaults to k), best first.
+               budgets=LDS_BUDGETS, modes=("asap",)):
+    """(tile_w, tile_h, round mode index) options for a k x kh window (kh
+    defaults to k), best first.
 
     One root tile per work-group. For each LDS budget (3, 2 or 1 work-groups
-    per CU) the root tile with the lowest estimated work whose arena fits;
-    duplicates removed. More work-groups per CU hide more of the merge rounds'
-    latency, larger tiles amortise more work: the tuner decides."""
+    per CU) and round mode, the root tile with the lowest estimated work whose
+    arena fits; duplicates removed. More work-groups per CU hide more of the
+    merge rounds' latency, larger tiles amortise more work, whole-schedule
+    rounds need fewer barriers but more LDS: the tuner decides."""
     kh = k if kh is None else kh
     out = []
-    for budget in budgets:
-        best = None
-        for (tw, th) in tile_options(k, kh):
-            key = (k, kh, tw, th)
-            if key not in cache:
-                cache[key] = _schedule_or_none(key)
-            S = cache[key]
-            if S is None or S.arena * elem_bytes > budget:
-                continue
-            c = _cost(S)
-            if best is None or c < best[0]:
-                best = (c, tw, th)
-        if best is not None and (best[1], best[2], 1) not in out:
-            out.append((best[1], best[2], 1))
+    for mode in modes:
+        mi = MODES.index(mode)
+        for budget in budgets:
+            best = None
+            for (tw, th) in tile_options(k, kh):
+                key = (k, kh, tw, th, mode)
+                if key not in cache:
+                    cache[key] = _schedule_or_none(key)
+                S = cache[key]
+                if S is None or S.arena * elem_bytes > budget:
+                    continue
+                c = _cost(S)
+                if best is None or c < best[0]:
+                    best = (c, tw, th)
+            if best is not None and (best[1], best[2], mi) not in out:
+                out.append((best[1], best[2], mi))
     assert out, k
-    # largest tile (least work) first: the default without a tuned table
-    out.sort(key=lambda c: -c[0] * c[1])
+    # largest tile (least work) first, whole-schedule rounds first among equals:
+    # the default without a tuned table
+    out.sort(key=lambda c: (-c[0] * c[1], -c[2]))
     return out
 
 
@@ -117,10 +128,11 @@ def lane_groups(S: dagen.Schedule, elem_bytes: int = 4) -> int:
 def global_tile(k: int, cache: dict):
     """Root tile of the global-memory form for a square k x k window: the
     lowest estimated work among the candidates whose arena the item format
-    can address, with no LDS budget (the lists live in a device workspace)."""
+    can address, with no LDS budget (the lists live in a device workspace);
+    rounds per recursion level (each pass then holds two whole levels)."""
     best = None
     for (tw, th) in tile_options(k, k):
-        key = (k, k, tw, th)
+        key = (k, k, tw, th, "phase")
         if key not in cache:
             cache[key] = _schedule_or_none(key)
         S = cache[key]
@@ -147,7 +159,7 @@ def tile3(k: int, elem_bytes: int, cache3: dict):
             continue
         if t not in cache3.setdefault(k, {}):
             try:
-                cache3[k][t] = dagen.schedule3(k, k, k, *t)
+                cache3[k][t] = dagen.schedule3(k, k, k, *t, rounds="asap")
             except (AssertionError, RuntimeError):
                 cache3[k][t] = None
         S = cache3[k][t]
@@ -161,8 +173,8 @@ def tile3(k: int, elem_bytes: int, cache3: dict):
 
 def choose_tile(k: int, elem_bytes: int, cache: dict, kh: int | None = None):
     kh = k if kh is None else kh
-    tw, th, _ = candidates(k, elem_bytes, cache, kh)[0]
-    return (k, kh, tw, th)
+    tw, th, mi = candidates(k, elem_bytes, cache, kh)[0]
+    return (k, kh, tw, th, MODES[mi])
 
 
 def windows() -> list:
@@ -172,7 +184,8 @@ def windows() -> list:
 
 def generate(out_dir: str, workers: int | None = None) -> dict:
     os.makedirs(out_dir, exist_ok=True)
-    keys = [(kw, kh, tw, th) for (kw, kh) in windows() for (tw, th) in tile_options(kw, kh)]
+    keys = [(kw, kh, tw, th, mode) for (kw, kh) in windows() for (tw, th) in tile_options(kw, kh)
+            for mode in (MODES if kw == kh else ("asap",))]
     # largest first so that the pool's tail is short
     keys.sort(key=lambda t: -(t[0] + t[2]) * (t[1] + t[3]))
     workers = workers or min(8, os.cpu_count() or 1)
@@ -213,26 +226,31 @@ def generate(out_dir: str, workers: int | None = None) -> dict:
             # 32-bit elements share a CU, the budget most square windows up
             # to k = 31 are tuned to
             if kw == kh:
-                opts = [c + (1,) for c in candidates(kw, es, cache)]
+                opts = [(tw, th, 1, 1, mi) for (tw, th, mi) in candidates(kw, es, cache, modes=MODES)]
             else:
                 # small tiles run several to a work-group in lane groups;
                 # their schedule is cut for the group's lanes
-                tw, th, T = candidates(kw, 4, cache, kh, LDS_BUDGETS[:1])[0]
-                opts = [(tw, th, T, lane_groups(cache[(kw, kh, tw, th)]))]
-            for (tw, th, T, G) in opts:
-                key = (kw, kh, tw, th, G)
-                S = cache[key[:4]] if G == 1 else dagen.schedule(kw, tw, th, kh=kh, lanes=dagen.LANES // G)
+                tw, th, mi = candidates(kw, 4, cache, kh, LDS_BUDGETS[:1])[0]
+                opts = [(tw, th, 1, lane_groups(cache[(kw, kh, tw, th, MODES[mi])]), mi)]
+            for (tw, th, T, G, mi) in opts:
+                key = (kw, kh, tw, th, G, MODES[mi])
+                S = cache[(kw, kh, tw, th, MODES[mi])] if G == 1 else \
+                    dagen.schedule(kw, tw, th, kh=kh, lanes=dagen.LANES // G, rounds=MODES[mi])
                 assert S.arena * (es if kw == kh else 4) * T * G <= LDS_BYTES
-                entries.append((kw, kh, 1, es, tw, th, 1, T, G, 0) + place(S, key))
+                entries.append((kw, kh, 1, es, tw, th, 1, T, G, 0, mi) + place(S, key))
         # global-memory form (square windows): lists in a device workspace,
         # so the tile is not bounded by the LDS
         for k in KS:
             tw, th = global_tile(k, cache)
-            entries.append((k, k, 1, es, tw, th, 1, 1, 1, 1) + place(cache[(k, k, tw, th)], (k, k, tw, th, 1)))
-        # 3-D boxes
+            entries.append((k, k, 1, es, tw, th, 1, 1, 1, 1, 0) +
+                           place(cache[(k, k, tw, th, "phase")], (k, k, tw, th, 1, "phase")))
+        # 3-D boxes; small tiles run several to a work-group in lane groups
         for k in K3:
             t = tile3(k, es, cache3)
-            entries.append((k, k, k, es) + t + (1, 1, 0) + place(cache3[k][t], (k, k, k) + t))
+            G = lane_groups(cache3[k][t], es)
+            S = cache3[k][t] if G == 1 else dagen.schedule3(k, k, k, *t, lanes=dagen.LANES // G, rounds="asap")
+            assert S.arena * es * G <= LDS_BYTES
+            entries.append((k, k, k, es) + t + (1, G, 0, 1) + place(S, (k, k, k) + t + (G,)))
     blob = np.concatenate(words).astype("<u4")
     bpath = os.path.join(out_dir, "mf_da_blob.bin")
     data = blob.tobytes()
@@ -241,7 +259,8 @@ def generate(out_dir: str, workers: int | None = None) -> dict:
             f.write(data)
     lines = ["// Generated by emit_da.py: data-aware schedules, one entry per",
              "// (k_w, k_h, k_z, element size, root tile t_w x t_h x t_z, tiles per lane,",
-             "// lane groups, memory: 0 = LDS arena, 1 = device workspace).",
+             "// lane groups, memory: 0 = LDS arena, 1 = device workspace, round mode:",
+             "// 0 = per recursion level, 1 = over the whole schedule).",
              "#pragma once",
              "#define MF_DA_BLOB_WORDS %d" % len(blob),
              "#define MF_DA_CHUNK %d" % dagen.CHUNK,

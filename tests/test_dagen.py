@@ -79,8 +79,8 @@ def test_rect_lane_groups(kw, kh):
     that divides the lanes, G arenas of 32-bit elements fit half the LDS, and
     the schedule cut for G lane groups still computes the oracle's median."""
     cache = {}
-    tw, th, _ = emit_da.candidates(kw, 4, cache, kh, emit_da.LDS_BUDGETS[:1])[0]
-    G = emit_da.lane_groups(cache[(kw, kh, tw, th)])
+    tw, th, mi = emit_da.candidates(kw, 4, cache, kh, emit_da.LDS_BUDGETS[:1])[0]
+    G = emit_da.lane_groups(cache[(kw, kh, tw, th, emit_da.MODES[mi])])
     assert 1 <= G <= emit_da.MAX_GROUPS and dg.LANES % G == 0 and G & (G - 1) == 0
     S = dg.schedule(kw, tw, th, kh=kh, lanes=dg.LANES // G)
     assert G * S.arena * 4 <= emit_da.LDS_BYTES // 2
@@ -113,9 +113,9 @@ def test_blob_layout_as_the_kernel_reads_it(tmp_path):
             for m in re.finditer(r"\{([0-9, ]+)\}", text)]
     assert len(rows) == info["entries"]
     seen = 0
-    for (kw, kh, kz, es, tw, th, tz, T, G, mem, c_off, nch, r_off, nr, l_off, p_off, o_off, arena) in rows:
-        assert T == 1 and G >= 1 and c_off % 4 == 0 and mem in (0, 1)
-        assert (kz, tz) == (1, 1) or (kz == kw == kh and mem == 0 and G == 1)
+    for (kw, kh, kz, es, tw, th, tz, T, G, mem, mode, c_off, nch, r_off, nr, l_off, p_off, o_off, arena) in rows:
+        assert T == 1 and G >= 1 and c_off % 4 == 0 and mem in (0, 1) and mode in (0, 1)
+        assert (kz, tz) == (1, 1) or (kz == kw == kh and mem == 0)
         rounds = blob[r_off:r_off + nr + 1]
         clen = blob[l_off:l_off + nr]
         phase = blob[p_off:p_off + nr]
@@ -125,7 +125,7 @@ def test_blob_layout_as_the_kernel_reads_it(tmp_path):
         assert mem == 1 or (arena * es * G) <= emit_da.LDS_BYTES
         assert arena + 64 < dg.MAX_OFF
         if kz == 1 and (kw, kh, tw, th) in ((25, 25, 16, 16), (35, 35, 16, 8), (9, 31, 2, 8), (5, 3, 4, 2)) and seen < 6:
-            S = dg.schedule(kw, tw, th, kh=kh, lanes=dg.LANES // G)
+            S = dg.schedule(kw, tw, th, kh=kh, lanes=dg.LANES // G, rounds=emit_da.MODES[mode])
             assert np.array_equal(blob[c_off:c_off + 4 * nch].reshape(-1, 4), S.items)
             assert np.array_equal(rounds, S.rounds) and np.array_equal(clen, S.chunk_len)
             assert np.array_equal(phase, S.round_phase)
@@ -134,13 +134,17 @@ def test_blob_layout_as_the_kernel_reads_it(tmp_path):
     assert seen >= 3
     # one global-memory entry per (square k, element size)
     glob = [r for r in rows if r[9] == 1]
+    assert all(r[10] == 0 for r in glob)
     assert sorted(set((r[0], r[3]) for r in glob)) == sorted((k, es) for k in emit_da.KS for es in (2, 4))
     # one 3-D entry per (cubic k, element size), its schedule as schedule3 makes it
     box = [r for r in rows if r[2] > 1]
     assert sorted((r[0], r[3]) for r in box) == sorted((k, es) for k in emit_da.K3 for es in (2, 4))
     r = [r for r in box if r[0] == 7 and r[3] == 2][0]
-    S = dg.schedule3(7, 7, 7, r[4], r[5], r[6])
-    assert np.array_equal(blob[r[10]:r[10] + 4 * r[11]].reshape(-1, 4), S.items) and r[17] == S.arena
+    S = dg.schedule3(7, 7, 7, r[4], r[5], r[6], rounds="asap")
+    assert np.array_equal(blob[r[11]:r[11] + 4 * r[12]].reshape(-1, 4), S.items) and r[18] == S.arena
+    # both round modes are offered for square windows
+    sq = [r for r in rows if r[2] == 1 and r[0] == r[1] and r[9] == 0 and r[0] == 25]
+    assert {r[10] for r in sq} == {0, 1}
 
 
 @pytest.mark.parametrize("k,tw,th", [(5, 4, 2), (9, 4, 4), (13, 8, 8), (25, 16, 8)])

@@ -85,3 +85,25 @@ def test_mixed_batch_workload_sampled():
         got = o.cpu().numpy()[ys, xs_]
         assert np.array_equal(got, oracle.median_points(a, k, ys, xs_)), (i, k, a.dtype, a.shape)
     plan.close()
+
+
+def test_batched_data_aware_8_and_16_bit_apart():
+    """Data-aware images of one k, tile and 16-bit element size but different
+    dtypes run different kernels (16-bit data can equal the merge sentinel,
+    8-bit data cannot): a batch mixing them, the 16-bit images full of the
+    largest value, matches the oracle image by image."""
+    from paper_2507_19926_amd import _lib
+    k = 25
+    assert _lib.query_config(_lib.MF_U16, k)[0] == _lib.MF_VARIANT_DATA_AWARE
+    imgs = []
+    for i in range(6):
+        t = wl.tie_heavy_plane(40 + 3 * i, 57 + 5 * i, np.uint8, levels=3, seed=i)
+        if i % 2:
+            imgs.append(np.where(t == 0, 0, np.where(t == 1, 0xFFFE, 0xFFFF)).astype(np.uint16))
+        else:
+            imgs.append((t * 100).astype(np.uint8))
+    xs = [torch.from_numpy(a).cuda() for a in imgs]
+    outs = median_filter_batched(xs, [k] * len(xs))
+    torch.cuda.synchronize()
+    for i, (a, o) in enumerate(zip(imgs, outs)):
+        assert o.cpu().numpy().tobytes() == oracle.median_filter(a, k).tobytes(), i
