@@ -85,9 +85,10 @@ __device__ __forceinline__ void mf_da_sortnet(uint32_t* v)
                     }
 }
 
-// Sort item: the n footprint values at base + i*stride (padded to N with the
-// sentinel), sorted by the network; ranks [lo, lo+cnt) are written from
-// out, followed by the sentinel.
+// Sort item: the n*L footprint values at base + j*lstep + i*stride (L
+// parallel lines of n values; padded to N with the sentinel), sorted by the
+// network; ranks [lo, lo+cnt) are written from out, followed by MF_DA_SENT
+// sentinels.
 template <class E, int N>
 __device__ __forceinline__ void mf_da_sort(E* __restrict__ gl, const uint4 d)
 {
@@ -96,63 +97,177 @@ __device__ __forceinline__ void mf_da_sort(E* __restrict__ gl, const uint4 d)
     const int base = (int)(d.x & kMask), n = (int)(d.x >> 18);
     const int stride = (int)(d.y & kMask), lo = (int)(d.y >> 18);
     const int oo = (int)(d.z & kMask), cnt = (int)(d.z >> 18);
+    const int lines = (int)((d.w >> 6) & 7u), lstep = (int)((d.w >> 9) & ((1u << 22) - 1));
+    const int total = n * lines, back = lstep - n * stride;
     uint32_t v[N];
+    int e = 0, off = base;
 #pragma unroll
-    for (int i = 0; i < N; ++i) v[i] = i < n ? (uint32_t)gl[base + i * stride] : kMax;
+    for (int i = 0; i < N; ++i) {
+        v[i] = i < total ? (uint32_t)gl[off] : kMax;
+        // next value: along the line, or the first of the next line
+        ++e;
+        off += stride;
+        const bool wrap = e == n;
+        e = wrap ? 0 : e;
+        off = wrap ? off + back : off;
+    }
     mf_da_sortnet<N>(v);
     E* out = gl + oo - lo;
 #pragma unroll
     for (int i = 0; i < N; ++i)
         if (i >= lo && i < lo + cnt) out[i] = (E)v[i];
-    gl[oo + cnt] = (E)kMax;
+#pragma unroll
+    for (int i = 0; i < MF_DA_SENT; ++i) gl[oo + cnt + i] = (E)kMax;
+}
+
+// Four consecutive 32-bit elements gl[e..e+3].
+template <class E>
+__device__ __forceinline__ void mf_da_get4(const E* __restrict__ gl, int e, uint32_t* v)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = (uint32_t)gl[e + i];
+}
+
+// Two 16-bit values per 32-bit register (element 2j in the low half).
+typedef unsigned short mf_u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t mf_pk_min(uint32_t x, uint32_t y)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(mf_u16x2, x),
+                                                                  __builtin_bit_cast(mf_u16x2, y)));
+}
+__device__ __forceinline__ uint32_t mf_pk_max(uint32_t x, uint32_t y)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(mf_u16x2, x),
+                                                                  __builtin_bit_cast(mf_u16x2, y)));
+}
+// Per half, 1 where x > y, else 0: min(max(x - y, 0), 1) on both halves at
+// once. Written as the two instructions themselves: the compiler otherwise
+// turns the expression into per-half compares and selects.
+__device__ __forceinline__ uint32_t mf_pk_gt01(uint32_t x, uint32_t y)
+{
+    uint32_t d, r;
+    asm("v_pk_sub_u16 %0, %1, %2 clamp" : "=v"(d) : "v"(x), "v"(y));
+    asm("v_pk_min_u16 %0, %1, %2" : "=v"(r) : "v"(d), "s"(0x00010001u));
+    return r;
+}
+__device__ __forceinline__ uint32_t mf_swap16(uint32_t x) { return __builtin_amdgcn_alignbit(x, x, 16); }
+
+// Four consecutive 16-bit elements from byte offset x (even) on, as the
+// pairs (x, x+2) and (x+4, x+6): the three aligned dwords that hold them,
+// shifted into place (v_alignbit takes the shift modulo 32, so x * 8 gives 0
+// or 16).
+__device__ __forceinline__ void mf_da_get4_pk(const unsigned char* __restrict__ gb, uint32_t x, uint32_t& lo,
+                                              uint32_t& hi)
+{
+    const uint32_t* __restrict__ w = reinterpret_cast<const uint32_t*>(gb + (x & ~3u));
+    const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
+    lo = __builtin_amdgcn_alignbit(w1, w0, x << 3);
+    hi = __builtin_amdgcn_alignbit(w2, w1, x << 3);
 }
 
 // Merge chunk: co-rank of rank r0 in (A window, B window), A first on ties,
-// by `steps` halving steps; then C merge steps. The element after each input
-// window is the sentinel or a list element ranked after every output this
-// chunk must produce, so no step tests for an exhausted input; steps past the
-// chunk's needed outputs write into the list's own padding. CLAMP keeps the A
-// index at the window end: needed when data can equal the sentinel value
-// (16-bit and 32-bit data), not for 8-bit data held in 16-bit elements.
+// over a range of fewer than 2^steps positions; then the chunk's nvalid
+// outputs, four per step. A step reads A[ia..ia+3] and B[ib..ib+3]
+// (independent loads, one dependent round trip per four outputs): the four
+// smallest of the eight are min(A[ia+i], B[ib+3-i]) for i = 0..3 (a
+// half-cleaner), element i coming from A exactly when A[ia+i] <= B[ib+3-i];
+// a bitonic sort of four puts them in order. The
+// elements after each input window are sentinels or list elements ranked
+// after every output this chunk must produce, so no step tests for an
+// exhausted input; the at most three outputs of the last step past nvalid
+// land in the list's sentinel slots, which the lane of the merge's last chunk
+// rewrites afterwards. Chunk outputs start at multiples of four elements, so
+// every step writes one aligned run of four. CLAMP keeps the A index at the
+// window end: needed when data can equal the sentinel value (16-bit and
+// 32-bit data), not for 8-bit data held in 16-bit elements.
 template <class E, bool CLAMP>
-__device__ __forceinline__ void mf_da_merge(E* __restrict__ gl, const uint4 d, const int C)
+__device__ __forceinline__ void mf_da_merge(E* __restrict__ gl, const uint4 d)
 {
     constexpr uint32_t kMask = (1u << 18) - 1;
     constexpr uint32_t kMax = (uint32_t)(E)~(E)0;
-    const E* __restrict__ A = gl + (d.x & kMask);
-    const E* __restrict__ B = gl + (d.y & kMask);
+    const int ao = (int)(d.x & kMask), bo = (int)(d.y & kMask);
+    const E* __restrict__ A = gl + ao;
+    const E* __restrict__ B = gl + bo;
     const int na = (int)(d.x >> 18), nb = (int)(d.y >> 18);
-    E* __restrict__ out = gl + (d.z & kMask);
+    const int oo = (int)(d.z & kMask);
     const int nvalid = (int)(d.z >> 18);
     const int r0 = (int)(d.w & kMask), steps = (int)((d.w >> 18) & 15u);
+    // co-rank: pos = lo + #{t in [lo, hi): A[t] <= B[r0-1-t]} (a prefix, the
+    // windows being sorted), by halving steps. A probe past the range reads
+    // A[hi-1] instead; when that one is taken every position is, and pos
+    // becomes hi, the answer. Extra steps at the top (2^s above the range)
+    // leave pos unchanged, so the wave runs the largest step count of its
+    // lanes as a uniform loop: its first active lane holds it, the chunks of
+    // a round being ordered by decreasing step count.
     const int hi = min(r0, na);
     int pos = max(0, r0 - nb);
-    for (int s = steps - 1; s >= 0; --s) {
-        const int t = pos + (1 << s) - 1;
-        const int tc = min(t, hi - 1);
-        const uint32_t av = A[tc], bv = B[r0 - 1 - tc];
-        pos = (t < hi && av <= bv) ? t + 1 : pos;
+    const E* __restrict__ Bm = B + (r0 - 1);
+    const int sw = __builtin_amdgcn_readfirstlane(steps);
+    for (int s = sw - 1; s >= 0; --s) {
+        const int tc = min(pos + (1 << s) - 1, hi - 1);
+        const uint32_t av = A[tc], bv = Bm[-tc];
+        pos = av <= bv ? tc + 1 : pos;
     }
     int ia = pos;
-    uint32_t a = A[ia], b = B[r0 - ia];
-    const E* __restrict__ Bq = B + r0 + 1;     // b of step q is Bq[q - ia]
-    for (int q0 = 0; q0 < C; q0 += 4) {
+    const int br = bo + r0;                // B's head of step q0 is element br + q0 - ia
+    if constexpr (sizeof(E) == 2) {
+        // the step on pairs: (a0,a1) meets (b3,b2) and (a2,a3) meets (b1,b0);
+        // an A element is taken unless it exceeds its partner, i.e. unless
+        // their saturating difference is nonzero
+        // the heads as byte offsets from the arena base
+        const unsigned char* __restrict__ gb = reinterpret_cast<const unsigned char*>(gl);
+        uint32_t xa = 2u * (uint32_t)(ao + ia), xb = 2u * (uint32_t)(br - ia);
+        for (int q0 = 0; q0 < nvalid; q0 += 4) {
+            uint32_t a01, a23, b01, b23;
+            mf_da_get4_pk(gb, xa, a01, a23);
+            mf_da_get4_pk(gb, xb, b01, b23);
+            const uint32_t r32 = mf_swap16(b23), r10 = mf_swap16(b01);
+            const uint32_t c01 = mf_pk_min(a01, r32), c23 = mf_pk_min(a23, r10);
+            const uint32_t gt = mf_pk_gt01(a01, r32) + mf_pk_gt01(a23, r10);
+            const int nA = 4 - (int)((gt & 0xffffu) + (gt >> 16));
+            // bitonic sort of four
+            const uint32_t x01 = mf_pk_min(c01, c23), x23 = mf_pk_max(c01, c23);
+            const uint32_t s01 = mf_swap16(x01), s23 = mf_swap16(x23);
+            const uint32_t y01 = (mf_pk_min(x01, s01) & 0xffffu) | (mf_pk_max(x01, s01) & 0xffff0000u);
+            const uint32_t y23 = (mf_pk_min(x23, s23) & 0xffffu) | (mf_pk_max(x23, s23) & 0xffff0000u);
+            *reinterpret_cast<uint2*>(gl + oo + q0) = make_uint2(y01, y23);
+            int ia2 = ia + nA;
+            if constexpr (CLAMP) ia2 = min(ia2, na);
+            xa += 2u * (uint32_t)(ia2 - ia);
+            xb += 8u - 2u * (uint32_t)(ia2 - ia);
+            ia = ia2;
+        }
+    } else {
+        for (int q0 = 0; q0 < nvalid; q0 += 4) {
+            uint32_t a[4], b[4], c[4];
+            mf_da_get4<E>(gl, ao + ia, a);
+            mf_da_get4<E>(gl, br + q0 - ia, b);
+            int nA = 0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const bool take = a <= b;
-            out[q0 + u] = (E)min(a, b);
-            ia += take ? 1 : 0;
+            for (int i = 0; i < 4; ++i) {
+                const bool takeA = a[i] <= b[3 - i];
+                c[i] = takeA ? a[i] : b[3 - i];
+                nA += takeA ? 1 : 0;
+            }
+            // bitonic sort of four
+            const uint32_t x0 = min(c[0], c[2]), x2 = max(c[0], c[2]);
+            const uint32_t x1 = min(c[1], c[3]), x3 = max(c[1], c[3]);
+            *reinterpret_cast<uint4*>(gl + oo + q0) =
+                make_uint4(min(x0, x1), max(x0, x1), min(x2, x3), max(x2, x3));
+            ia += nA;
             if constexpr (CLAMP) ia = min(ia, na);
-            a = A[ia];
-            b = Bq[q0 + u - ia];
         }
     }
-    if (d.w & (1u << 22)) out[nvalid] = (E)kMax;
+    if (d.w & (1u << 22)) {
+#pragma unroll
+        for (int i = 0; i < MF_DA_SENT; ++i) gl[oo + nvalid + i] = (E)kMax;
+    }
 }
 
 // Footprints of G root tiles (bx*G + t, by) -> arenas gl + t*arena, after
-// the guard, row-major fw x fh (replicate border); the guard's last slot of
-// each arena holds the sentinel. Work-group-wide; no barrier.
+// the guard, row-major fw x fh (replicate border); the guard's last MF_DA_SENT slots of
+// each arena hold the sentinel. Work-group-wide; no barrier.
 template <class E>
 __device__ __forceinline__ void
 mf_da_load(E* __restrict__ gl, const unsigned char* __restrict__ src, int H, int W, long long pitch, int dtype,
@@ -178,7 +293,8 @@ mf_da_load(E* __restrict__ gl, const unsigned char* __restrict__ src, int H, int
         }
         gl[t * arena + MF_DA_GUARD + e] = (E)v;
     }
-    if (threadIdx.x < G) gl[threadIdx.x * arena + MF_DA_GUARD - 1] = (E)kMax;
+    if (threadIdx.x < G * MF_DA_SENT)
+        gl[(threadIdx.x / MF_DA_SENT) * arena + MF_DA_GUARD - MF_DA_SENT + threadIdx.x % MF_DA_SENT] = (E)kMax;
 }
 
 // Rounds [r0, r1) of the schedule on one arena, lane lt of the L lanes that
@@ -189,10 +305,8 @@ __device__ __forceinline__ void mf_da_rounds(E* __restrict__ gl, const MfDaArgs&
     const uint32_t* __restrict__ blob = a.blob;
     const uint4* __restrict__ items = reinterpret_cast<const uint4*>(blob + a.c_off);
     const uint32_t* __restrict__ rounds = blob + a.r_off;
-    const uint32_t* __restrict__ clen = blob + a.l_off;
     for (int rd = r0; rd < r1; ++rd) {
         const int c1 = (int)rounds[rd + 1];
-        const int C = (int)clen[rd];
         for (int c = (int)rounds[rd] + lt; c < c1; c += L) {
             const uint4 d = items[c];
             if (d.w & 0x80000000u) {
@@ -205,7 +319,7 @@ __device__ __forceinline__ void mf_da_rounds(E* __restrict__ gl, const MfDaArgs&
                 default: mf_da_sort<E, 32>(gl, d); break;
                 }
             } else {
-                mf_da_merge<E, CLAMP>(gl, d, C);
+                mf_da_merge<E, CLAMP>(gl, d);
             }
         }
         __syncthreads();
@@ -348,7 +462,8 @@ mf_da3_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__
         }
         lds[t * a.arena + MF_DA_GUARD + e] = (E)v;
     }
-    if (threadIdx.x < G) lds[threadIdx.x * a.arena + MF_DA_GUARD - 1] = (E)kMax;
+    if (threadIdx.x < G * MF_DA_SENT)
+        lds[(threadIdx.x / MF_DA_SENT) * a.arena + MF_DA_GUARD - MF_DA_SENT + threadIdx.x % MF_DA_SENT] = (E)kMax;
     __syncthreads();
     mf_da_rounds<E, CLAMP>(lds + gi * a.arena, a, 0, a.nrounds, lt, L);
     const uint32_t* outs = a.blob + a.o_off;

@@ -12,7 +12,7 @@ Section 3 but realises every sort and merge with data-dependent work in LDS:
   number of lists each round (Section 5.1);
 * every two-way merge is executed with merge path: its output is cut into
   chunks, each chunk finds its start in both inputs by a co-rank binary
-  search and then merges sequentially (Section 5.1).
+  search and then merges sequentially, four outputs per step (Section 5.1).
 
 Forgetting (Section 2.2) and pruning become output windows: after a merge
 into a core only the middle min(n, u+1) ranks are kept, and a backward pass
@@ -24,30 +24,33 @@ nodes, assigns each node the recursion level (phase) that creates it,
 schedules the work of each phase in dependency rounds, allocates LDS (first
 fit, freed after the last reader) and emits compact items of 4 words.
 
-Every stored list is followed by one sentinel slot holding the largest
+Every stored list is followed by SENT_W sentinel slots holding the largest
 element value, so a merge never tests whether an input is exhausted: the
-element after an input window is either that sentinel or a list element
-ranked after every output the merge must produce, and in both cases it is
-never chosen while needed outputs remain.
+elements after an input window are sentinels or list elements ranked after
+every output the merge must produce, and they are never chosen while needed
+outputs remain.
 
 Items (4 uint32 words):
 
 * merge chunk: w0 = a_off | na << 18, w1 = b_off | nb << 18,
   w2 = out_off | nvalid << 18, w3 = r0 | steps << 18 | last << 22.
   The lane finds the co-rank of rank r0 (the chunk's first output, counted in
-  the merge of the two input windows; A first on ties) in `steps` halving
-  steps, then emits the round's chunk length C of outputs (C is uniform over
-  a round; a merge's last chunk is aligned to end at its window's end and may
-  overlap the previous one, rewriting the same values). When `last` is set
-  the lane then writes the sentinel at out_off + nvalid.
+  the merge of the two input windows; A first on ties) over a range of fewer
+  than 2^steps positions, then emits the round's chunk length C of outputs,
+  four per step (C is uniform over a round and a multiple of four; chunks
+  start at multiples of C, and a ragged end gets one more chunk ending at the
+  next multiple of four, overlapping the one before and rewriting the same
+  values; out_off is then a multiple of four). When `last` is set the lane
+  then writes the SENT_W sentinels from out_off + nvalid.
 * sort: w0 = base | n << 18, w1 = stride | lo << 18, w2 = out_off | (hi-lo) << 18,
-  w3 = SORT_FLAG | N: the n footprint values at base + i*stride are sorted by
-  the network for N (a power of two >= n, padded with the largest value); ranks
-  [lo, hi) are written from out_off, followed by the sentinel.
+  w3 = SORT_FLAG | N | L << 6 | step << 9: the n*L footprint values at
+  base + j*step + i*stride (L parallel lines of n values) are sorted by the
+  network for N (a power of two >= n*L, padded with the largest value);
+  ranks [lo, hi) are written from out_off, followed by the SENT_W sentinels.
 
 Per round: the item range (work-group barrier between rounds) and the chunk
 length C. Offsets are in elements of the LDS arena: a guard of GUARD elements
-(its last slot holds the sentinel value and stands in for empty input
+(its last SENT_W slots hold the sentinel value and stand in for empty input
 windows), then the raw footprint (row-major, fw = k_w+t_w-1 wide), then the
 lists; the arena ends with a pad that absorbs the reads and writes a chunk
 makes past its needed outputs.
@@ -67,9 +70,17 @@ MAX_LEN = 1 << (32 - OFF_BITS)
 SORT_MAX = 32       # largest per-lane sorting network
 ROUNDS = "asap"     # round assignment: "asap" over the whole DAG, or "phase"
                     # (ASAP within each recursion level)
-GUARD = 4           # arena elements before the footprint; slot GUARD-1 holds the sentinel
-SENTINEL_SLOT = GUARD - 1
+SENT_W = 4          # sentinel slots after every stored list (a merge step reads 4 ahead)
+GUARD = 8           # arena elements before the footprint; the last SENT_W hold sentinels
+SENTINEL_SLOT = GUARD - SENT_W
+ALIGN = 4           # stored lists start at multiples of ALIGN elements
+READ_PAST = 2 * SENT_W  # elements a merge may read after an input window's
+                    # end: its head stays within the SENT_W after it, and a
+                    # step reads four elements from the head (16-bit ones as
+                    # the aligned dwords that hold them)
 SORT_FLAG = 1 << 31
+LSTEP_SHIFT = 9     # sort items: w3 = SORT_FLAG | N | lines << 6 | line step << 9
+LSTEP_BITS = 22
 STEP_SHIFT = 18
 LAST_BIT = 1 << 22
 
@@ -81,7 +92,7 @@ class Node:
     a: tuple | None = None          # (node, lo, hi) input views
     b: tuple | None = None
     raw: tuple | None = None        # (x, y) for a single footprint value
-    line: tuple | None = None       # sort node: (base, stride, n) footprint offsets
+    line: tuple | None = None       # sort node: (base, stride, n, lines, line step) footprint offsets
     phase: int = 0
     need_lo: int = 0
     need_hi: int = 0
@@ -143,10 +154,37 @@ class Dag:
         offs = [self.offset(p) for p in pts]
         stride = offs[1] - offs[0] if len(offs) > 1 else 1
         assert stride > 0 and all(offs[i] == offs[0] + i * stride for i in range(len(offs)))
-        n = Node(len(self.nodes), len(pts), line=(offs[0], stride, len(pts)), phase=self.phase,
+        n = Node(len(self.nodes), len(pts), line=(offs[0], stride, len(pts), 1, 0), phase=self.phase,
                  role=self.role)
         self.nodes.append(n)
         return n
+
+    def sort_lines(self, lines: list[list[tuple]]) -> tuple:
+        """Sorted list of the footprint values on several parallel lines of
+        equal length and step, the lines themselves equally spaced: one
+        sorting network when they hold at most SORT_MAX values together,
+        else each line sorted alone; the sorted pieces are then merged."""
+        if not lines:
+            return (None, 0, 0)
+        n = len(lines[0])
+        per = max(1, min(7, SORT_MAX // max(n, 1)))     # at most 7 lines per item
+        pieces = []
+        for g in range(0, len(lines), per):
+            grp = lines[g:g + per]
+            if len(grp) == 1 or n == 0:
+                pieces.append(self.sort(grp[0]))
+                continue
+            first = [self.offset(p) for p in grp[0]]
+            stride = first[1] - first[0] if n > 1 else 1
+            lstep = self.offset(grp[1][0]) - first[0]
+            for j, ln in enumerate(grp):
+                offs = [self.offset(p) for p in ln]
+                assert len(ln) == n and all(offs[i] == first[0] + j * lstep + i * stride for i in range(n))
+            node = Node(len(self.nodes), n * len(grp), line=(first[0], stride, n, len(grp), lstep),
+                        phase=self.phase, role=self.role)
+            self.nodes.append(node)
+            pieces.append((node, 0, node.size))
+        return self.reduce(pieces)
 
     def sort(self, pts: list[tuple]) -> tuple:
         """Sorted list of the footprint values at pts ((x, y) or (x, y, z) on
@@ -196,9 +234,10 @@ def build_dag(k: int, tw: int, th: int, kh: int | None = None):
         return D.sort([(x, y) for x in xs])
 
     D.phase = 0
-    cols = [col(x, core_y) for x in core_x]
-    D.role = "core_init"
-    core = D.reduce(cols)
+    # the core: sorted core columns (several to one network when short),
+    # merged
+    D.role = "sort_col"
+    core = D.sort_lines([[(x, y) for y in core_y] for x in core_x])
     core = trim(core, N - len(core_x) * len(core_y))
     xcols = {x: col(x, core_y) for x in list(range(0, tw - 1)) + list(range(kw, kw + tw - 1))}
     xrows = {y: row(y, core_x) for y in list(range(0, th - 1)) + list(range(kh, kh + th - 1))}
@@ -471,6 +510,10 @@ def _window_inputs(n: Node):
 _OEMS_CES = {1: 0, 2: 1, 4: 5, 8: 19, 16: 63, 32: 191}
 
 
+def _ceil_to(n: int, m: int) -> int:
+    return -(-n // m) * m
+
+
 def _pow2_at_least(n: int) -> int:
     p = 1
     while p < n:
@@ -558,13 +601,16 @@ def _schedule_dag(D: Dag, outs: list, fw: int, fh: int, fd: int, npx: int, chunk
             last_read[m.nid] = max(last_read.get(m.nid, -1), n.rnd)
     for (n, _, _) in outs:
         last_read[n.nid] = len(order) + 1
-    # allocation: guard + raw footprint fixed at [0, GUARD + fw*fh); first fit for the rest
-    base = GUARD + fw * fh * fd
+    # allocation: guard + raw footprint fixed at [0, GUARD + fw*fh); first fit
+    # for the rest, every block a multiple of ALIGN elements at a multiple of
+    # ALIGN, so a chunk's steps of four outputs write aligned runs
+    base = _ceil_to(GUARD + fw * fh * fd, ALIGN)
     free = [(base, 1 << 40)]         # (start, end) holes, sorted
     peak = base
 
     def alloc(size):
         nonlocal peak
+        size = _ceil_to(size, ALIGN)
         for i, (s, e) in enumerate(free):
             if e - s >= size:
                 free[i] = (s + size, e)
@@ -575,6 +621,7 @@ def _schedule_dag(D: Dag, outs: list, fw: int, fh: int, fd: int, npx: int, chunk
         raise RuntimeError("arena exhausted")
 
     def release(s, size):
+        size = _ceil_to(size, ALIGN)
         free.append((s, s + size))
         free.sort()
         merged = []
@@ -598,27 +645,33 @@ def _schedule_dag(D: Dag, outs: list, fw: int, fh: int, fd: int, npx: int, chunk
         cmax = max(cmax, C)
         for n in group:
             nout = n.need_hi - n.need_lo
-            n.store = (max(nout, C) if n.a is not None else nout) + 1
+            n.store = (_ceil_to(nout, ALIGN) if n.a is not None else nout) + SENT_W
             n.off = alloc(n.store)
         sorts = []
         chunks = []
         for n in group:
             nout = n.need_hi - n.need_lo
             if n.line is not None:
-                b0, stride, cnt = n.line
-                N = _pow2_at_least(cnt)
+                b0, stride, cnt, nl, lstep = n.line
+                N = _pow2_at_least(cnt * nl)
                 assert N <= SORT_MAX and b0 < MAX_OFF and stride < MAX_OFF and n.off < MAX_OFF
+                assert 1 <= nl <= 7 and 0 <= lstep < (1 << LSTEP_BITS)
                 sorts.append((N, (b0 | (cnt << OFF_BITS), stride | (n.need_lo << OFF_BITS),
-                                  n.off | (nout << OFF_BITS), SORT_FLAG | N)))
+                                  n.off | (nout << OFF_BITS),
+                                  SORT_FLAG | N | (nl << 6) | (lstep << LSTEP_SHIFT))))
                 continue
             (aoff, na), (boff, nb), r0 = _window_inputs(n)
             assert 0 <= r0 and r0 + nout <= na + nb, (n.nid, r0, nout, na, nb)
+            # chunks at multiples of C; a ragged end gets one more chunk that
+            # ends at the next multiple of ALIGN (it overlaps the one before,
+            # rewriting the same values, and its few outputs past the end land
+            # in the sentinel slots, which its lane then rewrites)
             starts = list(range(0, nout - C + 1, C)) if nout >= C else [0]
             if nout > C and nout % C:
-                starts.append(nout - C)
+                starts.append(_ceil_to(nout, ALIGN) - C)
             for ci, c0 in enumerate(starts):
                 last = ci == len(starts) - 1
-                nvalid = C if nout >= C else nout
+                nvalid = min(C, nout - c0)
                 rr = r0 + c0
                 lo_i, hi_i = max(0, rr - nb), min(rr, na)
                 steps = max(hi_i - lo_i, 0).bit_length()
@@ -642,21 +695,24 @@ def _schedule_dag(D: Dag, outs: list, fw: int, fh: int, fd: int, npx: int, chunk
             if last_read.get(n.nid, -1) == r and n.off >= 0:
                 release(n.off, n.store)
                 n.off = -2 - n.off  # mark released (keeps the value recoverable)
-    arena = peak + cmax + 4
+    arena = _ceil_to(peak + READ_PAST, 2 * ALIGN)
     it = np.array(items, dtype=np.int64).reshape(-1, 4)
     m = (1 << OFF_BITS) - 1
     if len(it):
         isort = (it[:, 3] & SORT_FLAG) != 0
         mg = it[~isort]
         # merge reads: one element before each window (co-rank guard) up to
-        # the window end plus a chunk length (steps past the needed outputs)
+        # READ_PAST elements after the window end; writes: the chunk's
+        # outputs rounded up to four, then SENT_W sentinels
         for col in range(2):
             assert np.all((mg[:, col] & m) >= 1)
-            assert np.all((mg[:, col] & m) + (mg[:, col] >> OFF_BITS) + cmax + 1 <= arena)
-        assert np.all((mg[:, 2] & m) + cmax + 1 <= arena)
+            assert np.all((mg[:, col] & m) + (mg[:, col] >> OFF_BITS) + READ_PAST <= arena)
+        nv = mg[:, 2] >> OFF_BITS
+        assert np.all((mg[:, 2] & m) + np.maximum(-(-nv // 4) * 4, nv + SENT_W) <= arena)
+        assert np.all((mg[:, 2] & m) % ALIGN == 0) and arena % (2 * ALIGN) == 0
         srt = it[isort]
         assert np.all((srt[:, 0] & m) + (srt[:, 1] & m) * ((srt[:, 0] >> OFF_BITS) - 1) < GUARD + fw * fh * fd)
-        assert np.all((srt[:, 2] & m) + (srt[:, 2] >> OFF_BITS) + 1 <= arena)
+        assert np.all((srt[:, 2] & m) + (srt[:, 2] >> OFF_BITS) + SENT_W <= arena)
     outputs = []
     for (n, lo, hi) in outs:
         off = n.off if n.off >= 0 else (-2 - n.off)
@@ -670,7 +726,7 @@ def _schedule_dag(D: Dag, outs: list, fw: int, fh: int, fd: int, npx: int, chunk
         by_role[n.role] = by_role.get(n.role, 0) + (n.need_hi - n.need_lo)
     nmerge_items = int(np.sum((it[:, 3] & SORT_FLAG) == 0)) if len(it) else 0
     # compare-exchanges of the sorting networks the sort items run
-    sort_ces = sum(_OEMS_CES[int(w3) & 0xFFFF] for w3 in it[:, 3] if int(w3) & SORT_FLAG) if len(it) else 0
+    sort_ces = sum(_OEMS_CES[int(w3) & 63] for w3 in it[:, 3] if int(w3) & SORT_FLAG) if len(it) else 0
     st = {"rounds": len(order), "chunks": nmerge_items, "round_mode": st_mode, "sorts": len(items) - nmerge_items,
           "merge_outputs": merge_outputs, "sort_outputs": sort_outputs,
           "per_pixel_by_role": {r: round(v / npx, 1) for r, v in sorted(by_role.items())},
@@ -722,7 +778,7 @@ def _execute(S: Schedule, keys: np.ndarray, et, clamp: bool, exact: bool) -> np.
     MAXV = _sentinel(et)
     g = np.random.default_rng(S.arena)
     arena = g.integers(0, MAXV + 1, size=(T, S.arena), dtype=np.uint64).astype(et)
-    arena[:, SENTINEL_SLOT] = MAXV
+    arena[:, SENTINEL_SLOT:GUARD] = MAXV
     arena[:, GUARD:GUARD + keys.shape[1]] = keys
     mask = (1 << OFF_BITS) - 1
     rows = np.arange(T)
@@ -734,13 +790,14 @@ def _execute(S: Schedule, keys: np.ndarray, et, clamp: bool, exact: bool) -> np.
                 base, n = w0 & mask, w0 >> OFF_BITS
                 stride, lo = w1 & mask, w1 >> OFF_BITS
                 ooff, cnt = w2 & mask, w2 >> OFF_BITS
-                N = w3 & 0xFFFF
-                assert n <= N <= SORT_MAX
+                N, nl, lstep = w3 & 63, (w3 >> 6) & 7, (w3 >> LSTEP_SHIFT) & ((1 << LSTEP_BITS) - 1)
+                assert n * nl <= N <= SORT_MAX
                 vals = np.full((T, N), MAXV, dtype=et)
-                vals[:, :n] = arena[:, base + stride * np.arange(n)]
+                idx = (base + lstep * np.arange(nl)[:, None] + stride * np.arange(n)[None, :]).reshape(-1)
+                vals[:, :n * nl] = arena[:, idx]
                 vals = np.sort(vals, axis=1)
                 arena[:, ooff:ooff + cnt] = vals[:, lo:lo + cnt]
-                arena[:, ooff + cnt] = MAXV
+                arena[:, ooff + cnt:ooff + cnt + SENT_W] = MAXV
                 continue
             aoff, na = w0 & mask, w0 >> OFF_BITS
             boff, nb = w1 & mask, w1 >> OFF_BITS
@@ -752,8 +809,9 @@ def _execute(S: Schedule, keys: np.ndarray, et, clamp: bool, exact: bool) -> np.
                 m = np.sort(np.concatenate([A, B], axis=1), axis=1)
                 arena[:, ooff:ooff + nvalid] = m[:, r0:r0 + nvalid]
                 if last:
-                    arena[:, ooff + nvalid] = MAXV
+                    arena[:, ooff + nvalid:ooff + nvalid + SENT_W] = MAXV
                 continue
+            # co-rank search by halving steps, reads clamped into the window
             lo_i, hi_i = max(0, r0 - nb), min(r0, na)
             pos = np.full(T, lo_i, dtype=np.int64)
             for st in range(steps):
@@ -763,20 +821,26 @@ def _execute(S: Schedule, keys: np.ndarray, et, clamp: bool, exact: bool) -> np.
                 av = arena[rows, aoff + tc]
                 bv = arena[rows, boff + r0 - 1 - tc]
                 pos = np.where((t < hi_i) & (av <= bv), t + 1, pos)
+            # merge steps of four outputs: the four smallest of A[ia..ia+3]
+            # and B[ib..ib+3] are min(A[ia+i], B[ib+3-i]) (a half-cleaner),
+            # i taken from A exactly when A[ia+i] <= B[ib+3-i]; they are
+            # written in order after a bitonic sort of four
             ia = pos.copy()
-            a = arena[rows, aoff + ia]
-            b = arena[rows, boff + (r0 - ia)]
-            for q in range(C):
-                take = a <= b
-                arena[:, ooff + q] = np.minimum(a, b)
-                ia = ia + take
+            for q0 in range(0, nvalid, 4):
+                ib = r0 + q0 - ia
+                av = [arena[rows, aoff + ia + i] for i in range(4)]
+                bv = [arena[rows, boff + ib + i] for i in range(4)]
+                take = [av[i] <= bv[3 - i] for i in range(4)]
+                c = [np.where(take[i], av[i], bv[3 - i]) for i in range(4)]
+                for (x, y) in ((0, 2), (1, 3), (0, 1), (2, 3)):
+                    c[x], c[y] = np.minimum(c[x], c[y]), np.maximum(c[x], c[y])
+                for i in range(4):
+                    arena[:, ooff + q0 + i] = c[i]
+                ia = ia + sum(t.astype(np.int64) for t in take)
                 if clamp:
                     ia = np.minimum(ia, na)
-                ib = r0 + q + 1 - ia
-                a = arena[rows, aoff + ia]
-                b = arena[rows, boff + ib]
             if last:
-                arena[:, ooff + nvalid] = MAXV
+                arena[:, ooff + nvalid:ooff + nvalid + SENT_W] = MAXV
     return arena[:, S.outputs]
 
 

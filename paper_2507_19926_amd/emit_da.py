@@ -265,6 +265,7 @@ def generate(out_dir: str, workers: int | None = None) -> dict:
              "#define MF_DA_BLOB_WORDS %d" % len(blob),
              "#define MF_DA_CHUNK %d" % dagen.CHUNK,
              "#define MF_DA_GUARD %d" % dagen.GUARD,
+             "#define MF_DA_SENT %d" % dagen.SENT_W,
              "#define MF_DA_RECT_MAX_SIDE %d" % RECT_MAX_SIDE,
              "#define MF_DA_TABLE_ENTRIES \\"]
     for e in entries:

@@ -180,3 +180,49 @@ def test_3d_schedule_matches_oracle(box, tile):
         for exact in (False, True):
             got = dg.run_schedule_on_volume(S, vol, exact_merge_path=exact)
             assert got.view(np.uint8).tobytes() == want.view(np.uint8).tobytes(), (dt, exact)
+
+
+@pytest.mark.parametrize("k,tw,th,mode", [(9, 4, 4, "asap"), (25, 16, 16, "asap"), (25, 16, 16, "phase"),
+                                          (35, 16, 8, "asap"), (75, 16, 8, "asap")])
+def test_items_as_the_kernel_assumes(k, tw, th, mode):
+    """What the kernel takes for granted about the items: a round lists its
+    sorts first and then its chunks by non-increasing search steps (a wave
+    runs its first merging lane's step count), merge outputs start
+    at multiples of ALIGN elements (each step writes one aligned run of four),
+    chunks hold at most the round's chunk length, every merge read stays
+    READ_PAST elements inside the arena after its window, and multi-line sort
+    items gather lines that lie inside the footprint."""
+    S = dg.schedule(k, tw, th, rounds=mode)
+    m = (1 << dg.OFF_BITS) - 1
+    fp = dg.GUARD + S.fw * S.fh
+    assert S.arena % (2 * dg.ALIGN) == 0
+    lines = 0
+    for r in range(len(S.rounds) - 1):
+        C = int(S.chunk_len[r])
+        # sorts first, then chunks by non-increasing search steps: a wave's
+        # first merging lane holds the largest step count of the wave
+        w3 = S.items[S.rounds[r]:S.rounds[r + 1], 3].astype(np.int64)
+        srt = (w3 & dg.SORT_FLAG) != 0
+        assert not np.any(srt[1:] & ~srt[:-1])
+        st = (w3[~srt] >> dg.STEP_SHIFT) & 15
+        assert np.all(np.diff(st) <= 0)
+        for w0, w1, w2, w3 in S.items[S.rounds[r]:S.rounds[r + 1]].astype(np.int64):
+            if w3 & dg.SORT_FLAG:
+                n, N, nl = w0 >> dg.OFF_BITS, w3 & 63, (w3 >> 6) & 7
+                lstep = (w3 >> dg.LSTEP_SHIFT) & ((1 << dg.LSTEP_BITS) - 1)
+                assert 1 <= nl and n * nl <= N <= dg.SORT_MAX
+                last = (w0 & m) + (nl - 1) * lstep + (n - 1) * (w1 & m)
+                assert dg.GUARD <= (w0 & m) and last < fp
+                lines += nl > 1
+                continue
+            assert (w2 & m) % dg.ALIGN == 0 and 1 <= (w2 >> dg.OFF_BITS) <= C
+            for off, n in ((w0 & m, w0 >> dg.OFF_BITS), (w1 & m, w1 >> dg.OFF_BITS)):
+                assert off >= 1 and off + n + dg.READ_PAST <= S.arena
+    if 2 * (k - th + 1) <= dg.SORT_MAX:
+        assert lines > 0       # the core's short columns are sorted several to a network
+
+
+def test_round_count_k25_16x16():
+    """Rounds over the whole schedule: 12 barriers at k = 25, 16 x 16 (28
+    with binary reductions from singletons, one recursion level at a time)."""
+    assert dg.schedule(25, 16, 16, rounds="asap").stats["rounds"] <= 12
