@@ -784,7 +784,12 @@ def _execute(S: Schedule, keys: np.ndarray, et, clamp: bool, exact: bool) -> np.
     rows = np.arange(T)
     for ri in range(len(S.rounds) - 1):
         C = int(S.chunk_len[ri])
-        for c in S.items[S.rounds[ri]:S.rounds[ri + 1]]:
+        rnd = S.items[S.rounds[ri]:S.rounds[ri + 1]].astype(np.int64)
+        # a wave searches with its largest step count; any count at least an
+        # item's own gives its position, and the model takes the round's
+        mg3 = rnd[(rnd[:, 3] & SORT_FLAG) == 0, 3]
+        wave_steps = int(((mg3 >> STEP_SHIFT) & 15).max()) if len(mg3) else 0
+        for c in rnd:
             w0, w1, w2, w3 = (int(v) for v in c)
             if w3 & SORT_FLAG:
                 base, n = w0 & mask, w0 >> OFF_BITS
@@ -812,15 +817,16 @@ def _execute(S: Schedule, keys: np.ndarray, et, clamp: bool, exact: bool) -> np.
                     arena[:, ooff + nvalid:ooff + nvalid + SENT_W] = MAXV
                 continue
             # co-rank search by halving steps, reads clamped into the window
+            # (a probe past the range reads its last element; taking it means
+            # taking every position); a wave runs its largest step count, and
+            # any count at least the item's own gives its position
             lo_i, hi_i = max(0, r0 - nb), min(r0, na)
             pos = np.full(T, lo_i, dtype=np.int64)
-            for st in range(steps):
-                step = 1 << (steps - 1 - st)
-                t = pos + step - 1
-                tc = np.minimum(t, hi_i - 1)
+            for s in range(wave_steps - 1, -1, -1):
+                tc = np.minimum(pos + (1 << s) - 1, hi_i - 1)
                 av = arena[rows, aoff + tc]
                 bv = arena[rows, boff + r0 - 1 - tc]
-                pos = np.where((t < hi_i) & (av <= bv), t + 1, pos)
+                pos = np.where(av <= bv, tc + 1, pos)
             # merge steps of four outputs: the four smallest of A[ia..ia+3]
             # and B[ib..ib+3] are min(A[ia+i], B[ib+3-i]) (a half-cleaner),
             # i taken from A exactly when A[ia+i] <= B[ib+3-i]; they are
