@@ -352,6 +352,18 @@ mf_da_store(const E* __restrict__ gl, unsigned char* __restrict__ dst, int H, in
 // owns tile g and runs every round's items for it (small tiles, whose rounds
 // have few items, fill the work-group this way). LDS holds G arenas of
 // `arena` elements.
+// Tile of work-group b of n in one plane. Work-groups are dealt to the 8
+// XCDs in turn (b % 8), each with its own L2; this hands XCD x the x-th
+// contiguous eighth of the row-major tiles, in order, so horizontally
+// adjacent tiles (which share all but t_w columns of their footprints) run on
+// the same XCD one after the other and the rows above and below are read
+// shortly before. A bijection of [0, n) for any n.
+__device__ __forceinline__ int mf_da_xcd_tile(int b, int n)
+{
+    const int q = n >> 3, r = n & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
 template <class E, bool CLAMP>
 __device__ __forceinline__ void
 mf_da_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, int H, int W,
@@ -373,7 +385,8 @@ mf_da_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ 
              long long pitch, long long plane_stride, int dtype, MfDaArgs a, int ntx)
 {
     const long long po = (long long)blockIdx.y * plane_stride;   // plane = blockIdx.y
-    mf_da_block<E, CLAMP>(src + po, dst + po, H, W, pitch, dtype, a, blockIdx.x % ntx, blockIdx.x / ntx);
+    const int t = mf_da_xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    mf_da_block<E, CLAMP>(src + po, dst + po, H, W, pitch, dtype, a, t % ntx, t / ntx);
 }
 
 // Batched form, persistent: a resident-sized grid walks the nblocks blocks
@@ -440,7 +453,7 @@ mf_da3_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__
     E* lds = reinterpret_cast<E*>(mf_da_lds);
     const int G = a.groups, L = kDaThreads / G;
     const int gi = threadIdx.x / L, lt = threadIdx.x - gi * L;
-    const int b = blockIdx.x;
+    const int b = mf_da_xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int bx = b % ntx, by = (b / ntx) % nty, bz = b / (ntx * nty);
     const int fw = a.k + a.tw - 1, fh = a.kh + a.th - 1, fd = a.kz + a.tz - 1;
     const int fp = fw * fh * fd;
