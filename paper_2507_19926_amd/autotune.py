@@ -7,11 +7,14 @@ configurations the library was built with (``mf_list_configs``), times each on
 a seeded synthetic plane of the class's dtype, and writes a JSON table:
 
     {"p16": {"<k>": [variant, tile_w, tile_h, group, form, rows], ...},
-     "u32": {...}, "device": ..., "timings_ms": {...}}
+     "u16": {...}, "u32": {...}, "device": ..., "timings_ms": {...}}
 
-``p16`` covers uint8/uint16 (two 16-bit values per VGPR), ``u32`` covers
-uint32/float32. The build reads ``tuned.json`` next to this file and compiles
-the choices into the library's AUTO table.
+``p16`` is timed on uint8 data and covers uint8 (and uint16 where ``u16``
+has no entry): the oblivious networks pack two 16-bit values per VGPR for
+both, but the data-aware kernel holds 8-bit data in bytes and 16-bit data in
+16-bit elements, so ``u16`` is timed apart; ``u32`` covers uint32/float32.
+The build reads ``tuned.json`` next to this file and compiles the choices
+into the library's AUTO table.
 
 Usage (on a GPU): python -m paper_2507_19926_amd.autotune [--out PATH] [--ks K ...]
 """
@@ -25,7 +28,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNED = os.path.join(HERE, "tuned.json")
 
-CLASSES = {"p16": 0, "u32": 2}   # class -> representative mf_dtype
+CLASSES = {"p16": 0, "u16": 1, "u32": 2}   # class -> representative mf_dtype
 
 
 def _time_config(x, y, k, cfg, reps, stream):
@@ -56,7 +59,7 @@ def tune(shape=(4480, 6720), ks=None, verbose: bool = True) -> dict:
     table = {"device": torch.cuda.get_device_properties(0).gcnArchName, "shape": [H, W],
              "timings_ms": {}}
     for cls, code in CLASSES.items():
-        dt = np.uint8 if code == 0 else np.uint32
+        dt = {0: np.uint8, 1: np.uint16, 2: np.uint32}[code]
         x = torch.from_numpy(wl.uniform_plane(H, W, dt, seed=77)).to(dev)
         y = torch.empty_like(x)
         best = {}

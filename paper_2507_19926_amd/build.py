@@ -111,16 +111,17 @@ def _compile(src: str, obj: str, extra=(), incremental: bool = False) -> tuple[s
 
 def _write_auto_table() -> None:
     """AUTO choices per (value class, k) from tuned.json (autotune.py), as
-    MF_AUTO(class, k, variant, tile_w, tile_h, group, form, rows) lines; class 0 = 8/16-bit,
-    1 = 32-bit. Without tuned.json the table is empty and the library falls
-    back to its built-in order (oblivious first)."""
+    MF_AUTO(class, k, variant, tile_w, tile_h, group, form, rows) lines; class 0 = 8-bit
+    (and 16-bit where class 2 has no entry), 1 = 32-bit, 2 = 16-bit. Without
+    tuned.json the table is empty and the library falls back to its built-in
+    order (oblivious first)."""
     import json
     lines = ["// Generated from tuned.json: measured fastest configuration per (class, k)."]
     path = os.path.join(PKG, "tuned.json")
     if os.path.exists(path):
         with open(path) as f:
             t = json.load(f)
-        for cls, code in (("p16", 0), ("u32", 1)):
+        for cls, code in (("p16", 0), ("u32", 1), ("u16", 2)):
             for k, cfg in sorted(t.get(cls, {}).items(), key=lambda kv: int(kv[0])):
                 variant, tw, th, group = cfg[:4]
                 form = cfg[4] if len(cfg) > 4 else 0

@@ -63,7 +63,11 @@ const OblRectEntry* find_obl_rect(int kw, int kh)
 
 constexpr int kMaxK = 75;
 
-// Measured AUTO choices (class 0: 8/16-bit data, class 1: 32-bit data).
+// Measured AUTO choices (class 0: 8-bit data, and 16-bit data without a
+// class 2 entry; class 1: 32-bit data; class 2: 16-bit data). 8- and 16-bit
+// data share the oblivious networks, but the data-aware kernel holds 8-bit
+// data in bytes and 16-bit data in 16-bit elements, so their best tiles
+// differ.
 struct AutoEntry {
     int cls, k, variant, tw, th, group, form, rows;
 };
@@ -133,7 +137,10 @@ int32_t resolve(int32_t dtype, int32_t k, const mf_options* opt, int32_t* varian
     // measured choice for this (value class, k), when nothing was requested
     if (o.rows < 0) return fail(MF_ERR_CONFIG, "rows %d must be >= 0", o.rows);
     if (o.variant == MF_VARIANT_AUTO && !o.tile_w && !o.tile_h && !o.group && !o.form && !o.rows) {
-        const int cls = (dtype == MF_U8 || dtype == MF_U16) ? 0 : 1;
+        int cls = (dtype == MF_U8 || dtype == MF_U16) ? 0 : 1;
+        if (dtype == MF_U16)
+            for (const AutoEntry& a : kAutoTable)
+                if (a.cls == 2 && a.k == k) cls = 2;
         for (const AutoEntry& a : kAutoTable) {
             if (a.cls != cls || a.k != k) continue;
             if (a.variant == MF_VARIANT_OBLIVIOUS) {

@@ -166,6 +166,18 @@ __device__ __forceinline__ void mf_da_get4_pk(const unsigned char* __restrict__ 
     hi = __builtin_amdgcn_alignbit(w2, w1, x << 3);
 }
 
+// Four consecutive 8-bit elements from byte offset x on, widened to the
+// 16-bit pairs (x, x+1) and (x+2, x+3): the two aligned dwords that hold
+// them, shifted into place, then spread over 16-bit halves.
+__device__ __forceinline__ void mf_da_get4_u8(const unsigned char* __restrict__ gb, uint32_t x, uint32_t& lo,
+                                              uint32_t& hi)
+{
+    const uint32_t* __restrict__ w = reinterpret_cast<const uint32_t*>(gb + (x & ~3u));
+    const uint32_t v = __builtin_amdgcn_alignbyte(w[1], w[0], x & 3u);
+    lo = __builtin_amdgcn_perm(0u, v, 0x0c010c00u);
+    hi = __builtin_amdgcn_perm(0u, v, 0x0c030c02u);
+}
+
 // Merge chunk: co-rank of rank r0 in (A window, B window), A first on ties,
 // over a range of fewer than 2^steps positions; then the chunk's nvalid
 // outputs, four per step. A step reads A[ia..ia+3] and B[ib..ib+3]
@@ -211,7 +223,31 @@ __device__ __forceinline__ void mf_da_merge(E* __restrict__ gl, const uint4 d)
     }
     int ia = pos;
     const int br = bo + r0;                // B's head of step q0 is element br + q0 - ia
-    if constexpr (sizeof(E) == 2) {
+    if constexpr (sizeof(E) == 1) {
+        // 8-bit elements: the 16-bit step on the widened pairs, outputs
+        // narrowed back to one aligned dword
+        const unsigned char* __restrict__ gb = reinterpret_cast<const unsigned char*>(gl);
+        uint32_t xa = (uint32_t)(ao + ia), xb = (uint32_t)(br - ia);
+        for (int q0 = 0; q0 < nvalid; q0 += 4) {
+            uint32_t a01, a23, b01, b23;
+            mf_da_get4_u8(gb, xa, a01, a23);
+            mf_da_get4_u8(gb, xb, b01, b23);
+            const uint32_t r32 = mf_swap16(b23), r10 = mf_swap16(b01);
+            const uint32_t c01 = mf_pk_min(a01, r32), c23 = mf_pk_min(a23, r10);
+            const uint32_t gt = mf_pk_gt01(a01, r32) + mf_pk_gt01(a23, r10);
+            const int nA = 4 - (int)((gt & 0xffffu) + (gt >> 16));
+            const uint32_t x01 = mf_pk_min(c01, c23), x23 = mf_pk_max(c01, c23);
+            const uint32_t s01 = mf_swap16(x01), s23 = mf_swap16(x23);
+            const uint32_t y01 = (mf_pk_min(x01, s01) & 0xffffu) | (mf_pk_max(x01, s01) & 0xffff0000u);
+            const uint32_t y23 = (mf_pk_min(x23, s23) & 0xffffu) | (mf_pk_max(x23, s23) & 0xffff0000u);
+            *reinterpret_cast<uint32_t*>(gl + oo + q0) = __builtin_amdgcn_perm(y23, y01, 0x06040200u);
+            int ia2 = ia + nA;
+            if constexpr (CLAMP) ia2 = min(ia2, na);
+            xa += (uint32_t)(ia2 - ia);
+            xb += 4u - (uint32_t)(ia2 - ia);
+            ia = ia2;
+        }
+    } else if constexpr (sizeof(E) == 2) {
         // the step on pairs: (a0,a1) meets (b3,b2) and (a2,a3) meets (b1,b0);
         // an A element is taken unless it exceeds its partner, i.e. unless
         // their saturating difference is nonzero
@@ -507,10 +543,13 @@ const void* da3_kernel_for_dtype(int dtype)
     return (const void*)mf_da3_kernel<uint32_t, true>;
 }
 
+// 8-bit data: bytes in LDS (sentinel 0xff, equal to the largest data value,
+// hence the clamped kernel) for one plane form; the batched kernel keeps
+// 16-bit elements, whose sentinel no 8-bit value reaches.
 const void* da_kernel_for_dtype(int dtype, bool batched)
 {
     if (dtype == MF_U8)
-        return batched ? (const void*)mf_da_kernel_batched<uint16_t, false> : (const void*)mf_da_kernel<uint16_t, false>;
+        return batched ? (const void*)mf_da_kernel_batched<uint16_t, false> : (const void*)mf_da_kernel<uint8_t, true>;
     if (dtype == MF_U16)
         return batched ? (const void*)mf_da_kernel_batched<uint16_t, true> : (const void*)mf_da_kernel<uint16_t, true>;
     return batched ? (const void*)mf_da_kernel_batched<uint32_t, true> : (const void*)mf_da_kernel<uint32_t, true>;
@@ -635,7 +674,7 @@ hipError_t mf_da_launch(const void* src, void* dst, int planes, long long plane_
     const int bw = e->tw * e->tiles * e->groups;     // pixels of a work-group along x
     const int ntx = (W + bw - 1) / bw, nty = (H + e->th - 1) / e->th;
     if ((long long)ntx * nty > 0x7fffffffLL) return hipErrorInvalidConfiguration;   // grid.x limit
-    const size_t lds = (size_t)e->arena * e->es * e->tiles * e->groups;
+    const size_t lds = (size_t)e->arena * (dtype == MF_U8 ? 1 : e->es) * e->tiles * e->groups;
     for (int p0 = 0; p0 < planes; p0 += 65535) {     // grid rows are planes
         const int np = planes - p0 < 65535 ? planes - p0 : 65535;
         const unsigned char* s8 = (const unsigned char*)src + p0 * plane_stride;

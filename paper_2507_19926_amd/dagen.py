@@ -749,13 +749,16 @@ def _schedule_dag(D: Dag, outs: list, fw: int, fh: int, fd: int, npx: int, chunk
 # ------------------------------------------------------------- CPU model
 
 def _sentinel(dtype) -> int:
-    return 0xFFFF if np.dtype(dtype).itemsize <= 2 else 0xFFFFFFFF
+    return {1: 0xFF, 2: 0xFFFF}.get(np.dtype(dtype).itemsize, 0xFFFFFFFF)
 
 
-def _to_keys(win: np.ndarray, dtype):
-    """Elements as the kernel holds them: 16-bit for 8/16-bit data, else
-    32-bit (float32 through the order-preserving key)."""
+def _to_keys(win: np.ndarray, dtype, byte_elements: bool = False):
+    """Elements as the kernel holds them: 16-bit for 8/16-bit data (8-bit
+    for 8-bit data with byte_elements), else 32-bit (float32 through the
+    order-preserving key)."""
     et = np.uint16 if np.dtype(dtype).itemsize <= 2 else np.uint32
+    if byte_elements and np.dtype(dtype) == np.uint8:
+        et = np.uint8
     if dtype == np.float32:
         b = win.view(np.uint32)
         return et, b ^ np.where(b >> 31 == 1, np.uint32(0xFFFFFFFF), np.uint32(0x80000000))
@@ -850,7 +853,8 @@ def _execute(S: Schedule, keys: np.ndarray, et, clamp: bool, exact: bool) -> np.
     return arena[:, S.outputs]
 
 
-def run_schedule_on_image(S: Schedule, img: np.ndarray, exact_merge_path: bool = False) -> np.ndarray:
+def run_schedule_on_image(S: Schedule, img: np.ndarray, exact_merge_path: bool = False,
+                          byte_elements: bool = False) -> np.ndarray:
     """Execute a schedule on every root tile of img (replicate border).
 
     With exact_merge_path=False each merge chunk is checked against a sort of
@@ -859,7 +863,9 @@ def run_schedule_on_image(S: Schedule, img: np.ndarray, exact_merge_path: bool =
     step count and clamped reads, the C merge steps that read the sentinels
     and run past the needed outputs, the sentinel writes, and the ia clamp
     that 16-bit and 32-bit data use (8-bit data held in 16-bit elements never
-    equals the sentinel and runs without it)."""
+    equals the sentinel and runs without it). With byte_elements, 8-bit data
+    is held in 8-bit elements, as the one-plane kernel holds it: the
+    sentinel 0xff then equals the largest data value and the clamp is on."""
     kw, kh, tw, th = S.kw, S.rows, S.tw, S.th
     H, W = img.shape
     nty, ntx = -(-H // th), -(-W // tw)
@@ -868,8 +874,8 @@ def run_schedule_on_image(S: Schedule, img: np.ndarray, exact_merge_path: bool =
     pad = img[ys][:, xs]
     win = np.lib.stride_tricks.sliding_window_view(pad, (S.fh, S.fw))[::th, ::tw]
     T = nty * ntx
-    et, keys = _to_keys(np.ascontiguousarray(win.reshape(T, S.fw * S.fh)), img.dtype)
-    med = _execute(S, keys, et, img.dtype.itemsize >= 2, exact_merge_path)
+    et, keys = _to_keys(np.ascontiguousarray(win.reshape(T, S.fw * S.fh)), img.dtype, byte_elements)
+    med = _execute(S, keys, et, img.dtype.itemsize >= 2 or et == np.uint8, exact_merge_path)
     out = np.empty((nty * th, ntx * tw), dtype=et)
     for i in range(tw * th):
         py, px = divmod(i, tw)

@@ -226,3 +226,20 @@ def test_round_count_k25_16x16():
     """Rounds over the whole schedule: 12 barriers at k = 25, 16 x 16 (28
     with binary reductions from singletons, one recursion level at a time)."""
     assert dg.schedule(25, 16, 16, rounds="asap").stats["rounds"] <= 12
+
+
+@pytest.mark.parametrize("k,tw,th,mode", [(5, 4, 2, "asap"), (9, 4, 4, "phase"), (13, 8, 8, "asap"),
+                                          (25, 16, 8, "asap")])
+def test_byte_elements_exact_model(k, tw, th, mode):
+    """8-bit data held in 8-bit elements (the one-plane kernel's LDS form):
+    the sentinel 0xff equals the largest data value, so windows full of 255
+    need the clamped A index; the kernel's exact procedure gives the
+    oracle's median, as it does with 16-bit elements."""
+    S = dg.schedule(k, tw, th, rounds=mode)
+    t = wl.tie_heavy_plane(19, 23, np.uint8, levels=3, seed=k)
+    img = np.where(t == 0, 0, np.where(t == 1, 254, 255)).astype(np.uint8)
+    want = oracle.median_filter(img, k)
+    np.testing.assert_array_equal(dg.run_schedule_on_image(S, img, True, byte_elements=True), want)
+    u = wl.uniform_plane(17, 29, np.uint8, seed=k)
+    np.testing.assert_array_equal(dg.run_schedule_on_image(S, u, True, byte_elements=True),
+                                  oracle.median_filter(u, k))

@@ -301,13 +301,15 @@ def test_peak_diagnostic_runs():
 def test_data_aware_every_listed_schedule(k):
     """Every compiled data-aware configuration of k (each root tile and both
     round modes: rounds per recursion level, rounds over the whole schedule),
-    on images several tiles wide with ragged edges: 16-bit data full of the
-    largest value (the merge sentinel's value), 8-bit and 32-bit data."""
+    on images several tiles wide with ragged edges: 16-bit and 8-bit data
+    full of the largest value (the merge sentinel's value: 8-bit data is
+    held in bytes), uniform 8-bit data and 32-bit data."""
     t = wl.tie_heavy_plane(37 + k // 3, 61 + k, np.uint8, levels=3, seed=k)
     u16 = np.where(t == 0, 0, np.where(t == 1, 0xFFFE, 0xFFFF)).astype(np.uint16)
+    u8sat = np.where(t == 0, 0, np.where(t == 1, 0xFE, 0xFF)).astype(np.uint8)
     u8 = _img(np.uint8, 29 + k // 2, 47 + k, seed=k + 1)
     f32 = _img(np.float32, 31, 40 + k, seed=k + 2)
-    for img in (u16, u8, f32):
+    for img in (u16, u8sat, u8, f32):
         code = {np.dtype(np.uint8): _lib.MF_U8, np.dtype(np.uint16): _lib.MF_U16,
                 np.dtype(np.float32): _lib.MF_F32}[img.dtype]
         cfgs = [c for c in _lib.list_configs(code, k) if c[0] == _lib.MF_VARIANT_DATA_AWARE]
