@@ -415,8 +415,12 @@ mf_da_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
     mf_da_store<E>(lds, dst, H, W, pitch, dtype, a, G, bx, by);
 }
 
-template <class E, bool CLAMP>
-__global__ void __launch_bounds__(kDaThreads)
+// WAVES: the register budget the compiler is asked for (waves per SIMD; 0 =
+// none). 8- and 16-bit arenas small enough for four work-groups per CU take
+// the eight-wave budget (64 VGPRs: the sorting networks spill a little), the
+// others the default, which keeps six waves.
+template <class E, bool CLAMP, int WAVES = 0>
+__global__ void __launch_bounds__(kDaThreads) __attribute__((amdgpu_waves_per_eu(WAVES ? WAVES : 1)))
 mf_da_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst, int H, int W,
              long long pitch, long long plane_stride, int dtype, MfDaArgs a, int ntx)
 {
@@ -533,9 +537,9 @@ mf_da3_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__
 
 namespace {
 
-// kernel pointers by value class: 16-bit elements for 8-bit data (no clamp:
-// a value never equals the sentinel) and for 16-bit data, 32-bit elements
-// for 32-bit data
+// 3-D kernel pointers by value class: 16-bit elements for 8-bit data (no
+// clamp: a value never equals the sentinel) and for 16-bit data, 32-bit
+// elements for 32-bit data
 const void* da3_kernel_for_dtype(int dtype)
 {
     if (dtype == MF_U8) return (const void*)mf_da3_kernel<uint16_t, false>;
@@ -544,12 +548,19 @@ const void* da3_kernel_for_dtype(int dtype)
 }
 
 // 8-bit data: bytes in LDS (sentinel 0xff, equal to the largest data value,
-// hence the clamped kernel) for one plane form; the batched kernel keeps
-// 16-bit elements, whose sentinel no 8-bit value reaches.
+// hence the clamped kernel).
+constexpr size_t kDaLdsFourPerCu = 160 * 1024 / 4;
+
+// the one-plane 8- and 16-bit kernels with the eight-wave register budget
+const void* da_kernel_w8(int dtype)
+{
+    return dtype == MF_U8 ? (const void*)mf_da_kernel<uint8_t, true, 8> : (const void*)mf_da_kernel<uint16_t, true, 8>;
+}
+
 const void* da_kernel_for_dtype(int dtype, bool batched)
 {
     if (dtype == MF_U8)
-        return batched ? (const void*)mf_da_kernel_batched<uint16_t, false> : (const void*)mf_da_kernel<uint8_t, true>;
+        return batched ? (const void*)mf_da_kernel_batched<uint8_t, true> : (const void*)mf_da_kernel<uint8_t, true>;
     if (dtype == MF_U16)
         return batched ? (const void*)mf_da_kernel_batched<uint16_t, true> : (const void*)mf_da_kernel<uint16_t, true>;
     return batched ? (const void*)mf_da_kernel_batched<uint32_t, true> : (const void*)mf_da_kernel<uint32_t, true>;
@@ -599,6 +610,10 @@ hipError_t da_blob(const uint32_t** out)
                 e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
                 if (e != hipSuccess) return e;
             }
+        for (int dt = MF_U8; dt <= MF_U16; ++dt) {
+            e = hipFuncSetAttribute(da_kernel_w8(dt), hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            if (e != hipSuccess) return e;
+        }
         g_da_blob_dev[dev] = (const uint32_t*)p;
     }
     *out = g_da_blob_dev[dev];
@@ -680,7 +695,9 @@ hipError_t mf_da_launch(const void* src, void* dst, int planes, long long plane_
         const unsigned char* s8 = (const unsigned char*)src + p0 * plane_stride;
         unsigned char* d8 = (unsigned char*)dst + p0 * plane_stride;
         void* args[] = {&s8, &d8, &H, &W, &pitch, &plane_stride, &dtype, &a, (void*)&ntx};
-        err = hipLaunchKernel(da_kernel_for_dtype(dtype, false), dim3(ntx * nty, np), dim3(kDaThreads), args, lds, stream);
+        const void* fn = (dtype == MF_U8 || dtype == MF_U16) && lds <= kDaLdsFourPerCu ? da_kernel_w8(dtype)
+                                                                                      : da_kernel_for_dtype(dtype, false);
+        err = hipLaunchKernel(fn, dim3(ntx * nty, np), dim3(kDaThreads), args, lds, stream);
         if (err != hipSuccess) return err;
     }
     return hipSuccess;
@@ -697,7 +714,7 @@ hipError_t mf_da_batched(int dtype, int k, int tw, int th, int group, MfBatchedK
     *args = da_args(e, blob);
     kern->fn = da_kernel_for_dtype(dtype, true);
     kern->threads = kDaThreads;
-    kern->lds = (size_t)e->arena * e->es * e->tiles * e->groups;
+    kern->lds = (size_t)e->arena * (dtype == MF_U8 ? 1 : e->es) * e->tiles * e->groups;
     kern->bw = e->tw * e->tiles * e->groups;
     kern->bh = e->th;
     return hipSuccess;

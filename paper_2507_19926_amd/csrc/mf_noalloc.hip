@@ -108,7 +108,7 @@ extern "C" int32_t median_filter_batched_noalloc(const mf_image* imgs, int32_t n
         rc = mf_internal_resolve(m.dtype, m.k, &variant, &tw, &th, &group, &kp16, &ku32, &da_form);
         if (rc) return rc;
         // kernel class: the oblivious kernels serve 8- and 16-bit data alike;
-        // the data-aware kernels differ for 8-bit data (no sentinel clamp),
+        // the data-aware kernels differ for 8-bit data (byte elements),
         // 16-bit and 32-bit data
         const int packed = variant == MF_VARIANT_DATA_AWARE
                                ? 8 + (m.dtype == MF_U8 ? 0 : m.dtype == MF_U16 ? 1 : 2) * 4 + da_form

@@ -186,7 +186,7 @@ int32_t mf_plan_create(const mf_image* imgs, int32_t n, mf_plan* out)
         }
         const int packed = (m.dtype == MF_U8 || m.dtype == MF_U16) ? 1 : 0;
         // kernel class: the oblivious kernels serve 8- and 16-bit data alike;
-        // the data-aware kernels differ for 8-bit data (no sentinel clamp),
+        // the data-aware kernels differ for 8-bit data (byte elements),
         // 16-bit and 32-bit data
         const int cls = variant == MF_VARIANT_DATA_AWARE ? (m.dtype == MF_U8 ? 0 : m.dtype == MF_U16 ? 1 : 2) * 4 + da_form
                                                          : packed;
