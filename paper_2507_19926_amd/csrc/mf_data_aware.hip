@@ -537,12 +537,11 @@ mf_da3_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__
 
 namespace {
 
-// 3-D kernel pointers by value class: 16-bit elements for 8-bit data (no
-// clamp: a value never equals the sentinel) and for 16-bit data, 32-bit
-// elements for 32-bit data
+// 3-D kernel pointers by value class: bytes for 8-bit data (sentinel 0xff,
+// clamped), 16-bit elements for 16-bit data, 32-bit elements for 32-bit data
 const void* da3_kernel_for_dtype(int dtype)
 {
-    if (dtype == MF_U8) return (const void*)mf_da3_kernel<uint16_t, false>;
+    if (dtype == MF_U8) return (const void*)mf_da3_kernel<uint8_t, true>;
     if (dtype == MF_U16) return (const void*)mf_da3_kernel<uint16_t, true>;
     return (const void*)mf_da3_kernel<uint32_t, true>;
 }
@@ -868,7 +867,7 @@ hipError_t mf_da3_launch(const void* src, void* dst, int D, int H, int W, long l
     const int bw = e->tw * e->groups;     // voxels of a work-group along x
     const int ntx = (W + bw - 1) / bw, nty = (H + e->th - 1) / e->th, ntz = (D + e->tz - 1) / e->tz;
     if ((long long)ntx * nty * ntz > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    const size_t lds = (size_t)e->arena * e->es * e->groups;
+    const size_t lds = (size_t)e->arena * (dtype == MF_U8 ? 1 : e->es) * e->groups;
     void* args[] = {&src, &dst, &D, &H, &W, &pitch, &slice, &dtype, &a, (void*)&ntx, (void*)&nty};
     return hipLaunchKernel(da3_kernel_for_dtype(dtype), dim3(ntx * nty * ntz), dim3(kDaThreads), args, lds, stream);
 }
