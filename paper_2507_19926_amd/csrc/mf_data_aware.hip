@@ -17,14 +17,19 @@
 //
 // A merge is cut into chunks of one length per round: a lane finds its
 // chunk's start in the two sorted input windows with a co-rank binary search
-// of a fixed number of halving steps and then takes that many sequential
-// merge steps, each a compare, a min, an LDS store and two LDS loads at
-// addresses derived from one index (every stored list ends with a sentinel,
-// so no step tests for an exhausted input). Only the ranks some later step
-// can read are produced (forgetting and pruning as output windows).
+// (run as a wave-uniform loop of the wave's largest step count) and then
+// emits four outputs per step: the four smallest of the next four elements
+// of each input, by a half-cleaner and a bitonic sort of four (every stored
+// list ends with sentinels, so no step tests for an exhausted input). Only
+// the ranks some later step can read are produced (forgetting and pruning as
+// output windows).
 //
-// 8/16-bit data is held as 16-bit LDS elements, 32-bit data (uint32, float32
-// through an order-preserving key) as 32-bit elements.
+// 8-bit data is held as 8-bit LDS elements (16-bit in the global-memory
+// form), 16-bit data as 16-bit elements, 32-bit data (uint32, float32 through
+// an order-preserving key) as 32-bit elements; 8- and 16-bit steps work on
+// packed 16-bit pairs. Work-groups of the one-plane and 3-D kernels take
+// their tiles in contiguous runs per XCD, so each L2 serves neighbouring
+// footprints.
 #include <mutex>
 
 #include "mf_internal.h"
@@ -668,7 +673,6 @@ static MfDaArgs da_args(const DaEntry* e, const uint32_t* blob)
     a.c_off = e->c_off;
     a.r_off = e->r_off;
     a.nrounds = e->nrounds;
-    a.l_off = e->l_off;
     a.o_off = e->o_off;
     a.arena = e->arena;
     a.groups = e->groups;

@@ -69,7 +69,7 @@ int mf_da_list(int dtype, int k, int* tw, int* th, int* group, int cap, int* for
 // schedule offsets are filled into *args (see mf_da_batched_args).
 struct MfDaArgs {
     const uint32_t* blob;
-    int k, kh, tw, th, c_off, r_off, nrounds, l_off, o_off, arena;   // window k columns x kh rows
+    int k, kh, tw, th, c_off, r_off, nrounds, o_off, arena;   // window k columns x kh rows
     int groups;   // lane groups per work-group, each with its own root tiles
     int kz, tz;   // 3-D boxes: box depth and root tile depth (1 for planes)
 };
