@@ -112,13 +112,14 @@ MAX_GROUPS = 32      # lane groups per work-group: at least 16 lanes each
 
 def lane_groups(S: dagen.Schedule, elem_bytes: int = 4) -> int:
     """Lane groups G for a small root tile: enough groups that a group's
-    kDaThreads/G lanes match the schedule's mean items per round (lanes
-    beyond that would idle), a power of two <= MAX_GROUPS, and G arenas
-    within half the LDS (two work-groups per CU)."""
+    kDaThreads/G lanes are at least half the schedule's mean items per round
+    (each lane then runs one or two items a round, and fewer idle), a power
+    of two <= MAX_GROUPS, and G arenas within half the LDS (two work-groups
+    per CU)."""
     rounds = max(1, len(S.rounds) - 1)
     mean = max(1.0, len(S.items) / rounds)
     g = 1
-    while g < MAX_GROUPS and dagen.LANES / (2 * g) >= mean:
+    while g < MAX_GROUPS and dagen.LANES / (2 * g) >= mean / 2:
         g *= 2
     while g > 1 and g * S.arena * elem_bytes > LDS_BYTES // 2:
         g //= 2
@@ -224,19 +225,20 @@ def generate(out_dir: str, workers: int | None = None) -> dict:
             # rectangular windows keep one tile (no tuned choice), shared by
             # both element sizes: the best one that lets three work-groups of
             # 32-bit elements share a CU, the budget most square windows up
-            # to k = 31 are tuned to
+            # to k = 31 are tuned to; the lane groups per work-group follow
+            # the element size
             if kw == kh:
                 opts = [(tw, th, 1, 1, mi) for (tw, th, mi) in candidates(kw, es, cache, modes=MODES)]
             else:
                 # small tiles run several to a work-group in lane groups;
                 # their schedule is cut for the group's lanes
                 tw, th, mi = candidates(kw, 4, cache, kh, LDS_BUDGETS[:1])[0]
-                opts = [(tw, th, 1, lane_groups(cache[(kw, kh, tw, th, MODES[mi])]), mi)]
+                opts = [(tw, th, 1, lane_groups(cache[(kw, kh, tw, th, MODES[mi])], es), mi)]
             for (tw, th, T, G, mi) in opts:
                 key = (kw, kh, tw, th, G, MODES[mi])
                 S = cache[(kw, kh, tw, th, MODES[mi])] if G == 1 else \
                     dagen.schedule(kw, tw, th, kh=kh, lanes=dagen.LANES // G, rounds=MODES[mi])
-                assert S.arena * (es if kw == kh else 4) * T * G <= LDS_BYTES
+                assert S.arena * es * T * G <= LDS_BYTES
                 entries.append((kw, kh, 1, es, tw, th, 1, T, G, 0, mi) + place(S, key))
         # global-memory form (square windows): lists in a device workspace,
         # so the tile is not bounded by the LDS

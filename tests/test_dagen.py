@@ -140,7 +140,7 @@ def test_blob_layout_as_the_kernel_reads_it(tmp_path):
     box = [r for r in rows if r[2] > 1]
     assert sorted((r[0], r[3]) for r in box) == sorted((k, es) for k in emit_da.K3 for es in (2, 4))
     r = [r for r in box if r[0] == 7 and r[3] == 2][0]
-    S = dg.schedule3(7, 7, 7, r[4], r[5], r[6], rounds="asap")
+    S = dg.schedule3(7, 7, 7, r[4], r[5], r[6], lanes=dg.LANES // r[8], rounds="asap")
     assert np.array_equal(blob[r[11]:r[11] + 4 * r[12]].reshape(-1, 4), S.items) and r[18] == S.arena
     # both round modes are offered for square windows
     sq = [r for r in rows if r[2] == 1 and r[0] == r[1] and r[9] == 0 and r[0] == 25]
