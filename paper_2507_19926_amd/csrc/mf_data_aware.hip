@@ -70,6 +70,46 @@ __device__ __forceinline__ uint32_t mf_da_key_to_f32(uint32_t k)
     return k ^ ((uint32_t)((int32_t)~k >> 31) | 0x80000000u);
 }
 
+// Arena addressing of the sort items and the 8- and 16-bit merge steps.
+// With the arena in LDS (LDS = true) a location is its LDS byte address: no
+// base register to add per access. The global-memory form keeps the arena in
+// device memory; there a location is a byte offset from the arena base gb.
+typedef __attribute__((address_space(3))) uint32_t mf_lds_u32;
+typedef uint32_t mf_u32x2 __attribute__((ext_vector_type(2)));
+template <bool LDS>
+__device__ __forceinline__ uint32_t mf_da_addr(const unsigned char* gb, const void* p)
+{
+    if constexpr (LDS)
+        return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) unsigned char*)p;
+    else
+        return (uint32_t)((const unsigned char*)p - gb);
+}
+// the aligned dword holding location x
+template <bool LDS>
+__device__ __forceinline__ auto mf_da_dw(const unsigned char* gb, uint32_t x)
+{
+    if constexpr (LDS)
+        return (const mf_lds_u32*)(uintptr_t)(x & ~3u);
+    else
+        return reinterpret_cast<const uint32_t*>(gb + (x & ~3u));
+}
+template <bool LDS, class T>
+__device__ __forceinline__ void mf_da_put(unsigned char* gb, uint32_t x, T v)
+{
+    if constexpr (LDS)
+        *(__attribute__((address_space(3))) T*)(uintptr_t)x = v;
+    else
+        *reinterpret_cast<T*>(gb + x) = v;
+}
+template <bool LDS, class E>
+__device__ __forceinline__ E mf_da_get(const unsigned char* gb, uint32_t x)
+{
+    if constexpr (LDS)
+        return *(const __attribute__((address_space(3))) E*)(uintptr_t)x;
+    else
+        return *reinterpret_cast<const E*>(gb + x);
+}
+
 // Batcher's odd-even merge sort of N (a power of two) values in registers,
 // fully unrolled: every index is a compile-time constant.
 template <int N>
@@ -94,35 +134,42 @@ __device__ __forceinline__ void mf_da_sortnet(uint32_t* v)
 // parallel lines of n values; padded to N with the sentinel), sorted by the
 // network; ranks [lo, lo+cnt) are written from out, followed by MF_DA_SENT
 // sentinels.
-template <class E, int N>
+template <class E, int N, bool LDS>
 __device__ __forceinline__ void mf_da_sort(E* __restrict__ gl, const uint4 d)
 {
     constexpr uint32_t kMask = (1u << 18) - 1;
     constexpr uint32_t kMax = (uint32_t)(E)~(E)0;
+    constexpr uint32_t es = sizeof(E);
     const int base = (int)(d.x & kMask), n = (int)(d.x >> 18);
     const int stride = (int)(d.y & kMask), lo = (int)(d.y >> 18);
     const int oo = (int)(d.z & kMask), cnt = (int)(d.z >> 18);
     const int lines = (int)((d.w >> 6) & 7u), lstep = (int)((d.w >> 9) & ((1u << 22) - 1));
-    const int total = n * lines, back = lstep - n * stride;
+    const int total = n * lines;
+    // locations as in the merge steps (LDS byte addresses in LDS arenas), so
+    // that the arena base is needed once per item, not per value
+    unsigned char* gb = reinterpret_cast<unsigned char*>(gl);
+    const uint32_t xs = (uint32_t)stride * es, xback = ((uint32_t)lstep - (uint32_t)(n * stride)) * es;
     uint32_t v[N];
-    int e = 0, off = base;
+    int e = 0;
+    uint32_t x = mf_da_addr<LDS>(gb, gl + base);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        v[i] = i < total ? (uint32_t)gl[off] : kMax;
+        v[i] = i < total ? (uint32_t)mf_da_get<LDS, E>(gb, x) : kMax;
         // next value: along the line, or the first of the next line
         ++e;
-        off += stride;
+        x += xs;
         const bool wrap = e == n;
         e = wrap ? 0 : e;
-        off = wrap ? off + back : off;
+        x = wrap ? x + xback : x;
     }
     mf_da_sortnet<N>(v);
-    E* out = gl + oo - lo;
+    const uint32_t xo = mf_da_addr<LDS>(gb, gl + oo) - (uint32_t)lo * es;
 #pragma unroll
     for (int i = 0; i < N; ++i)
-        if (i >= lo && i < lo + cnt) out[i] = (E)v[i];
+        if (i >= lo && i < lo + cnt) mf_da_put<LDS>(gb, xo + (uint32_t)i * es, (E)v[i]);
+    const uint32_t xe = mf_da_addr<LDS>(gb, gl + oo + cnt);
 #pragma unroll
-    for (int i = 0; i < MF_DA_SENT; ++i) gl[oo + cnt + i] = (E)kMax;
+    for (int i = 0; i < MF_DA_SENT; ++i) mf_da_put<LDS>(gb, xe + (uint32_t)i * es, (E)kMax);
 }
 
 // Four consecutive 32-bit elements gl[e..e+3].
@@ -158,29 +205,53 @@ __device__ __forceinline__ uint32_t mf_pk_gt01(uint32_t x, uint32_t y)
 }
 __device__ __forceinline__ uint32_t mf_swap16(uint32_t x) { return __builtin_amdgcn_alignbit(x, x, 16); }
 
-// Four consecutive 16-bit elements from byte offset x (even) on, as the
-// pairs (x, x+2) and (x+4, x+6): the three aligned dwords that hold them,
-// shifted into place (v_alignbit takes the shift modulo 32, so x * 8 gives 0
-// or 16).
-__device__ __forceinline__ void mf_da_get4_pk(const unsigned char* __restrict__ gb, uint32_t x, uint32_t& lo,
-                                              uint32_t& hi)
+// Bytes of v spread by selector sel into the 16-bit halves (v_perm with a
+// zero first source). The selector is taken from a scalar register: as a
+// constant the compiler keeps it in a vector register, which in the 64-VGPR
+// builds it rematerialises at every step.
+__device__ __forceinline__ uint32_t mf_perm0(uint32_t v, uint32_t sel)
 {
-    const uint32_t* __restrict__ w = reinterpret_cast<const uint32_t*>(gb + (x & ~3u));
-    const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
-    lo = __builtin_amdgcn_alignbit(w1, w0, x << 3);
-    hi = __builtin_amdgcn_alignbit(w2, w1, x << 3);
+    uint32_t r;
+    asm("v_perm_b32 %0, 0, %1, %2" : "=v"(r) : "v"(v), "s"(sel));
+    return r;
 }
 
-// Four consecutive 8-bit elements from byte offset x on, widened to the
-// 16-bit pairs (x, x+1) and (x+2, x+3): the two aligned dwords that hold
-// them, shifted into place, then spread over 16-bit halves.
-__device__ __forceinline__ void mf_da_get4_u8(const unsigned char* __restrict__ gb, uint32_t x, uint32_t& lo,
-                                              uint32_t& hi)
+// Four consecutive 8-bit elements from location x on, widened to the 16-bit
+// pairs (x, x+1) and (x+2, x+3): the two aligned dwords that hold them,
+// shifted into place (v_alignbyte takes the shift from the location's low
+// two bits), then spread over 16-bit halves. _rev gives the four in reverse
+// order, as the pairs (x+3, x+2) and (x+1, x).
+template <bool LDS>
+__device__ __forceinline__ uint32_t mf_da_at4_u8(const unsigned char* gb, uint32_t x)
 {
-    const uint32_t* __restrict__ w = reinterpret_cast<const uint32_t*>(gb + (x & ~3u));
-    const uint32_t v = __builtin_amdgcn_alignbyte(w[1], w[0], x & 3u);
-    lo = __builtin_amdgcn_perm(0u, v, 0x0c010c00u);
-    hi = __builtin_amdgcn_perm(0u, v, 0x0c030c02u);
+    const auto w = mf_da_dw<LDS>(gb, x);
+    return __builtin_amdgcn_alignbyte(w[1], w[0], x);
+}
+template <bool LDS>
+__device__ __forceinline__ void mf_da_get4_u8(const unsigned char* gb, uint32_t x, uint32_t& lo, uint32_t& hi)
+{
+    const uint32_t v = mf_da_at4_u8<LDS>(gb, x);
+    lo = mf_perm0(v, 0x0c010c00u);
+    hi = mf_perm0(v, 0x0c030c02u);
+}
+template <bool LDS>
+__device__ __forceinline__ void mf_da_get4_u8_rev(const unsigned char* gb, uint32_t x, uint32_t& r32,
+                                                  uint32_t& r10)
+{
+    const uint32_t v = mf_da_at4_u8<LDS>(gb, x);
+    r32 = mf_perm0(v, 0x0c020c03u);
+    r10 = mf_perm0(v, 0x0c000c01u);
+}
+// Four consecutive 16-bit elements from location x (even) on, as the pairs
+// (x, x+2) and (x+4, x+6): the three aligned dwords that hold them, shifted
+// into place (by 0 or 2 bytes, from the location's low two bits).
+template <bool LDS>
+__device__ __forceinline__ void mf_da_get4_pk(const unsigned char* gb, uint32_t x, uint32_t& lo, uint32_t& hi)
+{
+    const auto w = mf_da_dw<LDS>(gb, x);
+    const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
+    lo = __builtin_amdgcn_alignbyte(w1, w0, x);
+    hi = __builtin_amdgcn_alignbyte(w2, w1, x);
 }
 
 // Merge chunk: co-rank of rank r0 in (A window, B window), A first on ties,
@@ -198,7 +269,7 @@ __device__ __forceinline__ void mf_da_get4_u8(const unsigned char* __restrict__ 
 // every step writes one aligned run of four. CLAMP keeps the A index at the
 // window end: needed when data can equal the sentinel value (16-bit and
 // 32-bit data), not for 8-bit data held in 16-bit elements.
-template <class E, bool CLAMP>
+template <class E, bool CLAMP, bool LDS>
 __device__ __forceinline__ void mf_da_merge(E* __restrict__ gl, const uint4 d)
 {
     constexpr uint32_t kMask = (1u << 18) - 1;
@@ -229,55 +300,66 @@ __device__ __forceinline__ void mf_da_merge(E* __restrict__ gl, const uint4 d)
     int ia = pos;
     const int br = bo + r0;                // B's head of step q0 is element br + q0 - ia
     if constexpr (sizeof(E) == 1) {
-        // 8-bit elements: the 16-bit step on the widened pairs, outputs
-        // narrowed back to one aligned dword
-        const unsigned char* __restrict__ gb = reinterpret_cast<const unsigned char*>(gl);
-        uint32_t xa = (uint32_t)(ao + ia), xb = (uint32_t)(br - ia);
-        for (int q0 = 0; q0 < nvalid; q0 += 4) {
-            uint32_t a01, a23, b01, b23;
-            mf_da_get4_u8(gb, xa, a01, a23);
-            mf_da_get4_u8(gb, xb, b01, b23);
-            const uint32_t r32 = mf_swap16(b23), r10 = mf_swap16(b01);
+        // 8-bit elements: the 16-bit step on the widened pairs, heads and
+        // output as LDS byte addresses. The half-cleaner pairs (a0,a1) with
+        // (b3,b2) and (a2,a3) with (b1,b0); a halve's 0/1 "A element larger"
+        // flags summed over both pairs give g in {0,1,2} per half, and the
+        // number of A elements taken, (2-g.lo) + (2-g.hi), is v_sad_u16 of g
+        // against (2,2), added to the A head in the same instruction. The
+        // bitonic sort's second stage compares (x0,x2) with (x1,x3), regrouped
+        // by v_perm, and the narrowing interleaves its minima and maxima.
+        unsigned char* gb = reinterpret_cast<unsigned char*>(gl);
+        uint32_t xa = mf_da_addr<LDS>(gb, A) + (uint32_t)ia;
+        const uint32_t xend = mf_da_addr<LDS>(gb, A) + (uint32_t)na;
+        uint32_t xo = mf_da_addr<LDS>(gb, gl + oo);
+        const uint32_t xo_end = xo + (uint32_t)nvalid;
+        // A head + B head == output + F at every step
+        const uint32_t F = mf_da_addr<LDS>(gb, B) + (uint32_t)r0 + mf_da_addr<LDS>(gb, A) - xo;
+        uint32_t xb = xo + F - xa;
+        for (; xo < xo_end; xo += 4) {
+            uint32_t a01, a23, r32, r10;
+            mf_da_get4_u8<LDS>(gb, xa, a01, a23);
+            mf_da_get4_u8_rev<LDS>(gb, xb, r32, r10);
             const uint32_t c01 = mf_pk_min(a01, r32), c23 = mf_pk_min(a23, r10);
-            const uint32_t gt = mf_pk_gt01(a01, r32) + mf_pk_gt01(a23, r10);
-            const int nA = 4 - (int)((gt & 0xffffu) + (gt >> 16));
+            const uint32_t g = mf_pk_gt01(a01, r32) + mf_pk_gt01(a23, r10);
             const uint32_t x01 = mf_pk_min(c01, c23), x23 = mf_pk_max(c01, c23);
-            const uint32_t s01 = mf_swap16(x01), s23 = mf_swap16(x23);
-            const uint32_t y01 = (mf_pk_min(x01, s01) & 0xffffu) | (mf_pk_max(x01, s01) & 0xffff0000u);
-            const uint32_t y23 = (mf_pk_min(x23, s23) & 0xffffu) | (mf_pk_max(x23, s23) & 0xffff0000u);
-            *reinterpret_cast<uint32_t*>(gl + oo + q0) = __builtin_amdgcn_perm(y23, y01, 0x06040200u);
-            int ia2 = ia + nA;
-            if constexpr (CLAMP) ia2 = min(ia2, na);
-            xa += (uint32_t)(ia2 - ia);
-            xb += 4u - (uint32_t)(ia2 - ia);
-            ia = ia2;
+            const uint32_t p02 = __builtin_amdgcn_perm(x23, x01, 0x05040100u);
+            const uint32_t p13 = __builtin_amdgcn_perm(x23, x01, 0x07060302u);
+            const uint32_t mn = mf_pk_min(p02, p13), mx = mf_pk_max(p02, p13);
+            mf_da_put<LDS>(gb, xo, __builtin_amdgcn_perm(mx, mn, 0x06020400u));
+            xa = __builtin_amdgcn_sad_u16(g, 0x00020002u, xa);
+            if constexpr (CLAMP) xa = min(xa, xend);
+            xb = xo + 4u + F - xa;
         }
     } else if constexpr (sizeof(E) == 2) {
-        // the step on pairs: (a0,a1) meets (b3,b2) and (a2,a3) meets (b1,b0);
-        // an A element is taken unless it exceeds its partner, i.e. unless
-        // their saturating difference is nonzero
-        // the heads as byte offsets from the arena base
-        const unsigned char* __restrict__ gb = reinterpret_cast<const unsigned char*>(gl);
-        uint32_t xa = 2u * (uint32_t)(ao + ia), xb = 2u * (uint32_t)(br - ia);
-        for (int q0 = 0; q0 < nvalid; q0 += 4) {
+        // the step on pairs, as for 8-bit elements: (a0,a1) meets (b3,b2) and
+        // (a2,a3) meets (b1,b0); heads and output as LDS byte addresses, two
+        // bytes per element, so the flags are doubled before v_sad_u16 adds
+        // twice the number of A elements taken to the A head
+        unsigned char* gb = reinterpret_cast<unsigned char*>(gl);
+        uint32_t xa = mf_da_addr<LDS>(gb, A) + 2u * (uint32_t)ia;
+        const uint32_t xend = mf_da_addr<LDS>(gb, A) + 2u * (uint32_t)na;
+        uint32_t xo = mf_da_addr<LDS>(gb, gl + oo);
+        const uint32_t xo_end = xo + 2u * (uint32_t)nvalid;
+        const uint32_t F = mf_da_addr<LDS>(gb, B) + 2u * (uint32_t)r0 + mf_da_addr<LDS>(gb, A) - xo;
+        uint32_t xb = xo + F - xa;
+        for (; xo < xo_end; xo += 8) {
             uint32_t a01, a23, b01, b23;
-            mf_da_get4_pk(gb, xa, a01, a23);
-            mf_da_get4_pk(gb, xb, b01, b23);
+            mf_da_get4_pk<LDS>(gb, xa, a01, a23);
+            mf_da_get4_pk<LDS>(gb, xb, b01, b23);
             const uint32_t r32 = mf_swap16(b23), r10 = mf_swap16(b01);
             const uint32_t c01 = mf_pk_min(a01, r32), c23 = mf_pk_min(a23, r10);
-            const uint32_t gt = mf_pk_gt01(a01, r32) + mf_pk_gt01(a23, r10);
-            const int nA = 4 - (int)((gt & 0xffffu) + (gt >> 16));
+            const uint32_t g2 = (mf_pk_gt01(a01, r32) + mf_pk_gt01(a23, r10)) << 1;
             // bitonic sort of four
             const uint32_t x01 = mf_pk_min(c01, c23), x23 = mf_pk_max(c01, c23);
-            const uint32_t s01 = mf_swap16(x01), s23 = mf_swap16(x23);
-            const uint32_t y01 = (mf_pk_min(x01, s01) & 0xffffu) | (mf_pk_max(x01, s01) & 0xffff0000u);
-            const uint32_t y23 = (mf_pk_min(x23, s23) & 0xffffu) | (mf_pk_max(x23, s23) & 0xffff0000u);
-            *reinterpret_cast<uint2*>(gl + oo + q0) = make_uint2(y01, y23);
-            int ia2 = ia + nA;
-            if constexpr (CLAMP) ia2 = min(ia2, na);
-            xa += 2u * (uint32_t)(ia2 - ia);
-            xb += 8u - 2u * (uint32_t)(ia2 - ia);
-            ia = ia2;
+            const uint32_t p02 = __builtin_amdgcn_perm(x23, x01, 0x05040100u);
+            const uint32_t p13 = __builtin_amdgcn_perm(x23, x01, 0x07060302u);
+            const uint32_t mn = mf_pk_min(p02, p13), mx = mf_pk_max(p02, p13);
+            mf_da_put<LDS>(gb, xo, mf_u32x2{__builtin_amdgcn_perm(mx, mn, 0x05040100u),
+                                            __builtin_amdgcn_perm(mx, mn, 0x07060302u)});
+            xa = __builtin_amdgcn_sad_u16(g2, 0x00040004u, xa);
+            if constexpr (CLAMP) xa = min(xa, xend);
+            xb = xo + 8u + F - xa;
         }
     } else {
         for (int q0 = 0; q0 < nvalid; q0 += 4) {
@@ -340,7 +422,7 @@ mf_da_load(E* __restrict__ gl, const unsigned char* __restrict__ src, int H, int
 
 // Rounds [r0, r1) of the schedule on one arena, lane lt of the L lanes that
 // share it; a work-group barrier after every round.
-template <class E, bool CLAMP>
+template <class E, bool CLAMP, bool LDS = true>
 __device__ __forceinline__ void mf_da_rounds(E* __restrict__ gl, const MfDaArgs& a, int r0, int r1, int lt, int L)
 {
     const uint32_t* __restrict__ blob = a.blob;
@@ -352,19 +434,31 @@ __device__ __forceinline__ void mf_da_rounds(E* __restrict__ gl, const MfDaArgs&
             const uint4 d = items[c];
             if (d.w & 0x80000000u) {
                 switch (d.w & 63u) {
-                case 1: mf_da_sort<E, 1>(gl, d); break;
-                case 2: mf_da_sort<E, 2>(gl, d); break;
-                case 4: mf_da_sort<E, 4>(gl, d); break;
-                case 8: mf_da_sort<E, 8>(gl, d); break;
-                case 16: mf_da_sort<E, 16>(gl, d); break;
-                default: mf_da_sort<E, 32>(gl, d); break;
+                case 1: mf_da_sort<E, 1, LDS>(gl, d); break;
+                case 2: mf_da_sort<E, 2, LDS>(gl, d); break;
+                case 4: mf_da_sort<E, 4, LDS>(gl, d); break;
+                case 8: mf_da_sort<E, 8, LDS>(gl, d); break;
+                case 16: mf_da_sort<E, 16, LDS>(gl, d); break;
+                default: mf_da_sort<E, 32, LDS>(gl, d); break;
                 }
             } else {
-                mf_da_merge<E, CLAMP>(gl, d);
+                mf_da_merge<E, CLAMP, LDS>(gl, d);
             }
         }
         __syncthreads();
     }
+}
+
+// All rounds on the LDS arena of lane group gi. When a group spans whole
+// waves (L >= 64) the arena base is the same on every lane of a wave and is
+// kept in a scalar register; otherwise it is per lane.
+template <class E, bool CLAMP>
+__device__ __forceinline__ void mf_da_rounds_lds(E* __restrict__ lds, const MfDaArgs& a, int gi, int lt, int L)
+{
+    if (L >= 64)
+        mf_da_rounds<E, CLAMP>(lds + __builtin_amdgcn_readfirstlane(gi) * a.arena, a, 0, a.nrounds, lt, L);
+    else
+        mf_da_rounds<E, CLAMP>(lds + gi * a.arena, a, 0, a.nrounds, lt, L);
 }
 
 // Medians of G root tiles (bx*G + t, by) from their arenas to dst.
@@ -416,7 +510,7 @@ mf_da_block(const unsigned char* __restrict__ src, unsigned char* __restrict__ d
     const int gi = threadIdx.x / L, lt = threadIdx.x - gi * L;
     mf_da_load<E>(lds, src, H, W, pitch, dtype, a, G, bx, by);
     __syncthreads();
-    mf_da_rounds<E, CLAMP>(lds + gi * a.arena, a, 0, a.nrounds, lt, L);
+    mf_da_rounds_lds<E, CLAMP>(lds, a, gi, lt, L);
     mf_da_store<E>(lds, dst, H, W, pitch, dtype, a, G, bx, by);
 }
 
@@ -477,7 +571,7 @@ mf_dag_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__
         mf_da_load<E>(gl, src + plane * plane_stride, H, W, pitch, dtype, a, 1, bx, by);
         __syncthreads();
     }
-    mf_da_rounds<E, CLAMP>(gl, a, r0, r1, threadIdx.x, kDaThreads);
+    mf_da_rounds<E, CLAMP, false>(gl, a, r0, r1, threadIdx.x, kDaThreads);
     if (last) mf_da_store<E>(gl, dst + plane * plane_stride, H, W, pitch, dtype, a, 1, bx, by);
 }
 
@@ -523,7 +617,7 @@ mf_da3_kernel(const unsigned char* __restrict__ src, unsigned char* __restrict__
     if (threadIdx.x < G * MF_DA_SENT)
         lds[(threadIdx.x / MF_DA_SENT) * a.arena + MF_DA_GUARD - MF_DA_SENT + threadIdx.x % MF_DA_SENT] = (E)kMax;
     __syncthreads();
-    mf_da_rounds<E, CLAMP>(lds + gi * a.arena, a, 0, a.nrounds, lt, L);
+    mf_da_rounds_lds<E, CLAMP>(lds, a, gi, lt, L);
     const uint32_t* outs = a.blob + a.o_off;
     const int tv = a.tw * a.th * a.tz;
     for (int q = threadIdx.x; q < G * tv; q += kDaThreads) {
