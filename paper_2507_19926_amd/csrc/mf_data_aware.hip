@@ -76,6 +76,7 @@ __device__ __forceinline__ uint32_t mf_da_key_to_f32(uint32_t k)
 // device memory; there a location is a byte offset from the arena base gb.
 typedef __attribute__((address_space(3))) uint32_t mf_lds_u32;
 typedef uint32_t mf_u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t mf_u32x4 __attribute__((ext_vector_type(4)));
 template <bool LDS>
 __device__ __forceinline__ uint32_t mf_da_addr(const unsigned char* gb, const void* p)
 {
@@ -172,14 +173,6 @@ __device__ __forceinline__ void mf_da_sort(E* __restrict__ gl, const uint4 d)
     for (int i = 0; i < MF_DA_SENT; ++i) mf_da_put<LDS>(gb, xe + (uint32_t)i * es, (E)kMax);
 }
 
-// Four consecutive 32-bit elements gl[e..e+3].
-template <class E>
-__device__ __forceinline__ void mf_da_get4(const E* __restrict__ gl, int e, uint32_t* v)
-{
-#pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = (uint32_t)gl[e + i];
-}
-
 // Two 16-bit values per 32-bit register (element 2j in the low half).
 typedef unsigned short mf_u16x2 __attribute__((ext_vector_type(2)));
 
@@ -204,6 +197,28 @@ __device__ __forceinline__ uint32_t mf_pk_gt01(uint32_t x, uint32_t y)
     return r;
 }
 __device__ __forceinline__ uint32_t mf_swap16(uint32_t x) { return __builtin_amdgcn_alignbit(x, x, 16); }
+
+// [a0 <= b0] + [a1 <= b1] + [a2 <= b2] + [a3 <= b3] (unsigned): a compare
+// per pair, the first result selected as 0/1, the others added through the
+// carry. Written as the instructions themselves: the compiler otherwise builds
+// a bit mask and counts its bits, twice the instructions.
+__device__ __forceinline__ uint32_t mf_count_le4(uint32_t a0, uint32_t b0, uint32_t a1, uint32_t b1, uint32_t a2,
+                                                 uint32_t b2, uint32_t a3, uint32_t b3)
+{
+    uint32_t n;
+    asm("v_cmp_le_u32 vcc, %1, %2\n\t"
+        "v_cndmask_b32 %0, 0, 1, vcc\n\t"
+        "v_cmp_le_u32 vcc, %3, %4\n\t"
+        "v_addc_co_u32 %0, vcc, 0, %0, vcc\n\t"
+        "v_cmp_le_u32 vcc, %5, %6\n\t"
+        "v_addc_co_u32 %0, vcc, 0, %0, vcc\n\t"
+        "v_cmp_le_u32 vcc, %7, %8\n\t"
+        "v_addc_co_u32 %0, vcc, 0, %0, vcc"
+        : "=&v"(n)
+        : "v"(a0), "v"(b0), "v"(a1), "v"(b1), "v"(a2), "v"(b2), "v"(a3), "v"(b3)
+        : "vcc");
+    return n;
+}
 
 // Bytes of v spread by selector sel into the 16-bit halves (v_perm with a
 // zero first source). The selector is taken from a scalar register: as a
@@ -297,8 +312,7 @@ __device__ __forceinline__ void mf_da_merge(E* __restrict__ gl, const uint4 d)
         const uint32_t av = A[tc], bv = Bm[-tc];
         pos = av <= bv ? tc + 1 : pos;
     }
-    int ia = pos;
-    const int br = bo + r0;                // B's head of step q0 is element br + q0 - ia
+    const int ia = pos;
     if constexpr (sizeof(E) == 1) {
         // 8-bit elements: the 16-bit step on the widened pairs, heads and
         // output as LDS byte addresses. The half-cleaner pairs (a0,a1) with
@@ -362,24 +376,32 @@ __device__ __forceinline__ void mf_da_merge(E* __restrict__ gl, const uint4 d)
             xb = xo + 8u + F - xa;
         }
     } else {
-        for (int q0 = 0; q0 < nvalid; q0 += 4) {
-            uint32_t a[4], b[4], c[4];
-            mf_da_get4<E>(gl, ao + ia, a);
-            mf_da_get4<E>(gl, br + q0 - ia, b);
-            int nA = 0;
+        // 32-bit elements, heads and output as locations (four bytes per
+        // element); the number of A elements taken counted by a compare and
+        // add-with-carry chain
+        unsigned char* gb = reinterpret_cast<unsigned char*>(gl);
+        uint32_t xa = mf_da_addr<LDS>(gb, A) + 4u * (uint32_t)ia;
+        const uint32_t xend = mf_da_addr<LDS>(gb, A) + 4u * (uint32_t)na;
+        uint32_t xo = mf_da_addr<LDS>(gb, gl + oo);
+        const uint32_t xo_end = xo + 4u * (uint32_t)nvalid;
+        const uint32_t F = mf_da_addr<LDS>(gb, B) + 4u * (uint32_t)r0 + mf_da_addr<LDS>(gb, A) - xo;
+        uint32_t xb = xo + F - xa;
+        for (; xo < xo_end; xo += 16) {
+            uint32_t a[4], b[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const bool takeA = a[i] <= b[3 - i];
-                c[i] = takeA ? a[i] : b[3 - i];
-                nA += takeA ? 1 : 0;
+                a[i] = mf_da_get<LDS, uint32_t>(gb, xa + 4u * i);
+                b[i] = mf_da_get<LDS, uint32_t>(gb, xb + 4u * i);
             }
+            const uint32_t c0 = min(a[0], b[3]), c1 = min(a[1], b[2]), c2 = min(a[2], b[1]), c3 = min(a[3], b[0]);
+            const uint32_t nA = mf_count_le4(a[0], b[3], a[1], b[2], a[2], b[1], a[3], b[0]);
             // bitonic sort of four
-            const uint32_t x0 = min(c[0], c[2]), x2 = max(c[0], c[2]);
-            const uint32_t x1 = min(c[1], c[3]), x3 = max(c[1], c[3]);
-            *reinterpret_cast<uint4*>(gl + oo + q0) =
-                make_uint4(min(x0, x1), max(x0, x1), min(x2, x3), max(x2, x3));
-            ia += nA;
-            if constexpr (CLAMP) ia = min(ia, na);
+            const uint32_t x0 = min(c0, c2), x2 = max(c0, c2);
+            const uint32_t x1 = min(c1, c3), x3 = max(c1, c3);
+            mf_da_put<LDS>(gb, xo, mf_u32x4{min(x0, x1), max(x0, x1), min(x2, x3), max(x2, x3)});
+            xa += 4u * nA;
+            if constexpr (CLAMP) xa = min(xa, xend);
+            xb = xo + 16u + F - xa;
         }
     }
     if (d.w & (1u << 22)) {
