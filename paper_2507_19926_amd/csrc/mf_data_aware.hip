@@ -27,9 +27,11 @@
 // 8-bit data is held as 8-bit LDS elements (16-bit in the global-memory
 // form), 16-bit data as 16-bit elements, 32-bit data (uint32, float32 through
 // an order-preserving key) as 32-bit elements; 8- and 16-bit steps work on
-// packed 16-bit pairs. Work-groups of the one-plane and 3-D kernels take
-// their tiles in contiguous runs per XCD, so each L2 serves neighbouring
-// footprints.
+// packed 16-bit pairs. Steps and sort items address the LDS arena by byte
+// address; when a lane group spans whole waves the arena base (and, for 8-
+// and 16-bit elements, the item loop) lives in scalar registers. Work-groups
+// of the one-plane and 3-D kernels take their tiles in contiguous runs per
+// XCD, so each L2 serves neighbouring footprints.
 #include <mutex>
 
 #include "mf_internal.h"
