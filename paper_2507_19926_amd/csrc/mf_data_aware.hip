@@ -324,14 +324,18 @@ __device__ __forceinline__ void mf_da_merge(E* __restrict__ gl, const uint4 d)
         // against (2,2), added to the A head in the same instruction. The
         // bitonic sort's second stage compares (x0,x2) with (x1,x3), regrouped
         // by v_perm, and the narrowing interleaves its minima and maxima.
+        // The B head advances by the B elements taken, g.lo + g.hi (v_sad_u16
+        // against 0). When the clamp pulls the A head back, the A elements it
+        // took past its window tied with B's head and every later output of
+        // the chunk has that value (the elements after a window rank after
+        // the chunk's outputs), so the B elements left behind yield the same
+        // outputs.
         unsigned char* gb = reinterpret_cast<unsigned char*>(gl);
         uint32_t xa = mf_da_addr<LDS>(gb, A) + (uint32_t)ia;
         const uint32_t xend = mf_da_addr<LDS>(gb, A) + (uint32_t)na;
         uint32_t xo = mf_da_addr<LDS>(gb, gl + oo);
         const uint32_t xo_end = xo + (uint32_t)nvalid;
-        // A head + B head == output + F at every step
-        const uint32_t F = mf_da_addr<LDS>(gb, B) + (uint32_t)r0 + mf_da_addr<LDS>(gb, A) - xo;
-        uint32_t xb = xo + F - xa;
+        uint32_t xb = mf_da_addr<LDS>(gb, B) + (uint32_t)(r0 - ia);
         for (; xo < xo_end; xo += 4) {
             uint32_t a01, a23, r32, r10;
             mf_da_get4_u8<LDS>(gb, xa, a01, a23);
@@ -345,20 +349,20 @@ __device__ __forceinline__ void mf_da_merge(E* __restrict__ gl, const uint4 d)
             mf_da_put<LDS>(gb, xo, __builtin_amdgcn_perm(mx, mn, 0x06020400u));
             xa = __builtin_amdgcn_sad_u16(g, 0x00020002u, xa);
             if constexpr (CLAMP) xa = min(xa, xend);
-            xb = xo + 4u + F - xa;
+            xb = __builtin_amdgcn_sad_u16(g, 0u, xb);
         }
     } else if constexpr (sizeof(E) == 2) {
         // the step on pairs, as for 8-bit elements: (a0,a1) meets (b3,b2) and
         // (a2,a3) meets (b1,b0); heads and output as LDS byte addresses, two
         // bytes per element, so the flags are doubled before v_sad_u16 adds
-        // twice the number of A elements taken to the A head
+        // twice the number of A elements taken to the A head (and twice the
+        // B elements taken to the B head)
         unsigned char* gb = reinterpret_cast<unsigned char*>(gl);
         uint32_t xa = mf_da_addr<LDS>(gb, A) + 2u * (uint32_t)ia;
         const uint32_t xend = mf_da_addr<LDS>(gb, A) + 2u * (uint32_t)na;
         uint32_t xo = mf_da_addr<LDS>(gb, gl + oo);
         const uint32_t xo_end = xo + 2u * (uint32_t)nvalid;
-        const uint32_t F = mf_da_addr<LDS>(gb, B) + 2u * (uint32_t)r0 + mf_da_addr<LDS>(gb, A) - xo;
-        uint32_t xb = xo + F - xa;
+        uint32_t xb = mf_da_addr<LDS>(gb, B) + 2u * (uint32_t)(r0 - ia);
         for (; xo < xo_end; xo += 8) {
             uint32_t a01, a23, b01, b23;
             mf_da_get4_pk<LDS>(gb, xa, a01, a23);
@@ -375,7 +379,7 @@ __device__ __forceinline__ void mf_da_merge(E* __restrict__ gl, const uint4 d)
                                             __builtin_amdgcn_perm(mx, mn, 0x07060302u)});
             xa = __builtin_amdgcn_sad_u16(g2, 0x00040004u, xa);
             if constexpr (CLAMP) xa = min(xa, xend);
-            xb = xo + 8u + F - xa;
+            xb = __builtin_amdgcn_sad_u16(g2, 0u, xb);
         }
     } else {
         // 32-bit elements, heads and output as locations (four bytes per
