@@ -427,8 +427,8 @@ def main():
     if not args.no_cpu:
         import oracle  # CPU baseline only
         nthreads = len(os.sched_getaffinity(0))
-        probe = 64
-        oracle.median_filter_rect(base[0], kw, kh, rows=(0, 16), nthreads=nthreads)   # warm-up (threads, caches)
+        probe = 256       # long enough that the rate it gives holds for the whole sample
+        oracle.median_filter_rect(base[0], kw, kh, rows=(0, 32), nthreads=nthreads)   # warm-up (threads, caches)
         t = time.perf_counter()
         oracle.median_filter_rect(base[0], kw, kh, rows=(0, probe), nthreads=nthreads)
         dt = time.perf_counter() - t
