@@ -284,8 +284,9 @@ __device__ __forceinline__ void mf_da_get4_pk(const unsigned char* gb, uint32_t 
 // land in the list's sentinel slots, which the lane of the merge's last chunk
 // rewrites afterwards. Chunk outputs start at multiples of four elements, so
 // every step writes one aligned run of four. CLAMP keeps the A index at the
-// window end: needed when data can equal the sentinel value (16-bit and
-// 32-bit data), not for 8-bit data held in 16-bit elements.
+// window end: needed when data can equal the sentinel value (8-bit data in
+// 8-bit elements, 16-bit and 32-bit data), not for 8-bit data held in 16-bit
+// elements (the global-memory form).
 template <class E, bool CLAMP, bool LDS>
 __device__ __forceinline__ void mf_da_merge(E* __restrict__ gl, const uint4 d)
 {
