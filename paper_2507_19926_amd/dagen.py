@@ -833,10 +833,16 @@ def _execute(S: Schedule, keys: np.ndarray, et, clamp: bool, exact: bool) -> np.
             # merge steps of four outputs: the four smallest of A[ia..ia+3]
             # and B[ib..ib+3] are min(A[ia+i], B[ib+3-i]) (a half-cleaner),
             # i taken from A exactly when A[ia+i] <= B[ib+3-i]; they are
-            # written in order after a bitonic sort of four
+            # written in order after a bitonic sort of four. The 8- and
+            # 16-bit kernels advance the B head by the B elements taken (it
+            # lags where the clamp pulls the A head back), the 32-bit kernel
+            # sets it from the A head
             ia = pos.copy()
+            b_counts = np.dtype(et).itemsize <= 2
+            ib = r0 - ia
             for q0 in range(0, nvalid, 4):
-                ib = r0 + q0 - ia
+                if not b_counts:
+                    ib = r0 + q0 - ia
                 av = [arena[rows, aoff + ia + i] for i in range(4)]
                 bv = [arena[rows, boff + ib + i] for i in range(4)]
                 take = [av[i] <= bv[3 - i] for i in range(4)]
@@ -845,7 +851,9 @@ def _execute(S: Schedule, keys: np.ndarray, et, clamp: bool, exact: bool) -> np.
                     c[x], c[y] = np.minimum(c[x], c[y]), np.maximum(c[x], c[y])
                 for i in range(4):
                     arena[:, ooff + q0 + i] = c[i]
-                ia = ia + sum(t.astype(np.int64) for t in take)
+                nA = sum(t.astype(np.int64) for t in take)
+                ia = ia + nA
+                ib = ib + 4 - nA
                 if clamp:
                     ia = np.minimum(ia, na)
             if last:
